@@ -1,0 +1,397 @@
+"""Seeded synthetic problem instances for the dynamic multi-commodity flow solver.
+
+This module only *builds inputs*: graphs, transition costs, capacities and
+per-commodity source/sink distributions.  It contains none of the solver's
+arithmetic (no kernel K = exp(-C/eps), no scalings, no messages), so both the
+FP64 oracle (through the tests) and the GPU library consume the same arrays.
+
+Problem data follow the multi-commodity problem of Section 3.2 of the paper
+(problem "multicommodity" with cost tensor "cost_multicommodity"), read with
+*states = graph nodes* (transition cost matrix C on graph edges plus waiting
+self-loops, capacity d on node occupancy at the interior times 1..T-1, source
+distribution R^(0,1) at time 0 and sink distribution R^(0,T) at time T).
+Topology is encoded by C = +inf (Section 3, hard constraints through infinite
+costs), i.e. by the CSR sparsity pattern.
+
+Every array is float64 / int32 numpy.  Node orderings are chosen for memory
+locality (Morton order for point clouds, row-major for grids); a relabelling of
+nodes does not change the problem.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.csgraph as csgraph
+import scipy.spatial
+
+__all__ = [
+    "Instance",
+    "grid_instance",
+    "rgg_instance",
+    "dense_blob_instance",
+    "road_grid_instance",
+    "serve_trace",
+    "instance_from_request",
+    "lp_feasible",
+]
+
+
+@dataclasses.dataclass
+class Instance:
+    """One dynamic multi-commodity flow problem.
+
+    n states, L commodities, T time steps (marginals at times 0..T), eps > 0.
+    kind == "csr": transitions are the CSR entries (rowptr, colidx, cost);
+    entry (i, j) with finite cost cost means moving from state i at time tau to
+    state j at time tau+1 is allowed at that cost.
+    kind == "dense": cost_dense (n, n) with +inf for forbidden transitions.
+    cap: (n,) applied at every interior time 1..T-1, or (T-1, n); +inf means
+    uncapacitated.  src / dst: (L, n) nonnegative, equal row sums (the
+    commodity masses).  state_cost: optional (L, n) per-commodity state cost
+    charged at interior times (None means zero).
+    """
+
+    name: str
+    n: int
+    L: int
+    T: int
+    eps: float
+    kind: str
+    src: np.ndarray
+    dst: np.ndarray
+    cap: np.ndarray
+    rowptr: Optional[np.ndarray] = None
+    colidx: Optional[np.ndarray] = None
+    cost: Optional[np.ndarray] = None
+    cost_dense: Optional[np.ndarray] = None
+    state_cost: Optional[np.ndarray] = None
+    meta: dict = dataclasses.field(default_factory=dict)
+
+    @property
+    def nnz(self) -> int:
+        if self.kind == "csr":
+            return int(self.rowptr[-1])
+        return int(np.isfinite(self.cost_dense).sum())
+
+    def cap_full(self) -> np.ndarray:
+        """Capacities as a (T-1, n) array (one row per interior time)."""
+        if self.cap.ndim == 1:
+            return np.broadcast_to(self.cap, (max(self.T - 1, 0), self.n)).copy()
+        return self.cap.copy()
+
+    def cost_csr(self) -> sp.csr_matrix:
+        """The transition cost matrix as scipy CSR (finite entries only)."""
+        if self.kind == "csr":
+            return sp.csr_matrix((self.cost, self.colidx, self.rowptr), shape=(self.n, self.n))
+        r, c = np.nonzero(np.isfinite(self.cost_dense))
+        return sp.csr_matrix((self.cost_dense[r, c], (r, c)), shape=(self.n, self.n))
+
+    def masses(self) -> np.ndarray:
+        return self.src.sum(axis=1)
+
+
+# ----------------------------------------------------------------------------
+# helpers
+# ----------------------------------------------------------------------------
+
+def _morton_order(pts: np.ndarray, bits: int = 16) -> np.ndarray:
+    q = np.clip((pts * (1 << bits)).astype(np.int64), 0, (1 << bits) - 1)
+
+    def spread(v):
+        v = v & 0xFFFF
+        v = (v | (v << 8)) & 0x00FF00FF
+        v = (v | (v << 4)) & 0x0F0F0F0F
+        v = (v | (v << 2)) & 0x33333333
+        v = (v | (v << 1)) & 0x55555555
+        return v
+
+    code = spread(q[:, 0]) | (spread(q[:, 1]) << 1)
+    return np.argsort(code, kind="stable")
+
+
+def _csr_from_pairs(n: int, rows: np.ndarray, cols: np.ndarray, vals: np.ndarray):
+    m = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    m.sum_duplicates()
+    m.sort_indices()
+    return (m.indptr.astype(np.int32), m.indices.astype(np.int32), m.data.astype(np.float64))
+
+
+def _hop_dist(rowptr, colidx, n, sources):
+    g = sp.csr_matrix((np.ones(len(colidx)), colidx, rowptr), shape=(n, n))
+    return csgraph.shortest_path(g, directed=True, unweighted=True, indices=sources)
+
+
+def lp_feasible(inst: Instance) -> bool:
+    """Feasibility of the (unregularised) dynamic multi-commodity flow problem.
+
+    Node-edge LP on the time-expanded network (Section 2.2): one flow variable
+    per (commodity, transition time, allowed transition); flow balance at every
+    (commodity, time, state), sources at time 0, sinks at time T, joint
+    occupancy capacity at interior times.  Used only to reject seeds that make
+    tiny instances infeasible.
+    """
+    from scipy.optimize import linprog
+
+    Cc = inst.cost_csr().tocoo()
+    src_e, dst_e = Cc.row, Cc.col
+    E = len(src_e)
+    n, L, T = inst.n, inst.L, inst.T
+    nv = L * T * E
+
+    def var(l, tau, e):
+        return (l * T + tau) * E + e
+
+    rows, cols, vals, rhs = [], [], [], []
+    r = 0
+    e_idx = np.arange(E)
+    for l in range(L):
+        # time 0 outflow = source
+        for i in range(n):
+            es = e_idx[src_e == i]
+            rows += [r] * len(es); cols += [var(l, 0, e) for e in es]; vals += [1.0] * len(es)
+            rhs.append(inst.src[l, i]); r += 1
+        # time T inflow = sink
+        for j in range(n):
+            es = e_idx[dst_e == j]
+            rows += [r] * len(es); cols += [var(l, T - 1, e) for e in es]; vals += [1.0] * len(es)
+            rhs.append(inst.dst[l, j]); r += 1
+        # balance at interior times
+        for tau in range(1, T):
+            for i in range(n):
+                ein = e_idx[dst_e == i]
+                eout = e_idx[src_e == i]
+                rows += [r] * (len(ein) + len(eout))
+                cols += [var(l, tau - 1, e) for e in ein] + [var(l, tau, e) for e in eout]
+                vals += [1.0] * len(ein) + [-1.0] * len(eout)
+                rhs.append(0.0); r += 1
+    A_eq = sp.csr_matrix((vals, (rows, cols)), shape=(r, nv))
+    b_eq = np.array(rhs)
+    capf = inst.cap_full()
+    rows, cols, vals, rhs = [], [], [], []
+    r = 0
+    for tau in range(1, T):
+        for i in range(n):
+            if not np.isfinite(capf[tau - 1, i]):
+                continue
+            ein = e_idx[dst_e == i]
+            for l in range(L):
+                rows += [r] * len(ein); cols += [var(l, tau - 1, e) for e in ein]; vals += [1.0] * len(ein)
+            rhs.append(capf[tau - 1, i]); r += 1
+    A_ub = sp.csr_matrix((vals, (rows, cols)), shape=(r, nv)) if r else None
+    b_ub = np.array(rhs) if r else None
+    res = linprog(np.zeros(nv), A_ub=A_ub, b_ub=b_ub, A_eq=A_eq, b_eq=b_eq,
+                  bounds=(0, None), method="highs")
+    return res.status == 0
+
+
+# ----------------------------------------------------------------------------
+# configuration generators
+# ----------------------------------------------------------------------------
+
+def grid_instance(side: int = 5, T: int = 10, L: int = 3, eps: float = 0.1,
+                  move_cost: float = 1.0, wait_cost: float = 0.1, cap: float = 0.5,
+                  seed: int = 0, check_feasible: bool = True, max_tries: int = 200) -> Instance:
+    """side x side 4-neighbour grid, unit-mass commodities, uniform node capacity.
+
+    Node r*side + c.  Sources and sinks are drawn without replacement; a draw
+    is rejected when the LP says the instance is infeasible.
+    """
+    n = side * side
+    rows, cols, vals = [], [], []
+    for r_ in range(side):
+        for c_ in range(side):
+            i = r_ * side + c_
+            rows.append(i); cols.append(i); vals.append(wait_cost)
+            for dr, dc in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                rr, cc = r_ + dr, c_ + dc
+                if 0 <= rr < side and 0 <= cc < side:
+                    rows.append(i); cols.append(rr * side + cc); vals.append(move_cost)
+    rowptr, colidx, cost = _csr_from_pairs(n, np.array(rows), np.array(cols), np.array(vals))
+    rng = np.random.default_rng(seed)
+    for attempt in range(max_tries):
+        srcs = rng.choice(n, size=L, replace=False)
+        dsts = rng.choice(n, size=L, replace=False)
+        src = np.zeros((L, n)); dst = np.zeros((L, n))
+        src[np.arange(L), srcs] = 1.0
+        dst[np.arange(L), dsts] = 1.0
+        hd = _hop_dist(rowptr, colidx, n, srcs)
+        if np.any(hd[np.arange(L), dsts] > T):
+            continue
+        inst = Instance(name=f"grid{side}x{side}", n=n, L=L, T=T, eps=eps, kind="csr",
+                        src=src, dst=dst, cap=np.full(n, cap), rowptr=rowptr,
+                        colidx=colidx, cost=cost,
+                        meta=dict(seed=seed, attempt=attempt, sources=srcs, sinks=dsts))
+        if not check_feasible or lp_feasible(inst):
+            return inst
+    raise RuntimeError("no feasible grid instance found")
+
+
+def rgg_instance(n: int = 2000, L: int = 256, T: int = 50, eps: float = 0.05, k: int = 7,
+                 wait_cost: float = 0.01, cap_lo: float = 0.2, cap_hi: float = 1.0,
+                 seed: int = 0) -> Instance:
+    """Random geometric graph: symmetrised k-NN over uniform points in the unit square.
+
+    Transition cost = Euclidean edge length, self-loop = wait cost.  Commodity
+    (source, sink) pairs are iid uniform nodes, rejected when the sink is more
+    than T hops away; masses ~ U[0.5, 1.5]; node capacity ~ U[cap_lo, cap_hi]
+    times the mean commodity mass.
+    """
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    pts = pts[_morton_order(pts)]
+    tree = scipy.spatial.cKDTree(pts)
+    _, nb = tree.query(pts, k=k + 1)
+    r0 = np.repeat(np.arange(n), k)
+    c0 = nb[:, 1:].reshape(-1)
+    rows = np.concatenate([r0, c0, np.arange(n)])
+    cols = np.concatenate([c0, r0, np.arange(n)])
+    # symmetrise (duplicates collapse), then attach costs
+    pat = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(n, n))
+    pat.sum_duplicates(); pat.sort_indices()
+    coo = pat.tocoo()
+    d = np.linalg.norm(pts[coo.row] - pts[coo.col], axis=1)
+    d[coo.row == coo.col] = wait_cost
+    rowptr, colidx, cost = _csr_from_pairs(n, coo.row, coo.col, d)
+    srcs = np.empty(L, dtype=np.int64); dsts = np.empty(L, dtype=np.int64)
+    filled = 0
+    while filled < L:
+        s = rng.integers(0, n, size=L - filled)
+        z = rng.integers(0, n, size=L - filled)
+        hd = _hop_dist(rowptr, colidx, n, s)
+        ok = hd[np.arange(len(s)), z] <= T
+        m = int(ok.sum())
+        srcs[filled:filled + m] = s[ok]; dsts[filled:filled + m] = z[ok]
+        filled += m
+    mass = rng.uniform(0.5, 1.5, size=L)
+    src = np.zeros((L, n)); dst = np.zeros((L, n))
+    src[np.arange(L), srcs] = mass
+    dst[np.arange(L), dsts] = mass
+    capv = rng.uniform(cap_lo, cap_hi, size=n) * mass.mean()
+    return Instance(name=f"rgg{n}", n=n, L=L, T=T, eps=eps, kind="csr", src=src, dst=dst,
+                    cap=capv, rowptr=rowptr, colidx=colidx, cost=cost,
+                    meta=dict(seed=seed, points=pts, sources=srcs, sinks=dsts, k=k))
+
+
+def dense_blob_instance(n: int = 4096, L: int = 1024, T: int = 32, eps: float = 0.02,
+                        trunc: float = 0.25, sigma: float = 0.05, cap_factor: float = 2.0,
+                        seed: int = 0) -> Instance:
+    """Complete graph on uniform points, cost = squared distance truncated at `trunc`.
+
+    C_ij = |x_i - x_j|^2 if that is <= trunc else +inf (C_ii = 0).  Source and
+    sink distributions are Gaussian blobs (std `sigma`) around uniform centres,
+    each normalised to unit mass; uniform capacity cap_factor * L / n.
+    """
+    rng = np.random.default_rng(seed)
+    pts = rng.random((n, 2))
+    pts = pts[_morton_order(pts)]
+    d2 = ((pts[:, None, :] - pts[None, :, :]) ** 2).sum(-1)
+    C = np.where(d2 <= trunc, d2, np.inf)
+    np.fill_diagonal(C, 0.0)
+    a = rng.random((L, 2)); b = rng.random((L, 2))
+
+    def blobs(centres):
+        e = np.exp(-((pts[None, :, :] - centres[:, None, :]) ** 2).sum(-1) / (2 * sigma ** 2))
+        return e / e.sum(axis=1, keepdims=True)
+
+    src = blobs(a); dst = blobs(b)
+    capv = np.full(n, cap_factor * L / n)
+    return Instance(name=f"dense{n}", n=n, L=L, T=T, eps=eps, kind="dense", src=src, dst=dst,
+                    cap=capv, cost_dense=C,
+                    meta=dict(seed=seed, points=pts, src_centres=a, dst_centres=b))
+
+
+def road_grid_instance(side: int = 100, L: int = 2000, T: int = 120, eps: float = 0.05,
+                       cost_lo: float = 1.0, cost_hi: float = 3.0, wait_cost: float = 0.1,
+                       zipf_s: float = 1.1, base_cap_factor: float = 4.0,
+                       weak_frac: float = 0.05, weak_factor: float = 0.1,
+                       seed: int = 0) -> Instance:
+    """Traffic-routing grid: side x side 4-neighbour roads with U[cost_lo, cost_hi] costs.
+
+    Undirected edge costs (symmetric C), wait cost on self-loops.  Origins and
+    destinations are Zipf(zipf_s)-weighted over a seeded node permutation; OD
+    pairs further than T in Manhattan distance are redrawn.  Masses are
+    lognormal(0, 0.5).  Origin/destination nodes are uncapacitated; relay nodes
+    get base_cap_factor * mean mass, a seeded weak_frac of them weak_factor
+    times that.
+    """
+    rng = np.random.default_rng(seed)
+    n = side * side
+    rows, cols, vals = [], [], []
+    for r_ in range(side):
+        for c_ in range(side):
+            i = r_ * side + c_
+            if c_ + 1 < side:
+                w = rng.uniform(cost_lo, cost_hi)
+                j = i + 1
+                rows += [i, j]; cols += [j, i]; vals += [w, w]
+            if r_ + 1 < side:
+                w = rng.uniform(cost_lo, cost_hi)
+                j = i + side
+                rows += [i, j]; cols += [j, i]; vals += [w, w]
+    rows += list(range(n)); cols += list(range(n)); vals += [wait_cost] * n
+    rowptr, colidx, cost = _csr_from_pairs(n, np.array(rows), np.array(cols), np.array(vals))
+    perm = rng.permutation(n)
+    w = 1.0 / np.arange(1, n + 1) ** zipf_s
+    p = w / w.sum()
+    o = np.empty(L, dtype=np.int64); z = np.empty(L, dtype=np.int64)
+    filled = 0
+    while filled < L:
+        oo = perm[rng.choice(n, size=L - filled, p=p)]
+        zz = perm[rng.choice(n, size=L - filled, p=p)]
+        man = np.abs(oo // side - zz // side) + np.abs(oo % side - zz % side)
+        ok = man <= T
+        m = int(ok.sum())
+        o[filled:filled + m] = oo[ok]; z[filled:filled + m] = zz[ok]
+        filled += m
+    mass = rng.lognormal(0.0, 0.5, size=L)
+    src = np.zeros((L, n)); dst = np.zeros((L, n))
+    np.add.at(src, (np.arange(L), o), mass)
+    np.add.at(dst, (np.arange(L), z), mass)
+    capv = np.full(n, base_cap_factor * mass.mean())
+    relay = np.setdiff1d(np.arange(n), np.union1d(o, z))
+    weak = rng.choice(relay, size=int(round(weak_frac * len(relay))), replace=False)
+    capv[weak] *= weak_factor
+    capv[np.union1d(o, z)] = np.inf
+    return Instance(name=f"road{side}x{side}", n=n, L=L, T=T, eps=eps, kind="csr",
+                    src=src, dst=dst, cap=capv, rowptr=rowptr, colidx=colidx, cost=cost,
+                    meta=dict(seed=seed, origins=o, destinations=z, weak=weak))
+
+
+# ----------------------------------------------------------------------------
+# serving trace
+# ----------------------------------------------------------------------------
+
+def serve_trace(num: int = 10000, rate: float = 100.0, seed: int = 0,
+                n_range=(200, 10000), T_range=(10, 120), L_range=(1, 512),
+                eps_choices=(0.02, 0.05, 0.1)) -> list:
+    """Poisson-arriving solve requests (specs only; build with instance_from_request).
+
+    Each request draws a generator (random geometric graph or road grid) with
+    probability 1/2, n log-uniform in n_range, T uniform in T_range, L
+    log-uniform in L_range and eps uniformly from eps_choices.  Arrival times
+    are a Poisson process of the given rate (requests per second).
+    """
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=num)
+    t = np.cumsum(gaps)
+    reqs = []
+    for r in range(num):
+        gen = "rgg" if rng.random() < 0.5 else "grid"
+        n = int(round(math.exp(rng.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        T = int(rng.integers(T_range[0], T_range[1] + 1))
+        L = max(1, int(round(math.exp(rng.uniform(math.log(L_range[0]), math.log(L_range[1]))))))
+        eps = float(rng.choice(eps_choices))
+        reqs.append(dict(id=r, gen=gen, n=n, T=T, L=L, eps=eps, seed=int(rng.integers(1 << 31)),
+                         arrival=float(t[r])))
+    return reqs
+
+
+def instance_from_request(req: dict) -> Instance:
+    if req["gen"] == "rgg":
+        return rgg_instance(n=req["n"], L=req["L"], T=req["T"], eps=req["eps"], seed=req["seed"])
+    side = max(2, int(round(math.sqrt(req["n"]))))
+    return road_grid_instance(side=side, L=req["L"], T=req["T"], eps=req["eps"], seed=req["seed"])

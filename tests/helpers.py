@@ -1,0 +1,50 @@
+"""Shared test helpers: random tiny instances and Instance -> oracle.Problem conversion."""
+import numpy as np
+import scipy.sparse as sp
+
+from oracle import alg2
+from paper_2106_14485_amd.instances import Instance
+
+
+def to_oracle(inst: Instance) -> alg2.Problem:
+    C = inst.cost_csr() if inst.kind == "csr" else inst.cost_dense
+    return alg2.make_problem(C, inst.eps, inst.T, inst.src, inst.dst, inst.cap, inst.state_cost)
+
+
+def random_tiny(n=4, T=4, L=2, seed=0, density=0.6, state_cost=True, cap_scale=0.6,
+                point=False, kind="csr", eps=0.5):
+    """A tiny random instance with self-loops (every state can wait)."""
+    rng = np.random.default_rng(seed)
+    pat = rng.random((n, n)) < density
+    np.fill_diagonal(pat, True)
+    ring = np.arange(n)
+    pat[ring, (ring + 1) % n] = True         # a two-way ring keeps every state reachable
+    pat[(ring + 1) % n, ring] = True
+    if T < 2:
+        pat[:] = True
+    C = np.where(pat, rng.uniform(0.0, 1.0, (n, n)), np.inf)
+    if point:
+        src = np.zeros((L, n)); dst = np.zeros((L, n))
+        m = rng.uniform(0.5, 1.5, L)
+        src[np.arange(L), rng.integers(0, n, L)] = m
+        dst[np.arange(L), rng.integers(0, n, L)] = m
+    else:
+        src = rng.uniform(0.1, 1.0, (L, n)) * (rng.random((L, n)) < 0.7)
+        src[:, 0] += 0.5
+        dst = rng.uniform(0.1, 1.0, (L, n)) * (rng.random((L, n)) < 0.7)
+        dst[:, -1] += 0.5
+        dst *= (src.sum(1) / dst.sum(1))[:, None]
+    cap = rng.uniform(cap_scale, 1.5 * cap_scale, (max(T - 1, 0), n)) * src.sum() / n * 2
+    sc = rng.uniform(0.0, 0.5, (L, n)) if state_cost else None
+    if kind == "csr":
+        r, c = np.nonzero(pat)
+        Cm = sp.csr_matrix((C[r, c], (r, c)), shape=(n, n))
+    else:
+        Cm = C
+    return alg2.make_problem(Cm, eps, T, src, dst, cap, sc), C
+
+
+def rel_l1(a, b):
+    a = np.asarray(a, dtype=np.float64); b = np.asarray(b, dtype=np.float64)
+    den = np.abs(b).sum()
+    return float(np.abs(a - b).sum() / (den if den > 0 else 1.0))
