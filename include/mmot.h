@@ -1,0 +1,189 @@
+/*
+ * mmot.h -- C ABI of the MI355X graph-structured multi-marginal Sinkhorn solver
+ * for dynamic multi-commodity min-cost network flow.
+ *
+ * Method: Haasler, Ringh, Chen, Karlsson, "Scalable computation of dynamic flow
+ * problems via multi-marginal graph-structured optimal transport".  The solver
+ * runs Algorithm 2 (Section 4.3): entropy-regularised problem
+ * "multicommodity_reg", whose optimum is M = K (.) U (Theorem 3/4) with
+ * K = exp(-C/eps) and scalings U^(0,1), u_t, U^(0,TT) (eq. U_multicommodity),
+ * computed by the Sinkhorn updates of eq. sinkhorn_multicommodity using the
+ * message recursions of Theorem 5 and the marginals of Corollary 1.
+ *
+ * Conventions used throughout this header
+ *   n   number of states (graph nodes); L commodities; T transitions, so the
+ *       marginals sit at times 0..T (the paper's TT = T + 1 time marginals).
+ *   Source distribution R^(0,1) at time 0, sink distribution R^(0,TT) at
+ *   time T, capacity d on the summed occupancy at the interior times 1..T-1.
+ *   All array arguments are DEVICE pointers owned by the caller unless the
+ *   parameter name ends in _host.  Matrices in the paper's L x n orientation
+ *   are row-major with the commodity index slowest ("l * n + i").
+ *   The library never allocates device memory: every buffer it keeps lives in
+ *   the caller-provided workspace (size from mmot_query_workspace).  All work
+ *   is enqueued on the stream given to mmot_create (a hipStream_t passed as
+ *   void*, NULL = default stream); calls that return host data synchronise it.
+ *   Calls on one solver are not thread-safe; distinct solvers are independent.
+ * Errors: every call returns mmot_status; MMOT_OK on success.  On error no
+ *   output is written and the solver (if any) stays usable unless stated.
+ */
+#ifndef MMOT_H
+#define MMOT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mmot_status {
+  MMOT_OK = 0,
+  MMOT_EINVAL = 1,        /* bad sizes, eps, NaN/negative data, unsorted CSR, unequal masses */
+  MMOT_ENOMEM = 2,        /* workspace smaller than mmot_query_workspace reported */
+  MMOT_EINFEASIBLE = 3,   /* a positive source/sink entry faces a zero message (Theorem 4 support) */
+  MMOT_ENUMERIC = 4,      /* non-finite values appeared (range exceeded in the scaled domain) */
+  MMOT_EHIP = 5,          /* a HIP runtime call failed */
+  MMOT_EAGAIN = 6,        /* pool: request does not fit the HBM budget right now */
+  MMOT_EUNSUPPORTED = 7   /* option combination not implemented */
+} mmot_status;
+
+enum { MMOT_CSR = 0, MMOT_DENSE = 1 };
+/* arithmetic of the K-products (messages); FP64 reductions are used for stats either way */
+enum { MMOT_FP32 = 0, MMOT_FP64 = 1, MMOT_BF16 = 2 /* dense only: BF16 MFMA + FP32 polish */ };
+/* range control: SCALED keeps per-commodity FP64 log offsets on linear panels,
+   LOG keeps log2-values (log-sum-exp products); AUTO picks from a range estimate */
+enum { MMOT_DOMAIN_AUTO = 0, MMOT_DOMAIN_SCALED = 1, MMOT_DOMAIN_LOG = 2 };
+
+/* Problem data (eq. multicommodity / multicommodity_reg).  kind == MMOT_CSR:
+ * the allowed moves i -> j (time tau to tau+1) are the CSR entries of C
+ * (rowptr[n+1], colidx[nnz] sorted ascending within each row, cost[nnz]);
+ * waiting is a diagonal entry.  kind == MMOT_DENSE: cost_dense[n*n],
+ * row-major, +INF marks a forbidden move.  Negative finite costs are allowed.
+ * state_cost: per-commodity state cost C_L (L x n) charged at interior times,
+ * or NULL (K_L = 1).  cap: n values (cap_per_step = 0, same at every interior
+ * time) or (T-1) x n (cap_per_step = 1); +INF = uncapacitated; must be > 0.
+ * src = R^(0,1), dst = R^(0,TT): L x n, >= 0, each commodity's row sums equal
+ * (relative 1e-9). */
+typedef struct mmot_problem {
+  int32_t n, L, T;
+  double eps;
+  int32_t kind;
+  int32_t cap_per_step;
+  int64_t nnz;
+  const int32_t* rowptr;
+  const int32_t* colidx;
+  const double* cost;
+  const double* cost_dense;
+  const double* state_cost;
+  const double* cap;
+  const double* src;
+  const double* dst;
+} mmot_problem;
+
+typedef struct mmot_options {
+  int32_t precision;     /* MMOT_FP32 (default), MMOT_FP64, MMOT_BF16 */
+  int32_t domain;        /* MMOT_DOMAIN_AUTO (default) / SCALED / LOG */
+  int32_t check_every;   /* mmot_solve: iterations between convergence checks (default 10) */
+  int32_t calib_every;   /* re-centre the range offsets every this many iterations (default 10; the first 3 always) */
+  int32_t polish_iters;  /* BF16: FP32 iterations appended by mmot_solve (default 20) */
+  int32_t use_graph;     /* capture one iteration in a HIP graph (default 1) */
+  double tol;            /* mmot_solve: stop when src_resid <= tol and cap_viol <= tol (default 1e-6) */
+} mmot_options;
+
+/* Convergence / dual statistics of the current iterate (FP64 reductions).
+ * dual_obj: dual objective of Theorem 3 at the current scalings,
+ *   eps*(<log U01,R01> + <log U0T,R0T> + sum_t <log u_t,d_t>) - eps*<K,U>.
+ * src_resid: sum|P_{0,1} - R01| / sum R01; cap_viol: max_t,i (P_t - d)_+ / d;
+ * mass_drift: max over times of |mass(t) - mass(T)| / mass(T) (Corollary 1
+ * makes it zero in exact arithmetic); dual_gap: eps*(<log U,P - R> terms). */
+typedef struct mmot_stats {
+  int32_t iters;
+  int32_t converged;
+  int32_t domain;        /* domain actually used */
+  int32_t precision;     /* precision actually used */
+  double dual_obj;
+  double src_resid;
+  double cap_viol;
+  double mass_drift;
+  double dual_gap;
+  double mass;
+} mmot_stats;
+
+typedef struct mmot_solver mmot_solver;
+
+/* Fill *opt with the defaults listed above. */
+void mmot_default_options(mmot_options* opt);
+
+/* Bytes of device workspace mmot_create needs for this problem and options.
+ * Only sizes/kind/precision are read (no device data is touched).
+ * EINVAL on bad sizes; EUNSUPPORTED on an unsupported combination. */
+mmot_status mmot_query_workspace(const mmot_problem* prob, const mmot_options* opt, size_t* bytes_host);
+
+/* Build a solver: validates the problem on the device, forms K (CSR of K and
+ * of K^T, or dense K/K^T), converts R01/R0T/C_L/d to the internal state-major
+ * layout and sets the initial scalings (u = 1, U0T = 1 on supp R0T).
+ * ws: device buffer of ws_bytes >= the queried size, 256-byte aligned, owned by
+ * the caller and kept alive until mmot_destroy.  The problem arrays may be
+ * freed after this call returns.  Synchronises the stream.
+ * *out receives a host-side handle.  EINVAL / ENOMEM / EHIP on failure. */
+mmot_status mmot_create(const mmot_problem* prob, const mmot_options* opt, void* ws, size_t ws_bytes,
+                        void* stream, mmot_solver** out);
+
+/* Enqueue n_iter Sinkhorn iterations (Algorithm 2 loop body: backward sweep,
+ * source update, forward sweep with capacity updates, sink update).
+ * Asynchronous unless stats_host != NULL: then a check pass computes the
+ * statistics of the resulting iterate and the call synchronises.
+ * Returns EINFEASIBLE / ENUMERIC if the device flagged such a condition
+ * (checked only when stats_host != NULL). */
+mmot_status mmot_iterate(mmot_solver* s, int32_t n_iter, mmot_stats* stats_host);
+
+/* Iterate with a convergence check every opt.check_every iterations until
+ * converged or max_iter iterations; BF16 solvers then run polish_iters FP32
+ * iterations.  Synchronous; fills *stats_host (nullable). */
+mmot_status mmot_solve(mmot_solver* s, int32_t max_iter, mmot_stats* stats_host);
+
+/* Statistics of the current iterate (one update-free pass).  Synchronous. */
+mmot_status mmot_stats_now(mmot_solver* s, mmot_stats* stats_host);
+
+/* Projections of the current plan M = K (.) U (Theorem 5, Corollary 1):
+ * occ[(T+1) * n] = occupancy P_t (row t = time t), always written;
+ * per_comm[(T+1) * L * n] = P_{0,t} (index (t*L + l)*n + i), optional (NULL).
+ * Asynchronous (device outputs). */
+mmot_status mmot_occupancy(mmot_solver* s, double* occ, double* per_comm);
+
+/* Aggregate edge flows (bi-marginal projections P_{t,t+1} summed over
+ * commodities, eq. proj_discrete_bi): flow[t * nnz + e] = mass moving along
+ * CSR entry e between times t and t+1, t = 0..T-1 (CSR problems only).
+ * cost_host (nullable): transport cost <C, M> (synchronises).  */
+mmot_status mmot_edge_flows(mmot_solver* s, double* flow, double* cost_host);
+
+/* Natural-log dual scalings of the current iterate: log_src, log_dst (L x n,
+ * -INF off the support), log_cap ((T-1) x n, <= 0).  Asynchronous. */
+mmot_status mmot_get_log_duals(mmot_solver* s, double* log_src, double* log_dst, double* log_cap);
+
+/* Warm start / resume: replace the scalings (same layout as above). Only
+ * log_dst and log_cap matter for the next iteration (log_src is recomputed by
+ * its first source update).  Asynchronous. */
+mmot_status mmot_set_log_duals(mmot_solver* s, const double* log_src, const double* log_dst,
+                               const double* log_cap);
+
+/* Release host-side resources (the workspace stays the caller's). */
+void mmot_destroy(mmot_solver* s);
+
+const char* mmot_status_str(mmot_status st);
+
+/* Iterations completed so far. */
+int64_t mmot_iterations(const mmot_solver* s);
+
+/* Profiling helper: average device time (ms, HIP events on the solver's
+ * stream) of `reps` back-to-back launches of one sweep step at the middle
+ * time, forward != 0: the forward product with its capacity-update epilogue
+ * (the u it computes goes to scratch), else the backward product.  Message
+ * panels are left needing a fresh backward sweep (done automatically by the
+ * next call that needs them).  Synchronous. */
+mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double* avg_ms_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMOT_H */

@@ -1,0 +1,698 @@
+// C ABI of the solver: workspace layout, setup, iteration scheduling (HIP
+// graphs), convergence checks and outputs.  Host code only; kernels live in
+// setup.hip and sweep_sparse.hip.
+#include "mmot_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+
+namespace mmot {
+// setup.hip
+void launch_validate_vals(const double*, size_t, int, int, int, int*, hipStream_t);
+void launch_validate_csr(const int*, const int*, int, long long, int*, hipStream_t);
+void launch_validate_mass(const double*, const double*, int, int, int*, double*, hipStream_t);
+template <typename V, bool LOG> void launch_gibbs(const double*, size_t, double, V*, hipStream_t);
+void launch_transpose_pattern(const int*, const int*, int, long long, int*, int*, int*, int*, int*, hipStream_t);
+template <typename V> void launch_gather_vals(const V*, const int*, long long, V*, hipStream_t);
+template <typename V, bool LOG> void launch_rowsum_max(const int*, const V*, int, double, uint32_t*, hipStream_t);
+template <typename V> void launch_to_panel(const double*, int, int, int, int, double, V, V*, hipStream_t);
+template <typename V, bool LOG> void launch_cap(const double*, int, int, int, V*, hipStream_t);
+template <typename V> void launch_fill(V*, size_t, V, hipStream_t);
+template <typename V, bool LOG> void launch_init_u0t(const V*, size_t, V*, hipStream_t);
+void launch_init_offsets(double*, double*, double*, double*, int, int, const uint32_t*, hipStream_t);
+template <typename V, bool LOG>
+void launch_log_duals(const V*, const double*, const V*, const double*, const V*, int, int, int, int, double*,
+                      double*, double*, hipStream_t);
+template <typename V, bool LOG>
+void launch_set_duals(const double*, const double*, const double*, int, int, int, int, V*, V*, V*, double*, double*,
+                      hipStream_t);
+void launch_excess(const int*, const int*, const double*, int, double*, int*, double*, hipStream_t);
+// sweep_sparse.hip
+template <typename V, bool LOG> void launch_step(const StepArgs<V>&, int, int, hipStream_t);
+template <typename V, bool LOG>
+void launch_source(int, int, int, int, const V*, const V*, const V*, V*, uint32_t*, int, size_t, int*, int,
+                   hipStream_t);
+template <typename V, bool LOG>
+void launch_check0(int, int, int, int, int, const V*, const V*, const V*, const double*, const double*, double*,
+                   double*, double*, int, hipStream_t);
+template <typename V, bool LOG>
+void launch_flows(int, int, int, int, int, const int*, const int*, const V*, const double*, const V*, const V*,
+                  const V*, const V*, const double*, const double*, double*, double*, int, hipStream_t);
+template <typename V, bool LOG>
+void launch_prep_bwd(int, int, const double*, double*, V*, const double*, hipStream_t);
+template <typename V, bool LOG>
+void launch_prep_fwd(int, int, int, const double*, const double*, double*, const double*, V*, V*, double*, double*,
+                     hipStream_t);
+void launch_consume(uint32_t*, double*, int, int, int, hipStream_t);
+void launch_reduce_stats(const double*, int, int, double*, double, double*, hipStream_t);
+void launch_reduce_cost(const double*, int, int, double*, double*, hipStream_t);
+}  // namespace mmot
+
+using namespace mmot;
+
+namespace {
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += std::max<size_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct mmot_solver {
+  // problem
+  int n = 0, L = 0, T = 0, kind = 0;
+  long long nnz = 0;
+  double eps = 0;
+  bool has_kl = false;
+  mmot_options opt{};
+  int prec = MMOT_FP32;   // FP32 or FP64 (element type V)
+  int dom = MMOT_DOMAIN_SCALED;
+  hipStream_t stream = nullptr;
+  // geometry
+  int vsize = 4, Lp = 0, G = 64, nchunk = 1, nblk = 8, nslot = 1;
+  // device buffers (carved from the workspace)
+  int *rp_b = nullptr, *ci_b = nullptr, *rp_f = nullptr, *ci_f = nullptr;
+  int *cnt = nullptr, *cursor = nullptr, *srcpos = nullptr;
+  void *kv_b = nullptr, *kv_f = nullptr;
+  double* cost = nullptr;
+  void *KL = nullptr, *cap = nullptr, *R01 = nullptr, *R0T = nullptr, *U01 = nullptr, *U0T = nullptr;
+  void *psi = nullptr, *zh = nullptr, *u = nullptr;
+  double *cb = nullptr, *cf = nullptr, *sigb = nullptr, *sigf = nullptr, *gauge0 = nullptr, *gaugeT = nullptr;
+  void *facb = nullptr, *facf = nullptr, *wgt = nullptr;
+  uint32_t *slots_b = nullptr, *slots_f = nullptr, *rho = nullptr;
+  double *part = nullptr, *tpart = nullptr, *stats_dev = nullptr, *masses = nullptr;
+  double *exc_row = nullptr, *exc = nullptr;
+  int* exc_cnt = nullptr;
+  int* flags = nullptr;
+  // host state
+  int64_t iters = 0;
+  bool psi_fresh = false, pend_b = false, pend_f = false;
+  int force_calib = 0;
+  hipStream_t cap_stream = nullptr;
+  std::map<int, hipGraphExec_t> graphs;
+  double* host_stats = nullptr;   // pinned
+  int* host_flags = nullptr;      // pinned
+
+  size_t panel_elems() const { return (size_t)n * Lp; }
+  template <typename V> V* P(void* p) const { return static_cast<V*>(p); }
+};
+
+namespace {
+
+int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
+
+void set_geometry(mmot_solver* s) {
+  s->vsize = (s->prec == MMOT_FP64) ? 8 : 4;
+  const int vec = 16 / s->vsize;
+  s->Lp = (s->L + vec - 1) / vec * vec;
+  const int lanes = s->Lp / vec;
+  s->G = std::min(64, next_pow2(lanes));
+  s->nchunk = (lanes + s->G - 1) / s->G;
+  const int rows_per_block = kWaves * (64 / s->G);
+  int nblk = (s->n + rows_per_block - 1) / rows_per_block;
+  nblk = (nblk + 7) / 8 * 8;
+  s->nblk = nblk;
+  s->nslot = std::max(1, std::min(32, nblk / 16));
+}
+
+void carve(mmot_solver* s, Carver& c) {
+  const size_t n = s->n, Lp = s->Lp, T = s->T, nnz = (size_t)s->nnz, vs = s->vsize;
+  const size_t Tm1 = T > 1 ? T - 1 : 0;
+  auto takev = [&](size_t cnt) { return static_cast<void*>(c.take<char>(cnt * vs)); };
+  s->rp_b = c.take<int>(n + 1);
+  s->ci_b = c.take<int>(nnz);
+  s->kv_b = takev(nnz);
+  s->cost = c.take<double>(nnz);
+  s->rp_f = c.take<int>(n + 1);
+  s->ci_f = c.take<int>(nnz);
+  s->kv_f = takev(nnz);
+  s->cnt = c.take<int>(n);
+  s->cursor = c.take<int>(n);
+  s->srcpos = c.take<int>(nnz);
+  s->KL = s->has_kl ? takev(n * Lp) : nullptr;
+  s->cap = takev(Tm1 * n);
+  s->R01 = takev(n * Lp);
+  s->R0T = takev(n * Lp);
+  s->U01 = takev(n * Lp);
+  s->U0T = takev(n * Lp);
+  s->psi = takev(T * n * Lp);
+  s->zh = takev(2 * n * Lp);
+  s->u = takev(Tm1 * n);
+  s->cb = c.take<double>((T + 1) * Lp);
+  s->cf = c.take<double>((T + 1) * Lp);
+  s->sigb = c.take<double>((T + 1) * Lp);
+  s->sigf = c.take<double>((T + 1) * Lp);
+  s->gauge0 = c.take<double>(Lp);
+  s->gaugeT = c.take<double>(Lp);
+  s->facb = takev((T + 1) * Lp);
+  s->facf = takev((T + 1) * Lp);
+  s->wgt = takev((T + 1) * Lp);
+  s->slots_b = c.take<uint32_t>((size_t)s->nslot * (T + 1) * Lp);
+  s->slots_f = c.take<uint32_t>((size_t)s->nslot * (T + 1) * Lp);
+  s->rho = c.take<uint32_t>(2);
+  s->part = c.take<double>((T + 1) * (size_t)s->nblk * kNSt);
+  s->tpart = c.take<double>((T + 1) * kNSt);
+  s->stats_dev = c.take<double>(8);
+  s->masses = c.take<double>(s->L);
+  s->exc_row = c.take<double>(n);
+  s->exc_cnt = c.take<int>(n);
+  s->exc = c.take<double>(1);
+  s->flags = c.take<int>(4);
+}
+
+mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
+  if (!p || !o) return MMOT_EINVAL;
+  if (p->n < 1 || p->L < 1 || p->T < 1) return MMOT_EINVAL;
+  if (!(p->eps > 0) || !std::isfinite(p->eps)) return MMOT_EINVAL;
+  if (p->kind != MMOT_CSR && p->kind != MMOT_DENSE) return MMOT_EINVAL;
+  if (p->kind == MMOT_DENSE) return MMOT_EUNSUPPORTED;
+  if (p->nnz < 1 || p->nnz > (1LL << 31) - 1) return MMOT_EINVAL;
+  if (o->precision != MMOT_FP32 && o->precision != MMOT_FP64) return MMOT_EUNSUPPORTED;
+  if (o->domain < MMOT_DOMAIN_AUTO || o->domain > MMOT_DOMAIN_LOG) return MMOT_EINVAL;
+  if ((size_t)p->n * (size_t)p->L > (size_t)1 << 33) return MMOT_EINVAL;
+  return MMOT_OK;
+}
+
+#define HIPCK(x)                                 \
+  do {                                           \
+    if ((x) != hipSuccess) return MMOT_EHIP;     \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// typed implementation
+// ---------------------------------------------------------------------------
+template <typename V, bool LOG>
+struct Impl {
+  static V* pan(mmot_solver* s, void* base, size_t k) { return static_cast<V*>(base) + k * s->panel_elems(); }
+  static V* psi(mmot_solver* s, int t) { return pan(s, s->psi, t); }
+  static V* zh(mmot_solver* s, int k) { return pan(s, s->zh, k & 1); }
+  static V* uat(mmot_solver* s, int tau) {  // u at interior time tau (1..T-1)
+    return (tau >= 1 && tau <= s->T - 1) ? static_cast<V*>(s->u) + (size_t)(tau - 1) * s->n : nullptr;
+  }
+  static StepArgs<V> base_args(mmot_solver* s) {
+    StepArgs<V> a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = s->n; a.Lp = s->Lp; a.L = s->L; a.G = s->G; a.nchunk = s->nchunk;
+    a.nslot = s->nslot;
+    a.nslot_stride = (size_t)(s->T + 1) * s->Lp;
+    a.flags = s->flags;
+    return a;
+  }
+
+  static StepArgs<V> bwd_args(mmot_solver* s, int t, bool calib) {
+    const int T = s->T;
+    StepArgs<V> a = base_args(s);
+    a.rp = s->rp_b; a.ci = s->ci_b; a.kv = static_cast<const V*>(s->kv_b);
+    a.xin = (t + 1 == T) ? static_cast<const V*>(s->U0T) : psi(s, t + 1);
+    a.uin = uat(s, t + 1);
+    a.fac = static_cast<const V*>(s->facb) + (size_t)t * s->Lp;
+    a.out = psi(s, t);
+    a.kl = (s->has_kl && t >= 1) ? static_cast<const V*>(s->KL) : nullptr;
+    a.epi = 0;
+    a.slots = calib ? s->slots_b + (size_t)t * s->Lp : nullptr;
+    return a;
+  }
+
+  static void backward(mmot_solver* s, bool consume, bool calib, hipStream_t st) {
+    const int T = s->T;
+    if (consume) launch_consume(s->slots_b, s->cb, T + 1, s->Lp, s->nslot, st);
+    launch_prep_bwd<V, LOG>(T, s->Lp, s->cb, s->sigb, static_cast<V*>(s->facb), s->gaugeT, st);
+    for (int t = T - 1; t >= 0; --t) launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk, st);
+  }
+
+  // forward product t -> t+1; mode 0 Sinkhorn update, mode 1 update-free pass
+  static StepArgs<V> fwd_args(mmot_solver* s, int t, int mode, bool calib, double* occ, double* pcomm) {
+    const int T = s->T;
+    const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
+    StepArgs<V> a = base_args(s);
+    a.rp = s->rp_f; a.ci = s->ci_f; a.kv = static_cast<const V*>(s->kv_f);
+    a.xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
+    a.uin = uat(s, t);
+    const int to = t + 1;
+    a.fac = static_cast<const V*>(s->facf) + (size_t)to * Lp;
+    a.update = (mode == 0);
+    if (mode == 1) {
+      a.part = s->part + (size_t)to * pstride;
+      a.occ = occ ? occ + (size_t)to * s->n : nullptr;
+      a.pcomm = pcomm ? pcomm + (size_t)to * s->L * s->n : nullptr;
+    }
+    if (to < T) {
+      a.epi = 1;
+      a.out = zh(s, to);
+      a.kl = s->has_kl ? static_cast<const V*>(s->KL) : nullptr;
+      a.wpan = psi(s, to);
+      a.wgt = static_cast<const V*>(s->wgt) + (size_t)to * Lp;
+      a.cap = static_cast<const V*>(s->cap) + (size_t)(to - 1) * s->n;
+      a.uout = static_cast<V*>(s->u) + (size_t)(to - 1) * s->n;
+      a.slots = (mode == 0 && calib) ? s->slots_f + (size_t)to * Lp : nullptr;
+    } else {
+      a.epi = 2;
+      a.rdst = static_cast<const V*>(s->R0T);
+      a.u0t = static_cast<V*>(s->U0T);
+      a.facT = static_cast<const V*>(s->facb) + (size_t)T * Lp;
+      a.sigT = s->sigb + (size_t)T * Lp;
+      a.sighT = s->sigf + (size_t)T * Lp;
+      a.slots = (mode == 0 && calib) ? s->slots_b + (size_t)T * Lp : nullptr;
+    }
+    return a;
+  }
+
+  // Forward sweep.  mode 0: Sinkhorn sweep (source update, capacity updates,
+  // sink update).  mode 1: update-free pass computing statistics and optional
+  // outputs (occupancy, per-commodity marginals, edge flows).
+  static void forward(mmot_solver* s, int mode, bool consume, bool calib, double* occ, double* pcomm,
+                      hipStream_t st) {
+    const int T = s->T;
+    const size_t Lp = s->Lp;
+    if (mode == 0 && consume) launch_consume(s->slots_f, s->cf, T + 1, s->Lp, s->nslot, st);
+    launch_prep_fwd<V, LOG>(T, s->Lp, mode, s->cf, s->cb, s->sigf, s->sigb, static_cast<V*>(s->facf),
+                            static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, st);
+    const size_t pstride = (size_t)s->nblk * kNSt;
+    if (mode == 0) {
+      launch_source<V, LOG>(s->n, s->Lp, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->R01),
+                            static_cast<const V*>(s->facf), static_cast<V*>(s->U01),
+                            calib ? s->slots_f : nullptr, s->nslot, (size_t)(T + 1) * Lp, s->flags, s->nblk, st);
+    } else {
+      launch_check0<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->U01),
+                            static_cast<const V*>(s->R01), s->sigf, s->sigb, s->part, occ,
+                            pcomm, s->nblk, st);
+    }
+    for (int t = 0; t < T; ++t) launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), 1, s->nblk, st);
+  }
+
+  // time `reps` launches of one sweep step at the middle time, as launched in
+  // the sweep (forward: with the capacity update, its u written to scratch)
+  static mmot_status time_step(mmot_solver* s, int fwd, int reps, double* avg_ms) {
+    const int t = std::max(0, std::min(s->T - 2, s->T / 2));
+    hipEvent_t e0, e1;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    StepArgs<V> a = fwd ? fwd_args(s, t, 0, false, nullptr, nullptr) : bwd_args(s, t, false);
+    if (fwd && a.epi == 1) a.uout = reinterpret_cast<V*>(s->exc_row);
+    HIPCK(hipEventRecord(e0, s->stream));
+    for (int r = 0; r < reps; ++r) launch_step<V, LOG>(a, fwd, s->nblk, s->stream);
+    HIPCK(hipEventRecord(e1, s->stream));
+    HIPCK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *avg_ms = ms / reps;
+    return MMOT_OK;
+  }
+
+  // flows need A_t from the update-free forward recursion: run the products
+  // and interleave the SDDMM at each time
+  static void flows_pass(mmot_solver* s, double* flow, hipStream_t st) {
+    const int T = s->T;
+    const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
+    launch_prep_fwd<V, LOG>(T, s->Lp, 1, s->cf, s->cb, s->sigf, s->sigb, static_cast<V*>(s->facf),
+                            static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, st);
+    for (int t = 0; t < T; ++t) {
+      const V* xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
+      const int tb = t + 1;
+      launch_flows<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, s->rp_b, s->ci_b, static_cast<const V*>(s->kv_b),
+                           s->cost, xin, uat(s, t), (tb == T) ? static_cast<const V*>(s->U0T) : psi(s, tb),
+                           uat(s, tb), s->sigf + (size_t)t * Lp, s->sigb + (size_t)tb * Lp,
+                           flow + (size_t)t * s->nnz, s->part + (size_t)t * pstride, s->nblk, st);
+      if (tb < T) {
+        StepArgs<V> a = base_args(s);
+        a.rp = s->rp_f; a.ci = s->ci_f; a.kv = static_cast<const V*>(s->kv_f);
+        a.xin = xin; a.uin = uat(s, t);
+        a.fac = static_cast<const V*>(s->facf) + (size_t)tb * Lp;
+        a.update = 0;
+        a.epi = 0;
+        a.out = zh(s, tb);
+        a.kl = s->has_kl ? static_cast<const V*>(s->KL) : nullptr;
+        launch_step<V, LOG>(a, 1, s->nblk, st);
+      }
+    }
+    launch_reduce_cost(s->part, s->nblk, T, s->tpart, s->stats_dev + 7, st);
+  }
+
+  static mmot_status setup(mmot_solver* s, const mmot_problem* p) {
+    hipStream_t st = s->stream;
+    const size_t n = s->n, L = s->L, Lp = s->Lp, T = s->T, nnz = (size_t)s->nnz;
+    const size_t Tm1 = T > 1 ? T - 1 : 0;
+    launch_fill<int>(s->flags, 4, 0, st);
+    launch_validate_vals(p->src, n * L, 0, 0, 0, s->flags, st);
+    launch_validate_vals(p->dst, n * L, 0, 0, 0, s->flags, st);
+    launch_validate_vals(p->cap, p->cap_per_step ? Tm1 * n : n, 1, 1, 0, s->flags, st);
+    launch_validate_vals(p->cost, nnz, 0, 0, 1, s->flags, st);
+    if (p->state_cost) launch_validate_vals(p->state_cost, n * L, 0, 0, 1, s->flags, st);
+    launch_validate_csr(p->rowptr, p->colidx, s->n, s->nnz, s->flags, st);
+    launch_validate_mass(p->src, p->dst, s->L, s->n, s->flags, s->masses, st);
+    HIPCK(hipMemcpyAsync(s->host_flags, s->flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    if (*s->host_flags) return MMOT_EINVAL;
+    // operators: backward = rows of K (input order), forward = rows of K^T
+    HIPCK(hipMemcpyAsync(s->rp_b, p->rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, st));
+    HIPCK(hipMemcpyAsync(s->ci_b, p->colidx, nnz * sizeof(int), hipMemcpyDeviceToDevice, st));
+    HIPCK(hipMemcpyAsync(s->cost, p->cost, nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_gibbs<V, LOG>(s->cost, nnz, s->eps, static_cast<V*>(s->kv_b), st);
+    launch_transpose_pattern(s->rp_b, s->ci_b, s->n, s->nnz, s->cnt, s->rp_f, s->cursor, s->ci_f, s->srcpos, st);
+    launch_gather_vals<V>(static_cast<const V*>(s->kv_b), s->srcpos, s->nnz, static_cast<V*>(s->kv_f), st);
+    launch_fill<uint32_t>(s->rho, 2, 0u, st);
+    launch_rowsum_max<V, LOG>(s->rp_b, static_cast<const V*>(s->kv_b), s->n, 0.0, s->rho, st);
+    launch_rowsum_max<V, LOG>(s->rp_f, static_cast<const V*>(s->kv_f), s->n, 0.0, s->rho + 1, st);
+    // panels
+    const V zero = LOG ? -static_cast<V>(INFINITY) : V(0);
+    const int vmode = LOG ? 1 : 0;
+    launch_to_panel<V>(p->src, s->L, s->n, s->Lp, vmode, s->eps, zero, static_cast<V*>(s->R01), st);
+    launch_to_panel<V>(p->dst, s->L, s->n, s->Lp, vmode, s->eps, zero, static_cast<V*>(s->R0T), st);
+    if (s->has_kl)
+      launch_to_panel<V>(p->state_cost, s->L, s->n, s->Lp, LOG ? 3 : 2, s->eps, LOG ? V(0) : V(1),
+                         static_cast<V*>(s->KL), st);
+    launch_cap<V, LOG>(p->cap, p->cap_per_step, s->n, (int)Tm1, static_cast<V*>(s->cap), st);
+    // initial scalings: u = 1, U0T = 1 on supp(R0T)
+    launch_fill<V>(static_cast<V*>(s->u), Tm1 * n, LOG ? V(0) : V(1), st);
+    launch_init_u0t<V, LOG>(static_cast<const V*>(s->R0T), n * Lp, static_cast<V*>(s->U0T), st);
+    launch_fill<V>(static_cast<V*>(s->U01), n * Lp, zero, st);
+    launch_fill<V>(static_cast<V*>(s->psi), T * n * Lp, zero, st);
+    launch_fill<V>(static_cast<V*>(s->zh), 2 * n * Lp, zero, st);
+    launch_fill<uint32_t>(s->slots_b, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
+    launch_fill<uint32_t>(s->slots_f, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
+    launch_init_offsets(s->cb, s->cf, s->gauge0, s->gaugeT, s->T, s->Lp, s->rho, st);
+    HIPCK(hipGetLastError());
+    HIPCK(hipStreamSynchronize(st));
+    return MMOT_OK;
+  }
+
+  static void iteration(mmot_solver* s, bool runB, bool consume_b, bool calib, bool consume_f, hipStream_t st) {
+    if (runB) backward(s, consume_b, calib, st);
+    forward(s, 0, consume_f, calib, nullptr, nullptr, st);
+  }
+};
+
+template <typename F>
+auto dispatch(mmot_solver* s, F&& f) {
+  if (s->prec == MMOT_FP64) {
+    if (s->dom == MMOT_DOMAIN_LOG) return f(Impl<double, true>());
+    return f(Impl<double, false>());
+  }
+  if (s->dom == MMOT_DOMAIN_LOG) return f(Impl<float, true>());
+  return f(Impl<float, false>());
+}
+
+mmot_status read_flags(mmot_solver* s) {
+  HIPCK(hipMemcpyAsync(s->host_flags, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream));
+  HIPCK(hipStreamSynchronize(s->stream));
+  const int f = *s->host_flags;
+  if (f & FLAG_INFEASIBLE) return MMOT_EINFEASIBLE;
+  if (f & FLAG_NONFINITE) return MMOT_ENUMERIC;
+  return MMOT_OK;
+}
+
+mmot_status run_iterations(mmot_solver* s, int n_iter) {
+  for (int k = 0; k < n_iter; ++k) {
+    const bool calib = s->iters < 3 || s->force_calib > 0 ||
+                       (s->opt.calib_every > 0 && s->iters % s->opt.calib_every == 0);
+    const bool runB = !s->psi_fresh;
+    const bool cb = runB && s->pend_b, cf = s->pend_f;
+    const int key = (runB ? 1 : 0) | (cb ? 2 : 0) | (calib ? 4 : 0) | (cf ? 8 : 0);
+    if (s->opt.use_graph) {
+      auto it = s->graphs.find(key);
+      if (it == s->graphs.end()) {
+        hipGraph_t g;
+        HIPCK(hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed));
+        dispatch(s, [&](auto impl) { decltype(impl)::iteration(s, runB, cb, calib, cf, s->cap_stream); return 0; });
+        HIPCK(hipStreamEndCapture(s->cap_stream, &g));
+        hipGraphExec_t ge;
+        if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) { (void)hipGraphDestroy(g); return MMOT_EHIP; }
+        (void)hipGraphDestroy(g);
+        it = s->graphs.emplace(key, ge).first;
+      }
+      HIPCK(hipGraphLaunch(it->second, s->stream));
+    } else {
+      dispatch(s, [&](auto impl) { decltype(impl)::iteration(s, runB, cb, calib, cf, s->stream); return 0; });
+      HIPCK(hipGetLastError());
+    }
+    // calibration sweeps leave column maxima to consume at the next prep of the
+    // same direction (the sink update records those of the U0T panel)
+    s->pend_b = calib ? true : (cb ? false : s->pend_b);
+    s->pend_f = calib;
+    s->psi_fresh = false;
+    if (s->force_calib > 0) --s->force_calib;
+    ++s->iters;
+  }
+  return MMOT_OK;
+}
+
+// fresh backward messages for the current scalings (no range update)
+void ensure_fresh(mmot_solver* s) {
+  if (s->psi_fresh) return;
+  const bool cb = s->pend_b;
+  dispatch(s, [&](auto impl) { decltype(impl)::backward(s, cb, false, s->stream); return 0; });
+  s->pend_b = false;
+  s->psi_fresh = true;
+}
+
+mmot_status collect_stats(mmot_solver* s, mmot_stats* out) {
+  launch_reduce_stats(s->part, s->nblk, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
+  HIPCK(hipMemcpyAsync(s->host_stats, s->stats_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+  mmot_status fs = read_flags(s);
+  if (out) {
+    out->iters = (int32_t)s->iters;
+    out->domain = s->dom;
+    out->precision = s->prec;
+    out->dual_obj = s->host_stats[0];
+    out->src_resid = s->host_stats[1];
+    out->cap_viol = s->host_stats[2];
+    out->mass_drift = s->host_stats[3];
+    out->dual_gap = s->host_stats[4];
+    out->mass = s->host_stats[5];
+    out->converged = (out->src_resid <= s->opt.tol && out->cap_viol <= s->opt.tol) ? 1 : 0;
+  }
+  if (fs != MMOT_OK) return fs;
+  if (s->host_stats[6] > 0 || !std::isfinite(s->host_stats[0])) return MMOT_ENUMERIC;
+  return MMOT_OK;
+}
+
+mmot_status check_pass(mmot_solver* s, double* occ, double* pcomm, mmot_stats* out) {
+  ensure_fresh(s);
+  dispatch(s, [&](auto impl) { decltype(impl)::forward(s, 1, false, false, occ, pcomm, s->stream); return 0; });
+  if (hipGetLastError() != hipSuccess) return MMOT_EHIP;
+  if (!out && !pcomm && !occ) return MMOT_OK;
+  if (out) return collect_stats(s, out);
+  return MMOT_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void mmot_default_options(mmot_options* o) {
+  if (!o) return;
+  o->precision = MMOT_FP32;
+  o->domain = MMOT_DOMAIN_AUTO;
+  o->check_every = 10;
+  o->calib_every = 10;
+  o->polish_iters = 20;
+  o->use_graph = 1;
+  o->tol = 1e-6;
+}
+
+mmot_status mmot_query_workspace(const mmot_problem* p, const mmot_options* o, size_t* bytes) {
+  if (!bytes) return MMOT_EINVAL;
+  mmot_status st = basic_checks(p, o);
+  if (st != MMOT_OK) return st;
+  mmot_solver tmp;
+  tmp.n = p->n; tmp.L = p->L; tmp.T = p->T; tmp.nnz = p->nnz; tmp.kind = p->kind;
+  tmp.has_kl = p->state_cost != nullptr;
+  tmp.prec = o->precision;
+  set_geometry(&tmp);
+  Carver c{nullptr};
+  carve(&tmp, c);
+  *bytes = c.off + 256;
+  return MMOT_OK;
+}
+
+mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, size_t ws_bytes, void* stream,
+                        mmot_solver** out) {
+  if (!out) return MMOT_EINVAL;
+  *out = nullptr;
+  mmot_status st = basic_checks(p, o);
+  if (st != MMOT_OK) return st;
+  if (!p->rowptr || !p->colidx || !p->cost || !p->cap || !p->src || !p->dst) return MMOT_EINVAL;
+  size_t need = 0;
+  st = mmot_query_workspace(p, o, &need);
+  if (st != MMOT_OK) return st;
+  if (!ws || ws_bytes < need) return MMOT_ENOMEM;
+  mmot_solver* s = new (std::nothrow) mmot_solver();
+  if (!s) return MMOT_ENOMEM;
+  s->n = p->n; s->L = p->L; s->T = p->T; s->nnz = p->nnz; s->kind = p->kind; s->eps = p->eps;
+  s->has_kl = p->state_cost != nullptr;
+  s->opt = *o;
+  if (s->opt.check_every < 1) s->opt.check_every = 10;
+  if (!(s->opt.tol > 0)) s->opt.tol = 1e-6;
+  s->prec = o->precision;
+  s->stream = static_cast<hipStream_t>(stream);
+  set_geometry(s);
+  uintptr_t b = reinterpret_cast<uintptr_t>(ws);
+  b = (b + 255) & ~uintptr_t(255);
+  Carver c{reinterpret_cast<char*>(b)};
+  carve(s, c);
+  auto fail = [&](mmot_status e) { mmot_destroy(s); return e; };
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->host_stats), 16 * sizeof(double), 0) != hipSuccess) return fail(MMOT_EHIP);
+  if (hipHostMalloc(reinterpret_cast<void**>(&s->host_flags), 4 * sizeof(int), 0) != hipSuccess) return fail(MMOT_EHIP);
+  if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MMOT_EHIP);
+  // domain: an estimate of the within-message dynamic range R = T * mean excess move cost / eps (log2 units)
+  if (o->domain == MMOT_DOMAIN_AUTO) {
+    launch_excess(p->rowptr, p->colidx, p->cost, p->n, s->exc_row, s->exc_cnt, s->exc, s->stream);
+    double h = 0;
+    if (hipMemcpyAsync(&s->host_stats[8], s->exc, sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return fail(MMOT_EHIP);
+    h = s->host_stats[8];
+    const double R = (double)p->T * h / p->eps;       // natural-log range estimate
+    const double limit = (s->prec == MMOT_FP64) ? 600.0 : 60.0;
+    s->dom = (R <= limit) ? MMOT_DOMAIN_SCALED : MMOT_DOMAIN_LOG;
+  } else {
+    s->dom = o->domain;
+  }
+  st = dispatch(s, [&](auto impl) { return decltype(impl)::setup(s, p); });
+  if (st != MMOT_OK) return fail(st);
+  *out = s;
+  return MMOT_OK;
+}
+
+mmot_status mmot_iterate(mmot_solver* s, int32_t n_iter, mmot_stats* stats) {
+  if (!s || n_iter < 0) return MMOT_EINVAL;
+  mmot_status st = run_iterations(s, n_iter);
+  if (st != MMOT_OK) return st;
+  if (stats) return check_pass(s, nullptr, nullptr, stats);
+  return MMOT_OK;
+}
+
+mmot_status mmot_stats_now(mmot_solver* s, mmot_stats* stats) {
+  if (!s || !stats) return MMOT_EINVAL;
+  return check_pass(s, nullptr, nullptr, stats);
+}
+
+mmot_status mmot_solve(mmot_solver* s, int32_t max_iter, mmot_stats* stats) {
+  if (!s || max_iter < 0) return MMOT_EINVAL;
+  mmot_stats local{};
+  int done = 0;
+  mmot_status st = MMOT_OK;
+  while (done < max_iter) {
+    const int k = std::min(s->opt.check_every, max_iter - done);
+    st = mmot_iterate(s, k, &local);
+    done += k;
+    if (st != MMOT_OK) break;
+    if (local.converged) break;
+  }
+  if (done == 0) st = mmot_stats_now(s, &local);
+  if (stats) *stats = local;
+  return st;
+}
+
+mmot_status mmot_occupancy(mmot_solver* s, double* occ, double* per_comm) {
+  if (!s || !occ) return MMOT_EINVAL;
+  return check_pass(s, occ, per_comm, nullptr);
+}
+
+mmot_status mmot_edge_flows(mmot_solver* s, double* flow, double* cost_host) {
+  if (!s || !flow) return MMOT_EINVAL;
+  if (s->kind != MMOT_CSR) return MMOT_EUNSUPPORTED;
+  ensure_fresh(s);
+  dispatch(s, [&](auto impl) { decltype(impl)::flows_pass(s, flow, s->stream); return 0; });
+  if (hipGetLastError() != hipSuccess) return MMOT_EHIP;
+  if (cost_host) {
+    if (hipMemcpyAsync(s->host_stats + 7, s->stats_dev + 7, sizeof(double), hipMemcpyDeviceToHost, s->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return MMOT_EHIP;
+    *cost_host = s->host_stats[7];
+  }
+  return MMOT_OK;
+}
+
+mmot_status mmot_get_log_duals(mmot_solver* s, double* ls, double* ld, double* lc) {
+  if (!s) return MMOT_EINVAL;
+  if (s->prec == MMOT_FP64) {
+    if (s->dom == MMOT_DOMAIN_LOG)
+      launch_log_duals<double, true>(static_cast<double*>(s->U01), s->gauge0, static_cast<double*>(s->U0T), s->gaugeT,
+                                     static_cast<double*>(s->u), s->n, s->L, s->Lp, s->T - 1, ls, ld, lc, s->stream);
+    else
+      launch_log_duals<double, false>(static_cast<double*>(s->U01), s->gauge0, static_cast<double*>(s->U0T), s->gaugeT,
+                                      static_cast<double*>(s->u), s->n, s->L, s->Lp, s->T - 1, ls, ld, lc, s->stream);
+  } else {
+    if (s->dom == MMOT_DOMAIN_LOG)
+      launch_log_duals<float, true>(static_cast<float*>(s->U01), s->gauge0, static_cast<float*>(s->U0T), s->gaugeT,
+                                    static_cast<float*>(s->u), s->n, s->L, s->Lp, s->T - 1, ls, ld, lc, s->stream);
+    else
+      launch_log_duals<float, false>(static_cast<float*>(s->U01), s->gauge0, static_cast<float*>(s->U0T), s->gaugeT,
+                                     static_cast<float*>(s->u), s->n, s->L, s->Lp, s->T - 1, ls, ld, lc, s->stream);
+  }
+  return hipGetLastError() == hipSuccess ? MMOT_OK : MMOT_EHIP;
+}
+
+mmot_status mmot_set_log_duals(mmot_solver* s, const double* ls, const double* ld, const double* lc) {
+  if (!s) return MMOT_EINVAL;
+  if (s->prec == MMOT_FP64) {
+    if (s->dom == MMOT_DOMAIN_LOG)
+      launch_set_duals<double, true>(ls, ld, lc, s->n, s->L, s->Lp, s->T - 1, static_cast<double*>(s->U01),
+                                     static_cast<double*>(s->U0T), static_cast<double*>(s->u), s->gauge0, s->gaugeT, s->stream);
+    else
+      launch_set_duals<double, false>(ls, ld, lc, s->n, s->L, s->Lp, s->T - 1, static_cast<double*>(s->U01),
+                                      static_cast<double*>(s->U0T), static_cast<double*>(s->u), s->gauge0, s->gaugeT, s->stream);
+  } else {
+    if (s->dom == MMOT_DOMAIN_LOG)
+      launch_set_duals<float, true>(ls, ld, lc, s->n, s->L, s->Lp, s->T - 1, static_cast<float*>(s->U01),
+                                    static_cast<float*>(s->U0T), static_cast<float*>(s->u), s->gauge0, s->gaugeT, s->stream);
+    else
+      launch_set_duals<float, false>(ls, ld, lc, s->n, s->L, s->Lp, s->T - 1, static_cast<float*>(s->U01),
+                                     static_cast<float*>(s->U0T), static_cast<float*>(s->u), s->gauge0, s->gaugeT, s->stream);
+  }
+  s->psi_fresh = false;
+  s->force_calib = 2;
+  return hipGetLastError() == hipSuccess ? MMOT_OK : MMOT_EHIP;
+}
+
+void mmot_destroy(mmot_solver* s) {
+  if (!s) return;
+  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->host_stats) (void)hipHostFree(s->host_stats);
+  if (s->host_flags) (void)hipHostFree(s->host_flags);
+  delete s;
+}
+
+const char* mmot_status_str(mmot_status st) {
+  switch (st) {
+    case MMOT_OK: return "ok";
+    case MMOT_EINVAL: return "invalid argument or problem data";
+    case MMOT_ENOMEM: return "workspace too small";
+    case MMOT_EINFEASIBLE: return "infeasible: a positive source/sink entry faces a zero message";
+    case MMOT_ENUMERIC: return "non-finite values (range exceeded)";
+    case MMOT_EHIP: return "HIP runtime error";
+    case MMOT_EAGAIN: return "over the HBM budget, retry later";
+    case MMOT_EUNSUPPORTED: return "unsupported option combination";
+  }
+  return "unknown status";
+}
+
+int64_t mmot_iterations(const mmot_solver* s) { return s ? s->iters : -1; }
+
+mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double* avg_ms) {
+  if (!s || reps < 1 || !avg_ms) return MMOT_EINVAL;
+  mmot_status st = dispatch(s, [&](auto impl) { return decltype(impl)::time_step(s, forward ? 1 : 0, reps, avg_ms); });
+  s->psi_fresh = false;   // the timed launches overwrite scratch message buffers
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Internal declarations of the MI355X graph-structured Sinkhorn library.
+//
+// Layout (HBM): every L x n quantity of the paper (messages Psi_t, hatPsi_t,
+// scalings U^(0,1), U^(0,TT), marginals R, state-cost kernel K_L) is stored
+// state-major as a "panel" [n][Lp]: row i holds the Lp >= L commodity values
+// of state i contiguously (Lp padded to 16 bytes), so a sparse product gathers
+// whole contiguous rows and the capacity reduction over commodities is a
+// wavefront reduction inside one row.
+//
+// Range control.  Scaled domain: panel value x represents x * 2^sigma[l] with
+// a per-commodity FP64 offset sigma (one per time and sweep direction).  Log
+// domain: panel value y represents 2^(y + sigma[l]).  Each product step
+// multiplies its output by 2^-c[t][l] (adds -c in the log domain); c is
+// re-centred from per-column maxima recorded on calibration sweeps.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/mmot.h"
+
+namespace mmot {
+
+constexpr int kBlock = 256;            // threads per block (4 wavefronts)
+constexpr int kWaves = kBlock / 64;
+constexpr int kNSt = 8;                // doubles per stats partial
+// stats partial fields
+enum { ST_SRC_ABS = 0, ST_SRC_MASS = 1, ST_CAP_VIOL = 2, ST_DUAL = 3, ST_GAP = 4, ST_MASS = 5, ST_NONFINITE = 6 };
+// device flag bits
+enum { FLAG_INFEASIBLE = 1, FLAG_NONFINITE = 2, FLAG_BADINPUT = 4, FLAG_BADCSR = 8, FLAG_MASS = 16 };
+
+// Arguments of one sparse sweep step: out = (in (.) u_in) * K-operator, scaled
+// per column by fac, followed by an epilogue that depends on the output time.
+template <typename V>
+struct StepArgs {
+  int n, Lp, L, G, nchunk;
+  const int* rp;        // operator CSR (rows = output states)
+  const int* ci;
+  const V* kv;          // K values (scaled) or log2 K (log)
+  const V* xin;         // input panel (already multiplied by K_L at its time)
+  const V* uin;         // u at the input time, nullptr = 1
+  const V* fac;         // [Lp] per-column output factor 2^-c (scaled) or -c (log)
+  V* out;               // output panel (nullptr = do not store)
+  const V* kl;          // [n][Lp] K_L multiplied into the stored output (interior times), nullptr = none
+  // forward epilogue: capacity update at an interior output time
+  int epi;              // 0 plain store, 1 capacity (u-update / check), 2 sink (E update / check)
+  int update;           // 1: Sinkhorn update, 0: update-free (check / output pass)
+  const V* wpan;        // backward stored panel W at the output time
+  const V* wgt;         // [Lp] 2^(sigma_hat + sigma) (scaled) or sigma_hat + sigma (log)
+  const V* cap;         // [n] capacity (log2 in the log domain) at the output time
+  V* uout;              // [n] u at the output time
+  const V* rdst;        // sink: R0T panel (log2 in the log domain)
+  V* u0t;               // sink: U0T panel (written when update)
+  const V* facT;        // sink: [Lp] factor of the U0T panel
+  const double* sigT;   // sink/check: [Lp] sigma of U0T (log2 units), sigma_hat of hatPsi_T
+  const double* sighT;
+  // calibration
+  uint32_t* slots;      // encoded column maxima of the stored output (slot p at slots + p*nslot_stride), nullptr = off
+  int nslot;
+  size_t nslot_stride;
+  int* flags;
+  // check pass
+  double* part;         // [nblk][kNSt] stats partials of this time (nullptr = no stats)
+  int tout;             // output time (for per-commodity output)
+  double* occ;          // [n] occupancy at the output time (output pass), nullptr = none
+  double* pcomm;        // [L][n] per-commodity marginal at the output time, nullptr = none
+};
+
+struct ElemArgs {       // row-wise kernels over one panel time
+  int n, Lp, L, G, nchunk;
+};
+
+// order-preserving float encoding for atomicMax on signed values (0 = empty)
+__device__ __forceinline__ uint32_t enc_f32(float f) {
+  uint32_t b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__host__ __device__ __forceinline__ float dec_f32(uint32_t e) {
+  uint32_t b = (e & 0x80000000u) ? (e & 0x7fffffffu) : ~e;
+  union { uint32_t u; float f; } c; c.u = b; return c.f;
+}
+
+// XCD-aware block order: hardware dispatches block b to XCD b % 8; give each
+// XCD a contiguous range of logical blocks so neighbouring states (which share
+// gathered rows) meet in the same L2.  nblk must be a multiple of 8.
+__device__ __forceinline__ int xcd_block(int b, int nblk) {
+  const int per = nblk >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+}  // namespace mmot
