@@ -30,11 +30,12 @@ template <typename V, bool LOG>
 void launch_set_duals(const double*, const double*, const double*, int, int, int, int, V*, V*, V*, double*, double*,
                       hipStream_t);
 void launch_excess(const int*, const int*, const double*, int, double*, int*, double*, hipStream_t);
+void launch_max_degree(const int*, int, int*, hipStream_t);
+template <typename V> void launch_build_ell(const int*, const int*, const V*, int, int, V, int*, V*, int*, hipStream_t);
 // sweep_sparse.hip
 template <typename V, bool LOG> void launch_step(const StepArgs<V>&, int, int, hipStream_t);
 template <typename V, bool LOG>
-void launch_source(int, int, int, int, const V*, const V*, const V*, V*, uint32_t*, int, size_t, int*, int,
-                   hipStream_t);
+void launch_source(int, int, int, int, const V*, const V*, V*, uint32_t*, int, size_t, int*, int, hipStream_t);
 template <typename V, bool LOG>
 void launch_check0(int, int, int, int, int, const V*, const V*, const V*, const double*, const double*, double*,
                    double*, double*, int, hipStream_t);
@@ -42,13 +43,14 @@ template <typename V, bool LOG>
 void launch_flows(int, int, int, int, int, const int*, const int*, const V*, const double*, const V*, const V*,
                   const V*, const V*, const double*, const double*, double*, double*, int, hipStream_t);
 template <typename V, bool LOG>
-void launch_prep_bwd(int, int, const double*, double*, V*, const double*, hipStream_t);
+void launch_prep_bwd(int, int, const double*, double*, V*, const double*, double*, uint32_t*, int, hipStream_t);
 template <typename V, bool LOG>
-void launch_prep_fwd(int, int, int, const double*, const double*, double*, const double*, V*, V*, double*, double*,
-                     hipStream_t);
-void launch_consume(uint32_t*, double*, int, int, int, hipStream_t);
+void launch_prep_fwd(int, int, int, const double*, double*, const double*, V*, V*, double*, double*, double*, uint32_t*,
+                     int, hipStream_t);
+void launch_growth(double*, const float*, int, int, int, hipStream_t);
+void launch_levels(uint32_t*, float*, int, int, int, hipStream_t);
 void launch_reduce_stats(const double*, int, int, double*, double, double*, hipStream_t);
-void launch_reduce_cost(const double*, int, int, double*, double*, hipStream_t);
+void launch_reduce_cost(const double*, const double*, int, int, double*, double*, double*, hipStream_t);
 }  // namespace mmot
 
 using namespace mmot;
@@ -90,11 +92,18 @@ struct mmot_solver {
   void *psi = nullptr, *zh = nullptr, *u = nullptr;
   double *cb = nullptr, *cf = nullptr, *sigb = nullptr, *sigf = nullptr, *gauge0 = nullptr, *gaugeT = nullptr;
   void *facb = nullptr, *facf = nullptr, *wgt = nullptr;
-  uint32_t *slots_b = nullptr, *slots_f = nullptr, *rho = nullptr;
+  uint32_t *slots_b = nullptr, *slots_f = nullptr, *slotsE = nullptr, *slotsS = nullptr, *rho = nullptr;
+  double *lvlT = nullptr, *lvl0 = nullptr;
+  float *levb = nullptr, *levf = nullptr;
   double *part = nullptr, *tpart = nullptr, *stats_dev = nullptr, *masses = nullptr;
+  double *part_flow = nullptr, *tpart_flow = nullptr;
   double *exc_row = nullptr, *exc = nullptr;
   int* exc_cnt = nullptr;
   int* flags = nullptr;
+  // ELL copies of the operators (row width ellD, 0 = use CSR)
+  int ellD = 0;
+  int *ell_ci_b = nullptr, *ell_ci_f = nullptr, *deg_b = nullptr, *deg_f = nullptr, *maxdeg = nullptr;
+  void *ell_kv_b = nullptr, *ell_kv_f = nullptr;
   // host state
   int64_t iters = 0;
   bool psi_fresh = false, pend_b = false, pend_f = false;
@@ -111,6 +120,8 @@ struct mmot_solver {
 namespace {
 
 int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
+constexpr int kEllMax = 64;    // widest ELL row kept; wider graphs use CSR
+constexpr int kEllQuant = 16;  // ELL rows padded to a multiple of the gather batch
 
 void set_geometry(mmot_solver* s) {
   s->vsize = (s->prec == MMOT_FP64) ? 8 : 4;
@@ -160,15 +171,30 @@ void carve(mmot_solver* s, Carver& c) {
   s->wgt = takev((T + 1) * Lp);
   s->slots_b = c.take<uint32_t>((size_t)s->nslot * (T + 1) * Lp);
   s->slots_f = c.take<uint32_t>((size_t)s->nslot * (T + 1) * Lp);
+  s->slotsE = c.take<uint32_t>((size_t)s->nslot * Lp);
+  s->slotsS = c.take<uint32_t>((size_t)s->nslot * Lp);
+  s->lvlT = c.take<double>(Lp);
+  s->lvl0 = c.take<double>(Lp);
+  s->levb = c.take<float>((T + 1) * Lp);
+  s->levf = c.take<float>((T + 1) * Lp);
   s->rho = c.take<uint32_t>(2);
   s->part = c.take<double>((T + 1) * (size_t)s->nblk * kNSt);
   s->tpart = c.take<double>((T + 1) * kNSt);
+  s->part_flow = c.take<double>((T + 1) * (size_t)s->nblk * kNSt);
+  s->tpart_flow = c.take<double>((T + 1) * kNSt);
   s->stats_dev = c.take<double>(8);
   s->masses = c.take<double>(s->L);
   s->exc_row = c.take<double>(n);
   s->exc_cnt = c.take<int>(n);
   s->exc = c.take<double>(1);
   s->flags = c.take<int>(4);
+  s->ell_ci_b = c.take<int>(n * kEllMax);
+  s->ell_ci_f = c.take<int>(n * kEllMax);
+  s->ell_kv_b = takev(n * kEllMax);
+  s->ell_kv_f = takev(n * kEllMax);
+  s->deg_b = c.take<int>(n);
+  s->deg_f = c.take<int>(n);
+  s->maxdeg = c.take<int>(2);
 }
 
 mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
@@ -204,6 +230,7 @@ struct Impl {
     StepArgs<V> a;
     std::memset(&a, 0, sizeof(a));
     a.n = s->n; a.Lp = s->Lp; a.L = s->L; a.G = s->G; a.nchunk = s->nchunk;
+    a.eps = s->eps;
     a.nslot = s->nslot;
     a.nslot_stride = (size_t)(s->T + 1) * s->Lp;
     a.flags = s->flags;
@@ -214,6 +241,7 @@ struct Impl {
     const int T = s->T;
     StepArgs<V> a = base_args(s);
     a.rp = s->rp_b; a.ci = s->ci_b; a.kv = static_cast<const V*>(s->kv_b);
+    if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_b; a.kv = static_cast<const V*>(s->ell_kv_b); a.deg = s->deg_b; }
     a.xin = (t + 1 == T) ? static_cast<const V*>(s->U0T) : psi(s, t + 1);
     a.uin = uat(s, t + 1);
     a.fac = static_cast<const V*>(s->facb) + (size_t)t * s->Lp;
@@ -226,8 +254,12 @@ struct Impl {
 
   static void backward(mmot_solver* s, bool consume, bool calib, hipStream_t st) {
     const int T = s->T;
-    if (consume) launch_consume(s->slots_b, s->cb, T + 1, s->Lp, s->nslot, st);
-    launch_prep_bwd<V, LOG>(T, s->Lp, s->cb, s->sigb, static_cast<V*>(s->facb), s->gaugeT, st);
+    if (consume) {
+      launch_levels(s->slots_b, s->levb, T + 1, s->Lp, s->nslot, st);
+      launch_growth(s->cb, s->levb, T, s->Lp, 0, st);
+    }
+    launch_prep_bwd<V, LOG>(T, s->Lp, s->cb, s->sigb, static_cast<V*>(s->facb), s->gaugeT, s->lvlT, s->slotsE,
+                            s->nslot, st);
     for (int t = T - 1; t >= 0; --t) launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk, st);
   }
 
@@ -237,6 +269,7 @@ struct Impl {
     const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
     StepArgs<V> a = base_args(s);
     a.rp = s->rp_f; a.ci = s->ci_f; a.kv = static_cast<const V*>(s->kv_f);
+    if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_f; a.kv = static_cast<const V*>(s->ell_kv_f); a.deg = s->deg_f; }
     a.xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
     a.uin = uat(s, t);
     const int to = t + 1;
@@ -260,10 +293,14 @@ struct Impl {
       a.epi = 2;
       a.rdst = static_cast<const V*>(s->R0T);
       a.u0t = static_cast<V*>(s->U0T);
-      a.facT = static_cast<const V*>(s->facb) + (size_t)T * Lp;
       a.sigT = s->sigb + (size_t)T * Lp;
       a.sighT = s->sigf + (size_t)T * Lp;
-      a.slots = (mode == 0 && calib) ? s->slots_b + (size_t)T * Lp : nullptr;
+      if (mode == 0) {
+        a.slots = s->slotsE;             // exact level of the new U0T panel, every iteration
+        a.nslot_stride = Lp;
+        a.slots_o = calib ? s->slots_f + (size_t)T * Lp : nullptr;
+        a.nslot_stride_o = (size_t)(T + 1) * Lp;
+      }
     }
     return a;
   }
@@ -275,20 +312,23 @@ struct Impl {
                       hipStream_t st) {
     const int T = s->T;
     const size_t Lp = s->Lp;
-    if (mode == 0 && consume) launch_consume(s->slots_f, s->cf, T + 1, s->Lp, s->nslot, st);
-    launch_prep_fwd<V, LOG>(T, s->Lp, mode, s->cf, s->cb, s->sigf, s->sigb, static_cast<V*>(s->facf),
-                            static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, st);
-    const size_t pstride = (size_t)s->nblk * kNSt;
     if (mode == 0) {
+      // source update first: its output level feeds the offsets of the sweep
       launch_source<V, LOG>(s->n, s->Lp, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->R01),
-                            static_cast<const V*>(s->facf), static_cast<V*>(s->U01),
-                            calib ? s->slots_f : nullptr, s->nslot, (size_t)(T + 1) * Lp, s->flags, s->nblk, st);
-    } else {
-      launch_check0<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->U01),
-                            static_cast<const V*>(s->R01), s->sigf, s->sigb, s->part, occ,
-                            pcomm, s->nblk, st);
+                            static_cast<V*>(s->U01), s->slotsS, s->nslot, Lp, s->flags, s->nblk, st);
+      if (consume) {
+        launch_levels(s->slots_f, s->levf, T + 1, s->Lp, s->nslot, st);
+        launch_growth(s->cf, s->levf, T, s->Lp, 1, st);
+      }
     }
-    for (int t = 0; t < T; ++t) launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), 1, s->nblk, st);
+    launch_prep_fwd<V, LOG>(T, s->Lp, mode, s->cf, s->sigf, s->sigb, static_cast<V*>(s->facf),
+                            static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, s->lvl0, s->slotsS, s->nslot, st);
+    if (mode == 1) {
+      launch_check0<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->U01),
+                            static_cast<const V*>(s->R01), s->sigf, s->sigb, s->part, occ, pcomm, s->nblk, st);
+    }
+    for (int t = 0; t < T; ++t)
+      launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), mode == 0 ? 1 : 2, s->nblk, st);
   }
 
   // time `reps` launches of one sweep step at the middle time, as launched in
@@ -317,28 +357,18 @@ struct Impl {
   static void flows_pass(mmot_solver* s, double* flow, hipStream_t st) {
     const int T = s->T;
     const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
-    launch_prep_fwd<V, LOG>(T, s->Lp, 1, s->cf, s->cb, s->sigf, s->sigb, static_cast<V*>(s->facf),
-                            static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, st);
+    launch_prep_fwd<V, LOG>(T, s->Lp, 1, s->cf, s->sigf, s->sigb, static_cast<V*>(s->facf),
+                            static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, s->lvl0, s->slotsS, s->nslot, st);
     for (int t = 0; t < T; ++t) {
       const V* xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
       const int tb = t + 1;
       launch_flows<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, s->rp_b, s->ci_b, static_cast<const V*>(s->kv_b),
                            s->cost, xin, uat(s, t), (tb == T) ? static_cast<const V*>(s->U0T) : psi(s, tb),
                            uat(s, tb), s->sigf + (size_t)t * Lp, s->sigb + (size_t)tb * Lp,
-                           flow + (size_t)t * s->nnz, s->part + (size_t)t * pstride, s->nblk, st);
-      if (tb < T) {
-        StepArgs<V> a = base_args(s);
-        a.rp = s->rp_f; a.ci = s->ci_f; a.kv = static_cast<const V*>(s->kv_f);
-        a.xin = xin; a.uin = uat(s, t);
-        a.fac = static_cast<const V*>(s->facf) + (size_t)tb * Lp;
-        a.update = 0;
-        a.epi = 0;
-        a.out = zh(s, tb);
-        a.kl = s->has_kl ? static_cast<const V*>(s->KL) : nullptr;
-        launch_step<V, LOG>(a, 1, s->nblk, st);
-      }
+                           flow + (size_t)t * s->nnz, s->part_flow + (size_t)t * pstride, s->nblk, st);
+      if (tb < T) launch_step<V, LOG>(fwd_args(s, t, 1, false, nullptr, nullptr), 2, s->nblk, st);
     }
-    launch_reduce_cost(s->part, s->nblk, T, s->tpart, s->stats_dev + 7, st);
+    launch_reduce_cost(s->part_flow, s->part, s->nblk, T, s->tpart_flow, s->tpart, s->stats_dev + 7, st);
   }
 
   static mmot_status setup(mmot_solver* s, const mmot_problem* p) {
@@ -363,6 +393,23 @@ struct Impl {
     launch_gibbs<V, LOG>(s->cost, nnz, s->eps, static_cast<V*>(s->kv_b), st);
     launch_transpose_pattern(s->rp_b, s->ci_b, s->n, s->nnz, s->cnt, s->rp_f, s->cursor, s->ci_f, s->srcpos, st);
     launch_gather_vals<V>(static_cast<const V*>(s->kv_b), s->srcpos, s->nnz, static_cast<V*>(s->kv_f), st);
+    launch_fill<int>(s->maxdeg, 2, 0, st);
+    launch_max_degree(s->rp_b, s->n, s->maxdeg, st);
+    launch_max_degree(s->rp_f, s->n, s->maxdeg + 1, st);
+    HIPCK(hipMemcpyAsync(s->host_flags, s->maxdeg, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCK(hipStreamSynchronize(st));
+    {
+      const int D = std::max(s->host_flags[0], s->host_flags[1]);
+      const int Dp = (D + kEllQuant - 1) / kEllQuant * kEllQuant;
+      s->ellD = (Dp >= kEllQuant && Dp <= kEllMax) ? Dp : 0;
+    }
+    if (s->ellD) {
+      const V pad = LOG ? -static_cast<V>(INFINITY) : V(0);
+      launch_build_ell<V>(s->rp_b, s->ci_b, static_cast<const V*>(s->kv_b), s->n, s->ellD, pad, s->ell_ci_b,
+                          static_cast<V*>(s->ell_kv_b), s->deg_b, st);
+      launch_build_ell<V>(s->rp_f, s->ci_f, static_cast<const V*>(s->kv_f), s->n, s->ellD, pad, s->ell_ci_f,
+                          static_cast<V*>(s->ell_kv_f), s->deg_f, st);
+    }
     launch_fill<uint32_t>(s->rho, 2, 0u, st);
     launch_rowsum_max<V, LOG>(s->rp_b, static_cast<const V*>(s->kv_b), s->n, 0.0, s->rho, st);
     launch_rowsum_max<V, LOG>(s->rp_f, static_cast<const V*>(s->kv_f), s->n, 0.0, s->rho + 1, st);
@@ -383,6 +430,10 @@ struct Impl {
     launch_fill<V>(static_cast<V*>(s->zh), 2 * n * Lp, zero, st);
     launch_fill<uint32_t>(s->slots_b, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
     launch_fill<uint32_t>(s->slots_f, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
+    launch_fill<uint32_t>(s->slotsE, (size_t)s->nslot * Lp, 0u, st);
+    launch_fill<uint32_t>(s->slotsS, (size_t)s->nslot * Lp, 0u, st);
+    launch_fill<double>(s->lvlT, Lp, 0.0, st);
+    launch_fill<double>(s->lvl0, Lp, 0.0, st);
     launch_init_offsets(s->cb, s->cf, s->gauge0, s->gaugeT, s->T, s->Lp, s->rho, st);
     HIPCK(hipGetLastError());
     HIPCK(hipStreamSynchronize(st));
@@ -416,8 +467,9 @@ mmot_status read_flags(mmot_solver* s) {
 
 mmot_status run_iterations(mmot_solver* s, int n_iter) {
   for (int k = 0; k < n_iter; ++k) {
-    const bool calib = s->iters < 3 || s->force_calib > 0 ||
-                       (s->opt.calib_every > 0 && s->iters % s->opt.calib_every == 0);
+    const bool calib = s->opt.calib_every >= 0 &&
+                       (s->iters < 3 || s->force_calib > 0 ||
+                        (s->opt.calib_every > 0 && s->iters % s->opt.calib_every == 0));
     const bool runB = !s->psi_fresh;
     const bool cb = runB && s->pend_b, cf = s->pend_f;
     const int key = (runB ? 1 : 0) | (cb ? 2 : 0) | (calib ? 4 : 0) | (cf ? 8 : 0);
@@ -658,6 +710,10 @@ mmot_status mmot_set_log_duals(mmot_solver* s, const double* ls, const double* l
       launch_set_duals<float, false>(ls, ld, lc, s->n, s->L, s->Lp, s->T - 1, static_cast<float*>(s->U01),
                                      static_cast<float*>(s->U0T), static_cast<float*>(s->u), s->gauge0, s->gaugeT, s->stream);
   }
+  launch_fill<uint32_t>(s->slotsE, (size_t)s->nslot * s->Lp, 0u, s->stream);
+  launch_fill<uint32_t>(s->slotsS, (size_t)s->nslot * s->Lp, 0u, s->stream);
+  launch_fill<double>(s->lvlT, s->Lp, 0.0, s->stream);
+  launch_fill<double>(s->lvl0, s->Lp, 0.0, s->stream);
   s->psi_fresh = false;
   s->force_calib = 2;
   return hipGetLastError() == hipSuccess ? MMOT_OK : MMOT_EHIP;

@@ -10,8 +10,12 @@
 // Range control.  Scaled domain: panel value x represents x * 2^sigma[l] with
 // a per-commodity FP64 offset sigma (one per time and sweep direction).  Log
 // domain: panel value y represents 2^(y + sigma[l]).  Each product step
-// multiplies its output by 2^-c[t][l] (adds -c in the log domain); c is
-// re-centred from per-column maxima recorded on calibration sweeps.
+// multiplies its output by 2^-c[t][l] (adds -c in the log domain), where c is
+// the step's growth (log2 column-max of the output minus that of the input,
+// measured on calibration sweeps, so it does not depend on how the input was
+// scaled).  The first product of each sweep also removes the exact column
+// level of the sweep's starting panel (U0T or U01), recorded by the kernel
+// that wrote that panel every iteration.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -25,7 +29,8 @@ constexpr int kBlock = 256;            // threads per block (4 wavefronts)
 constexpr int kWaves = kBlock / 64;
 constexpr int kNSt = 8;                // doubles per stats partial
 // stats partial fields
-enum { ST_SRC_ABS = 0, ST_SRC_MASS = 1, ST_CAP_VIOL = 2, ST_DUAL = 3, ST_GAP = 4, ST_MASS = 5, ST_NONFINITE = 6 };
+enum { ST_SRC_ABS = 0, ST_SRC_MASS = 1, ST_CAP_VIOL = 2, ST_DUAL = 3, ST_GAP = 4, ST_MASS = 5, ST_NONFINITE = 6,
+       ST_SCOST = 7 };
 // device flag bits
 enum { FLAG_INFEASIBLE = 1, FLAG_NONFINITE = 2, FLAG_BADINPUT = 4, FLAG_BADCSR = 8, FLAG_MASS = 16 };
 
@@ -34,9 +39,12 @@ enum { FLAG_INFEASIBLE = 1, FLAG_NONFINITE = 2, FLAG_BADINPUT = 4, FLAG_BADCSR =
 template <typename V>
 struct StepArgs {
   int n, Lp, L, G, nchunk;
-  const int* rp;        // operator CSR (rows = output states)
-  const int* ci;
-  const V* kv;          // K values (scaled) or log2 K (log)
+  double eps;
+  const int* rp;        // operator CSR (rows = output states); unused when ellD > 0
+  const int* ci;        // CSR column indices, or ELL [n][ellD] (padding: index = row)
+  const V* kv;          // K values (scaled) or log2 K (log); ELL padding 0 / -inf
+  int ellD;             // > 0: ELL layout with this (padded) row width, deg[] = true row lengths
+  const int* deg;
   const V* xin;         // input panel (already multiplied by K_L at its time)
   const V* uin;         // u at the input time, nullptr = 1
   const V* fac;         // [Lp] per-column output factor 2^-c (scaled) or -c (log)
@@ -51,13 +59,14 @@ struct StepArgs {
   V* uout;              // [n] u at the output time
   const V* rdst;        // sink: R0T panel (log2 in the log domain)
   V* u0t;               // sink: U0T panel (written when update)
-  const V* facT;        // sink: [Lp] factor of the U0T panel
   const double* sigT;   // sink/check: [Lp] sigma of U0T (log2 units), sigma_hat of hatPsi_T
   const double* sighT;
-  // calibration
-  uint32_t* slots;      // encoded column maxima of the stored output (slot p at slots + p*nslot_stride), nullptr = off
+  // column-level recording (log2 column maxima, encoded, slot p at base + p*nslot_stride)
+  uint32_t* slots;      // levels of the stored output panel (sink: of the new U0T panel), nullptr = off
+  uint32_t* slots_o;    // sink only: levels of hatPsi_T itself, nullptr = off
   int nslot;
   size_t nslot_stride;
+  size_t nslot_stride_o;
   int* flags;
   // check pass
   double* part;         // [nblk][kNSt] stats partials of this time (nullptr = no stats)

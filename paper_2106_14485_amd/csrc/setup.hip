@@ -140,6 +140,26 @@ __global__ void k_rowsum_max(const int* __restrict__ rp, const V* __restrict__ k
   if ((threadIdx.x & 63) == 0 && v > -INFINITY) atomicMax(out, enc_f32(v));
 }
 
+// -------- ELL copy of an operator (rows padded to D entries) --------
+__global__ void k_max_degree(const int* __restrict__ rp, int n, int* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  int d = (i < n) ? rp[i + 1] - rp[i] : 0;
+  for (int m = 32; m > 0; m >>= 1) d = max(d, __shfl_xor(d, m, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, d);
+}
+template <typename V>
+__global__ void k_build_ell(const int* __restrict__ rp, const int* __restrict__ ci, const V* __restrict__ kv, int n,
+                            int D, V pad, int* __restrict__ eci, V* __restrict__ ekv, int* __restrict__ deg) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int a = rp[i], d = rp[i + 1] - a;
+  deg[i] = d;
+  for (int k = 0; k < D; ++k) {
+    eci[(size_t)i * D + k] = (k < d) ? ci[a + k] : i;
+    ekv[(size_t)i * D + k] = (k < d) ? kv[a + k] : pad;
+  }
+}
+
 // -------- layout conversion: (L x n, l-major, double) -> panel [n][Lp] --------
 // mode 0: value; 1: log2(value) (-inf for 0); 2: exp(-value/eps) (state cost -> K_L);
 // 3: -value/eps*log2(e) (state cost -> log2 K_L).  Padding columns get padv.
@@ -282,6 +302,18 @@ __global__ void k_excess_total(const double* __restrict__ rowsum, const int* __r
 
 // -------- launchers --------
 static inline int gs(size_t cnt) { return (int)((cnt + 255) / 256 > 4096 ? 4096 : (cnt + 255) / 256 ? (cnt + 255) / 256 : 1); }
+
+void launch_max_degree(const int* rp, int n, int* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_max_degree, dim3((n + 255) / 256), dim3(256), 0, s, rp, n, out);
+}
+template <typename V>
+void launch_build_ell(const int* rp, const int* ci, const V* kv, int n, int D, V pad, int* eci, V* ekv, int* deg,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_build_ell<V>, dim3((n + 255) / 256), dim3(256), 0, s, rp, ci, kv, n, D, pad, eci, ekv, deg);
+}
+template void launch_build_ell<float>(const int*, const int*, const float*, int, int, float, int*, float*, int*, hipStream_t);
+template void launch_build_ell<double>(const int*, const int*, const double*, int, int, double, int*, double*, int*,
+                                       hipStream_t);
 
 void launch_validate_vals(const double* x, size_t cnt, int allow_inf, int strictly_pos, int allow_neg, int* flags,
                           hipStream_t s) {

@@ -125,9 +125,10 @@ __device__ void calib_chunk(const V (&val)[VT<V>::N], int G, int chunk_col0, int
 // ---------------------------------------------------------------------------
 // the sweep step
 // ---------------------------------------------------------------------------
-template <typename V, bool LOG, bool FWD>
+template <typename V, bool LOG, bool FWD, bool CHK>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
   constexpr int NV = VT<V>::N;
+  constexpr int KB = 16;   // neighbours gathered per batch
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = a.G;
   const int grp = lane / G, gl = lane & (G - 1);
@@ -135,8 +136,12 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
   const int lb = xcd_block(blockIdx.x, gridDim.x);
   const int row = (lb * kWaves + wave) * rpw + grp;
   const bool valid = row < a.n;
+  const bool ell = a.ellD > 0;
   int e0 = 0, e1 = 0;
-  if (valid) { e0 = a.rp[row]; e1 = a.rp[row + 1]; }
+  if (valid) {
+    if (ell) { e0 = row * a.ellD; e1 = e0 + a.deg[row]; }
+    else { e0 = a.rp[row]; e1 = a.rp[row + 1]; }
+  }
   if (G == 64) { e0 = __builtin_amdgcn_readfirstlane(e0); e1 = __builtin_amdgcn_readfirstlane(e1); }
   const size_t Lp = (size_t)a.Lp;
 
@@ -149,41 +154,54 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
     const int col = (ch * G + gl) * NV;
     const bool cv = valid && col < a.Lp;
     V o[NV];
+    // operands of the epilogue that do not depend on the product: issue first
+    V w[NV], g[NV], f[NV];
+    const bool capepi = FWD && a.epi == 1 && cv;
+    if (capepi) {
+      vld(a.wpan + row * Lp + col, w);
+      vld(a.wgt + col, g);
+    }
+    if (cv) vld(a.fac + col, f);
     // ---------------- product ----------------
+    // neighbours in batches of KB: all indices, then all u values and rows are
+    // requested before any of them is used, so one batch costs ~one latency
     if (!LOG) {
       V acc[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] = 0;
       if (cv) {
-        int e = e0;
-        for (; e + 4 <= e1; e += 4) {
-          const int i0 = a.ci[e], i1 = a.ci[e + 1], i2 = a.ci[e + 2], i3 = a.ci[e + 3];
-          V c0 = a.kv[e], c1 = a.kv[e + 1], c2 = a.kv[e + 2], c3 = a.kv[e + 3];
-          if (a.uin) { c0 *= a.uin[i0]; c1 *= a.uin[i1]; c2 *= a.uin[i2]; c3 *= a.uin[i3]; }
-          V x0[NV], x1[NV], x2[NV], x3[NV];
-          vld(a.xin + i0 * Lp + col, x0);
-          vld(a.xin + i1 * Lp + col, x1);
-          vld(a.xin + i2 * Lp + col, x2);
-          vld(a.xin + i3 * Lp + col, x3);
+        for (int e = e0;; e += KB) {
+          const int cnt = min(KB, e1 - e);
+          int idx[KB];
+          V cf[KB];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            acc[v] = fma(c0, x0[v], acc[v]);
-            acc[v] = fma(c1, x1[v], acc[v]);
-            acc[v] = fma(c2, x2[v], acc[v]);
-            acc[v] = fma(c3, x3[v], acc[v]);
+          for (int k = 0; k < KB; ++k) {
+            // ELL rows are padded to a multiple of KB: load without waiting for the row length
+            const bool in = ell || k < cnt;
+            idx[k] = in ? a.ci[e + k] : 0;
+            cf[k] = in ? a.kv[e + k] : V(0);
+            if (k >= cnt) cf[k] = V(0);
           }
-        }
-        for (; e < e1; ++e) {
-          const int i0 = a.ci[e];
-          V c0 = a.kv[e];
-          if (a.uin) c0 *= a.uin[i0];
-          V x0[NV];
-          vld(a.xin + i0 * Lp + col, x0);
+          V x[KB][NV];
 #pragma unroll
-          for (int v = 0; v < NV; ++v) acc[v] = fma(c0, x0[v], acc[v]);
+          for (int k = 0; k < KB; ++k) {
+            if (k < cnt) vld(a.xin + idx[k] * Lp + col, x[k]);
+            else {
+#pragma unroll
+              for (int v = 0; v < NV; ++v) x[k][v] = 0;
+            }
+          }
+          if (a.uin) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) if (k < cnt) cf[k] *= a.uin[idx[k]];
+          }
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v] = fma(cf[k], x[k][v], acc[v]);
+          }
+          if (e + KB >= e1) break;
         }
-        V f[NV];
-        vld(a.fac + col, f);
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = acc[v] * f[v];
       } else {
@@ -191,48 +209,52 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
         for (int v = 0; v < NV; ++v) o[v] = 0;
       }
     } else {
-      V m[NV], s[NV];
+      V m[NV], sm[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) { m[v] = ninf<V>(); s[v] = 0; }
+      for (int v = 0; v < NV; ++v) { m[v] = ninf<V>(); sm[v] = 0; }
       if (cv) {
-        int e = e0;
-        for (; e + 4 <= e1; e += 4) {
-          const int i0 = a.ci[e], i1 = a.ci[e + 1], i2 = a.ci[e + 2], i3 = a.ci[e + 3];
-          V c0 = a.kv[e], c1 = a.kv[e + 1], c2 = a.kv[e + 2], c3 = a.kv[e + 3];
-          if (a.uin) { c0 += a.uin[i0]; c1 += a.uin[i1]; c2 += a.uin[i2]; c3 += a.uin[i3]; }
-          V x0[NV], x1[NV], x2[NV], x3[NV];
-          vld(a.xin + i0 * Lp + col, x0);
-          vld(a.xin + i1 * Lp + col, x1);
-          vld(a.xin + i2 * Lp + col, x2);
-          vld(a.xin + i3 * Lp + col, x3);
+        for (int e = e0;; e += KB) {
+          const int cnt = min(KB, e1 - e);
+          int idx[KB];
+          V cf[KB];
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            const bool in = ell || k < cnt;
+            idx[k] = in ? a.ci[e + k] : 0;
+            cf[k] = in ? a.kv[e + k] : ninf<V>();
+            if (k >= cnt) cf[k] = ninf<V>();
+          }
+          V x[KB][NV];
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            if (k < cnt) vld(a.xin + idx[k] * Lp + col, x[k]);
+            else {
+#pragma unroll
+              for (int v = 0; v < NV; ++v) x[k][v] = ninf<V>();
+            }
+          }
+          if (a.uin) {
+#pragma unroll
+            for (int k = 0; k < KB; ++k) if (k < cnt) cf[k] += a.uin[idx[k]];
+          }
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const V y0 = c0 + x0[v], y1 = c1 + x1[v], y2 = c2 + x2[v], y3 = c3 + x3[v];
-            const V nm = fmax(m[v], fmax(fmax(y0, y1), fmax(y2, y3)));
+            V y[KB];
+            V bm = ninf<V>();
+#pragma unroll
+            for (int k = 0; k < KB; ++k) { y[k] = cf[k] + x[k][v]; bm = fmax(bm, y[k]); }
+            const V nm = fmax(m[v], bm);
             const V b = (nm == ninf<V>()) ? V(0) : nm;
-            s[v] = s[v] * xexp2(m[v] - b) + xexp2(y0 - b) + xexp2(y1 - b) + xexp2(y2 - b) + xexp2(y3 - b);
+            V acc = sm[v] * xexp2(m[v] - b);
+#pragma unroll
+            for (int k = 0; k < KB; ++k) acc += xexp2(y[k] - b);
+            sm[v] = acc;
             m[v] = nm;
           }
+          if (e + KB >= e1) break;
         }
-        for (; e < e1; ++e) {
-          const int i0 = a.ci[e];
-          V c0 = a.kv[e];
-          if (a.uin) c0 += a.uin[i0];
-          V x0[NV];
-          vld(a.xin + i0 * Lp + col, x0);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const V y0 = c0 + x0[v];
-            const V nm = fmax(m[v], y0);
-            const V b = (nm == ninf<V>()) ? V(0) : nm;
-            s[v] = s[v] * xexp2(m[v] - b) + xexp2(y0 - b);
-            m[v] = nm;
-          }
-        }
-        V f[NV];
-        vld(a.fac + col, f);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) o[v] = (s[v] > V(0)) ? m[v] + xlog2(s[v]) + f[v] : ninf<V>();
+        for (int v = 0; v < NV; ++v) o[v] = (sm[v] > V(0)) ? m[v] + xlog2(sm[v]) + f[v] : ninf<V>();
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = ninf<V>();
@@ -244,21 +266,20 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
     if (FWD && a.epi == 2) {
       // sink: U0T = R0T ./ hatPsi_T (Algorithm 2), zero off the support
       if (cv) {
-        V r[NV], f[NV], cur[NV];
+        V r[NV], cur[NV];
         vld(a.rdst + row * Lp + col, r);
-        vld(a.facT + col, f);
-        if (a.update) {
+        if (!CHK) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             if (!LOG) {
               if (r[v] > V(0)) {
                 if (!(o[v] > V(0))) atomicOr(a.flags, FLAG_INFEASIBLE);
-                z[v] = r[v] / o[v] * f[v];
+                z[v] = r[v] / o[v];
               } else z[v] = 0;
             } else {
               if (r[v] != ninf<V>()) {
                 if (o[v] == ninf<V>()) atomicOr(a.flags, FLAG_INFEASIBLE);
-                z[v] = r[v] - o[v] + f[v];
+                z[v] = r[v] - o[v];
               } else z[v] = ninf<V>();
             }
           }
@@ -268,7 +289,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) z[v] = cur[v];
         }
-        if (a.part || a.occ || a.pcomm) {
+        if (CHK) {
           // P_{0,T} = U0T (.) hatPsi_T, the sink marginal of the current plan
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
@@ -297,10 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
         for (int v = 0; v < NV; ++v) z[v] = LOG ? ninf<V>() : V(0);
       }
     } else {
-      if (FWD && cv && a.epi == 1) {
-        V w[NV], g[NV];
-        vld(a.wpan + row * Lp + col, w);
-        vld(a.wgt + col, g);
+      if (capepi) {
         if (!LOG) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) ssum = fma(o[v] * w[v], g[v], ssum);
@@ -314,9 +332,12 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
             lm = nm;
           }
         }
-        if (a.pcomm) {
-          // output pass: u is final, P_{0,t} = hatPsi (.) Psi (.) K_L u_t (eq. proj_0t)
+        if (CHK && (a.pcomm || a.kl)) {
+          // update-free pass: u is final, P_{0,t} = hatPsi (.) Psi (.) K_L u_t (eq. proj_0t);
+          // with state costs also accumulate <C_L, P_{0,t}> (cost tensor, eq. cost_multicommodity)
           const V ur = a.uout[row];
+          V k[NV];
+          if (a.kl) vld(a.kl + row * Lp + col, k);
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             const int l = col + v;
@@ -324,7 +345,11 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
             double P = LOG ? ((o[v] == ninf<V>() || w[v] == ninf<V>()) ? 0.0
                                 : exp2((double)o[v] + (double)w[v] + (double)g[v] + (double)ur))
                            : (double)o[v] * (double)w[v] * (double)g[v] * (double)ur;
-            a.pcomm[(size_t)l * a.n + row] = P;
+            if (a.pcomm) a.pcomm[(size_t)l * a.n + row] = P;
+            if (a.kl && P > 0.0) {
+              const double cl = LOG ? -(double)k[v] * a.eps * M_LN2 : -a.eps * log((double)k[v]);
+              st[ST_SCOST] += P * cl;
+            }
           }
         }
       }
@@ -344,6 +369,13 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
       }
     }
     if (a.slots) calib_chunk<V, LOG>(z, G, ch * G * NV, a.Lp, a.slots + (size_t)(blockIdx.x % a.nslot) * a.nslot_stride);
+    if (FWD && a.slots_o) {
+      if (!cv) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) o[v] = LOG ? ninf<V>() : V(0);
+      }
+      calib_chunk<V, LOG>(o, G, ch * G * NV, a.Lp, a.slots_o + (size_t)(blockIdx.x % a.nslot) * a.nslot_stride_o);
+    }
   }
 
   // ---------------- capacity update (Corollary 1 + Proposition 1) ----------------
@@ -354,14 +386,14 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
     if (valid && gl == 0) {
       const V d = a.cap[row];
       V u;
-      if (a.update) {
+      if (!CHK) {
         if (!LOG) u = (sv <= d) ? V(1) : d / sv;
         else u = fmin(V(0), d - sv);
         a.uout[row] = u;
       } else {
         u = a.uout[row];
       }
-      if (a.part || a.occ) {
+      if (CHK) {
         double occ, dd, lnu;
         if (!LOG) { occ = (double)u * (double)sv; dd = (double)d; lnu = log((double)u); }
         else {
@@ -379,13 +411,13 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
       }
     }
   }
-  if (FWD && a.epi == 2 && (a.part || a.occ)) {
+  if (CHK && a.epi == 2) {
     // gather the row's occupancy across the group lanes for the output
     double t = occ_row;
     for (int m = G >> 1; m > 0; m >>= 1) t += __shfl_xor(t, m, 64);
     if (valid && gl == 0 && a.occ) a.occ[row] = t;
   }
-  if (FWD && a.part) block_stats(st, a.part, blockIdx.x);
+  if (CHK && a.part) block_stats(st, a.part, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,9 +425,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
 // ---------------------------------------------------------------------------
 template <typename V, bool LOG>
 __global__ __launch_bounds__(kBlock) void k_source(int n, int Lp, int G, int nchunk, const V* __restrict__ psi0,
-                                                   const V* __restrict__ rsrc, const V* __restrict__ fac,
-                                                   V* __restrict__ u01, uint32_t* slots, int nslot,
-                                                   size_t slot_stride, int* flags) {
+                                                   const V* __restrict__ rsrc, V* __restrict__ u01, uint32_t* slots,
+                                                   int nslot, size_t slot_stride, int* flags) {
   constexpr int NV = VT<V>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / G, gl = lane & (G - 1);
@@ -407,21 +438,20 @@ __global__ __launch_bounds__(kBlock) void k_source(int n, int Lp, int G, int nch
     const bool cv = valid && col < Lp;
     V z[NV];
     if (cv) {
-      V x[NV], r[NV], f[NV];
+      V x[NV], r[NV];
       vld(psi0 + (size_t)row * Lp + col, x);
       vld(rsrc + (size_t)row * Lp + col, r);
-      vld(fac + col, f);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (!LOG) {
           if (r[v] > V(0)) {
             if (!(x[v] > V(0))) atomicOr(flags, FLAG_INFEASIBLE);
-            z[v] = r[v] / x[v] * f[v];
+            z[v] = r[v] / x[v];
           } else z[v] = 0;
         } else {
           if (r[v] != ninf<V>()) {
             if (x[v] == ninf<V>()) atomicOr(flags, FLAG_INFEASIBLE);
-            z[v] = r[v] - x[v] + f[v];
+            z[v] = r[v] - x[v];
           } else z[v] = ninf<V>();
         }
       }
@@ -575,21 +605,52 @@ __global__ __launch_bounds__(kBlock) void k_flows(int n, int Lp, int L, int G, i
 }
 
 // ---------------------------------------------------------------------------
-// range-offset bookkeeping (one thread per commodity column)
+// range-offset bookkeeping
 // ---------------------------------------------------------------------------
-// c[t][l] += max over calibration slots (log2 of the column max of the stored
-// panel), slots cleared.  Thread per (t, l).
-__global__ void k_consume(uint32_t* slots, double* c, int T1, int Lp, int nslot) {
+// lev[t][l] = max over calibration slots (log2 column max of the panel stored
+// at time t, -inf if nothing was recorded); slots cleared.  Thread per (t, l);
+// all slot reads are issued before any clear.
+__global__ void k_levels(uint32_t* slots, float* lev, int T1, int Lp, int nslot) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= T1 * Lp) return;
+  const size_t stride = (size_t)T1 * Lp;
+  uint32_t v[32];
+#pragma unroll
+  for (int p = 0; p < 32; ++p) v[p] = (p < nslot) ? slots[p * stride + idx] : 0u;
   float m = -INFINITY;
-  for (int p = 0; p < nslot; ++p) {
-    uint32_t* s = slots + (size_t)p * T1 * Lp + idx;
-    const uint32_t e = *s;
-    if (e) m = fmaxf(m, dec_f32(e));
-    *s = 0u;
+#pragma unroll
+  for (int p = 0; p < 32; ++p) {
+    if (v[p]) {
+      m = fmaxf(m, dec_f32(v[p]));
+      slots[p * stride + idx] = 0u;
+    }
   }
-  if (m > -INFINITY && isfinite(m)) c[idx] += (double)m;
+  lev[idx] = m;
+}
+
+// wave-level helpers for the one-wavefront-per-commodity prep kernels
+__device__ __forceinline__ double wave_incl_scan(double x) {
+  const int lane = threadIdx.x & 63;
+  for (int d = 1; d < 64; d <<= 1) {
+    const double y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+// exact column level of a sweep's starting panel: lane p reads slot p (cleared);
+// keeps the previous level when nothing was recorded
+__device__ __forceinline__ double wave_take_level(uint32_t* slots, int nslot, int Lp, int l, double prev) {
+  const int lane = threadIdx.x & 63;
+  uint32_t e = 0;
+  if (lane < nslot) {
+    e = slots[(size_t)lane * Lp + l];
+    if (e) slots[(size_t)lane * Lp + l] = 0u;
+  }
+  float m = e ? dec_f32(e) : -INFINITY;
+  for (int d = 32; d > 0; d >>= 1) m = fmaxf(m, __shfl_xor(m, d, 64));
+  const bool any = __ballot(e != 0) != 0;
+  if (!any) return prev;
+  return (m > -INFINITY && isfinite(m)) ? (double)m : 0.0;
 }
 
 template <typename V, bool LOG>
@@ -601,47 +662,102 @@ __device__ __forceinline__ V to_wgt(double s) {
   return LOG ? static_cast<V>(s) : static_cast<V>(exp2(s));
 }
 
-// Backward-sweep offsets: sigma_b[T] = gauge of U0T, sigma_b[t] = sigma_b[t+1] + c_b[t].
-template <typename V, bool LOG>
-__global__ void k_prep_bwd(int T, int Lp, const double* __restrict__ cb, double* __restrict__ sigb,
-                           V* __restrict__ facb, const double* __restrict__ gaugeT) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
-  if (l >= Lp) return;
-  double s = gaugeT[l];
-  sigb[(size_t)T * Lp + l] = s;
-  facb[(size_t)T * Lp + l] = to_fac<V, LOG>(cb[(size_t)T * Lp + l]);
-  for (int t = T - 1; t >= 0; --t) {
-    const double c = cb[(size_t)t * Lp + l];
-    s += c;
-    sigb[(size_t)t * Lp + l] = s;
-    facb[(size_t)t * Lp + l] = to_fac<V, LOG>(c);
+// Growth update from a calibration sweep's column levels (thread per (t, l)):
+// backward (dir 0): c[T-1] += lev[T-1], c[t] += lev[t] - lev[t+1];
+// forward (dir 1):  c[1] += lev[1],     c[t] += lev[t] - lev[t-1] (t = 2..T).
+__global__ void k_growth(double* c, const float* __restrict__ lev, int T, int Lp, int dir) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (T + 1) * Lp) return;
+  const int t = idx / Lp;
+  const float a = lev[idx];
+  if (!(a > -INFINITY)) return;
+  if (dir == 0) {
+    if (t > T - 1) return;
+    if (t == T - 1) { c[idx] += (double)a; return; }
+    const float b = lev[idx + Lp];
+    if (b > -INFINITY) c[idx] += (double)a - (double)b;
+  } else {
+    if (t < 1) return;
+    if (t == 1) { c[idx] += (double)a; return; }
+    const float b = lev[idx - Lp];
+    if (b > -INFINITY) c[idx] += (double)a - (double)b;
   }
 }
 
-// Forward-sweep offsets.  mode 0 (Sinkhorn sweep): the source update writes a
-// new U01 panel, sigma_hat_0 = c_f[0] - sigma_b[0]; mode 1 (check / output
-// pass): U01 is kept, sigma_hat_0 = gauge0.  Then sigma_hat_t = sigma_hat_{t-1}
-// + c_f[t]; weights wgt[t] = 2^(sigma_hat_t + sigma_b[t]); in mode 0 the gauge
-// of the U0T panel the sink update will write is c_b[T] - sigma_hat_T.
+// Backward sweep offsets, one wavefront per commodity l (lanes = times).
+// Start level of the U0T panel from its slots; sigma_b[T] = gauge of U0T;
+// sigma_b[t] = sigma_b[t+1] + c_b[t] (suffix scan), the first product also
+// removing the start level.
 template <typename V, bool LOG>
-__global__ void k_prep_fwd(int T, int Lp, int mode, const double* __restrict__ cf, const double* __restrict__ cb,
-                           double* __restrict__ sigf, const double* __restrict__ sigb, V* __restrict__ facf,
-                           V* __restrict__ wgt, double* __restrict__ gauge0, double* __restrict__ gaugeT) {
-  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_prep_bwd(int T, int Lp, const double* __restrict__ cb, double* __restrict__ sigb,
+                           V* __restrict__ facb, const double* __restrict__ gaugeT, double* __restrict__ lvlT,
+                           uint32_t* slotsE, int nslot) {
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (l >= Lp) return;
-  double s = (mode == 0) ? cf[l] - sigb[l] : gauge0[l];
-  if (mode == 0) gauge0[l] = s;
-  sigf[l] = s;
-  facf[l] = to_fac<V, LOG>(cf[l]);
-  wgt[l] = to_wgt<V, LOG>(s + sigb[l]);
-  for (int t = 1; t <= T; ++t) {
-    const double c = cf[(size_t)t * Lp + l];
-    s += c;
-    sigf[(size_t)t * Lp + l] = s;
-    facf[(size_t)t * Lp + l] = to_fac<V, LOG>(c);
-    wgt[(size_t)t * Lp + l] = to_wgt<V, LOG>(s + sigb[(size_t)t * Lp + l]);
+  const double lv = wave_take_level(slotsE, nslot, Lp, l, lvlT[l]);
+  double carry = gaugeT[l];
+  if (lane == 0) {
+    lvlT[l] = lv;
+    sigb[(size_t)T * Lp + l] = carry;
+    facb[(size_t)T * Lp + l] = to_fac<V, LOG>(0.0);
   }
-  if (mode == 0) gaugeT[l] = cb[(size_t)T * Lp + l] - s;
+  for (int base = T - 1; base >= 0; base -= 64) {
+    const int t = base - lane;
+    const double c = (t >= 0) ? cb[(size_t)t * Lp + l] + ((t == T - 1) ? lv : 0.0) : 0.0;
+    const double incl = wave_incl_scan(c);
+    if (t >= 0) {
+      sigb[(size_t)t * Lp + l] = carry + incl;
+      facb[(size_t)t * Lp + l] = to_fac<V, LOG>(c);
+    }
+    carry += __shfl(incl, 63, 64);
+  }
+}
+
+// Forward sweep offsets, one wavefront per commodity.  mode 0 (Sinkhorn sweep,
+// after the source update wrote U01 = R01 ./ Psi_1 unscaled):
+// sigma_hat_0 = -sigma_b[0], start level from the source kernel's slots;
+// mode 1 (check / output pass): U01 is kept, sigma_hat_0 = gauge0 and the stored
+// start level.  sigma_hat_t = sigma_hat_{t-1} + c_f[t] (prefix scan); weights
+// wgt[t] = 2^(sigma_hat_t + sigma_b[t]); mode 0 also sets the gauge of the U0T
+// panel the sink update is about to write: -sigma_hat_T.
+template <typename V, bool LOG>
+__global__ void k_prep_fwd(int T, int Lp, int mode, const double* __restrict__ cf, double* __restrict__ sigf,
+                           const double* __restrict__ sigb, V* __restrict__ facf, V* __restrict__ wgt,
+                           double* __restrict__ gauge0, double* __restrict__ gaugeT, double* __restrict__ lvl0,
+                           uint32_t* slotsS, int nslot) {
+  const int lane = threadIdx.x & 63;
+  const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (l >= Lp) return;
+  double s0, lv;
+  if (mode == 0) {
+    s0 = -sigb[l];
+    lv = wave_take_level(slotsS, nslot, Lp, l, lvl0[l]);
+  } else {
+    s0 = gauge0[l];
+    lv = lvl0[l];
+  }
+  if (lane == 0) {
+    if (mode == 0) { gauge0[l] = s0; lvl0[l] = lv; }
+    sigf[l] = s0;
+    facf[l] = to_fac<V, LOG>(0.0);
+    wgt[l] = to_wgt<V, LOG>(s0 + sigb[l]);
+  }
+  double carry = s0;
+  for (int base = 1; base <= T; base += 64) {
+    const int t = base + lane;
+    const bool ok = t <= T;
+    const double c = ok ? cf[(size_t)t * Lp + l] + ((t == 1) ? lv : 0.0) : 0.0;
+    const double sb = ok ? sigb[(size_t)t * Lp + l] : 0.0;
+    const double sg = carry + wave_incl_scan(c);
+    if (ok) {
+      sigf[(size_t)t * Lp + l] = sg;
+      facf[(size_t)t * Lp + l] = to_fac<V, LOG>(c);
+      wgt[(size_t)t * Lp + l] = to_wgt<V, LOG>(sg + sb);
+      if (mode == 0 && t == T) gaugeT[l] = -sg;
+    }
+    carry = __shfl(sg, 63, 64);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -695,27 +811,32 @@ __global__ void k_reduce_stats2(const double* __restrict__ tpart, int T1, double
   out[6] = nonfin;
 }
 
-// transport cost = sum of the flow-kernel partials (stage-1 output of T slots)
-__global__ void k_reduce_cost(const double* __restrict__ tpart, int T, double* __restrict__ out) {
+// transport cost = move costs from the flow-kernel partials (tflow, T slots)
+// + state costs from the update-free forward steps (tstate, slots 1..T-1)
+__global__ void k_reduce_cost(const double* __restrict__ tflow, const double* __restrict__ tstate, int T,
+                              double* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double s = 0;
-  for (int t = 0; t < T; ++t) s += tpart[(size_t)t * kNSt];
+  for (int t = 0; t < T; ++t) s += tflow[(size_t)t * kNSt];
+  for (int t = 1; t < T; ++t) s += tstate[(size_t)t * kNSt + ST_SCOST];
   out[0] = s;
 }
 
 // ---------------------------------------------------------------------------
 // host-side launchers (explicit instantiations)
 // ---------------------------------------------------------------------------
+// fwd: 0 backward product, 1 forward Sinkhorn step, 2 forward update-free (check / output) step
 template <typename V, bool LOG>
 void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
-  if (fwd) hipLaunchKernelGGL((k_step<V, LOG, true>), dim3(nblk), dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_step<V, LOG, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+  if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+  else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+  else hipLaunchKernelGGL((k_step<V, LOG, false, false>), dim3(nblk), dim3(kBlock), 0, s, a);
 }
 template <typename V, bool LOG>
-void launch_source(int n, int Lp, int G, int nchunk, const V* psi0, const V* rsrc, const V* fac, V* u01,
-                   uint32_t* slots, int nslot, size_t slot_stride, int* flags, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL((k_source<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, n, Lp, G, nchunk, psi0, rsrc, fac, u01,
-                     slots, nslot, slot_stride, flags);
+void launch_source(int n, int Lp, int G, int nchunk, const V* psi0, const V* rsrc, V* u01, uint32_t* slots,
+                   int nslot, size_t slot_stride, int* flags, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL((k_source<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, n, Lp, G, nchunk, psi0, rsrc, u01, slots,
+                     nslot, slot_stride, flags);
 }
 template <typename V, bool LOG>
 void launch_check0(int n, int Lp, int L, int G, int nchunk, const V* psi0, const V* u01, const V* rsrc,
@@ -732,41 +853,50 @@ void launch_flows(int n, int Lp, int L, int G, int nchunk, const int* rp, const 
                      ua, B, ub, siga, sigb, flow, part);
 }
 template <typename V, bool LOG>
-void launch_prep_bwd(int T, int Lp, const double* cb, double* sigb, V* facb, const double* gaugeT, hipStream_t s) {
-  hipLaunchKernelGGL((k_prep_bwd<V, LOG>), dim3((Lp + 255) / 256), dim3(256), 0, s, T, Lp, cb, sigb, facb, gaugeT);
+void launch_prep_bwd(int T, int Lp, const double* cb, double* sigb, V* facb, const double* gaugeT, double* lvlT,
+                     uint32_t* slotsE, int nslot, hipStream_t s) {
+  hipLaunchKernelGGL((k_prep_bwd<V, LOG>), dim3((Lp + 3) / 4), dim3(256), 0, s, T, Lp, cb, sigb, facb, gaugeT, lvlT,
+                     slotsE, nslot);
 }
 template <typename V, bool LOG>
-void launch_prep_fwd(int T, int Lp, int mode, const double* cf, const double* cb, double* sigf, const double* sigb,
-                     V* facf, V* wgt, double* gauge0, double* gaugeT, hipStream_t s) {
-  hipLaunchKernelGGL((k_prep_fwd<V, LOG>), dim3((Lp + 255) / 256), dim3(256), 0, s, T, Lp, mode, cf, cb, sigf,
-                     sigb, facf, wgt, gauge0, gaugeT);
+void launch_prep_fwd(int T, int Lp, int mode, const double* cf, double* sigf, const double* sigb, V* facf, V* wgt,
+                     double* gauge0, double* gaugeT, double* lvl0, uint32_t* slotsS, int nslot, hipStream_t s) {
+  hipLaunchKernelGGL((k_prep_fwd<V, LOG>), dim3((Lp + 3) / 4), dim3(256), 0, s, T, Lp, mode, cf, sigf, sigb, facf,
+                     wgt, gauge0, gaugeT, lvl0, slotsS, nslot);
 }
-void launch_consume(uint32_t* slots, double* c, int T1, int Lp, int nslot, hipStream_t s) {
+void launch_growth(double* c, const float* lev, int T, int Lp, int dir, hipStream_t s) {
+  const int tot = (T + 1) * Lp;
+  hipLaunchKernelGGL(k_growth, dim3((tot + 255) / 256), dim3(256), 0, s, c, lev, T, Lp, dir);
+}
+void launch_levels(uint32_t* slots, float* lev, int T1, int Lp, int nslot, hipStream_t s) {
   const int tot = T1 * Lp;
-  hipLaunchKernelGGL(k_consume, dim3((tot + 255) / 256), dim3(256), 0, s, slots, c, T1, Lp, nslot);
+  hipLaunchKernelGGL(k_levels, dim3((tot + 255) / 256), dim3(256), 0, s, slots, lev, T1, Lp, nslot);
 }
 void launch_reduce_stats(const double* part, int nblk, int T1, double* tpart, double eps, double* out,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_stats1, dim3(T1), dim3(kBlock), 0, s, part, nblk, tpart);
   hipLaunchKernelGGL(k_reduce_stats2, dim3(1), dim3(64), 0, s, tpart, T1, eps, out);
 }
-void launch_reduce_cost(const double* part, int nblk, int T, double* tpart, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, part, nblk, tpart);
-  hipLaunchKernelGGL(k_reduce_cost, dim3(1), dim3(64), 0, s, tpart, T, out);
+void launch_reduce_cost(const double* pflow, const double* pstate, int nblk, int T, double* tflow, double* tstate,
+                        double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, pflow, nblk, tflow);
+  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, pstate, nblk, tstate);
+  hipLaunchKernelGGL(k_reduce_cost, dim3(1), dim3(64), 0, s, tflow, tstate, T, out);
 }
 
 #define MMOT_INST(V, LOG)                                                                                         \
   template void launch_step<V, LOG>(const StepArgs<V>&, int, int, hipStream_t);                                       \
-  template void launch_source<V, LOG>(int, int, int, int, const V*, const V*, const V*, V*, uint32_t*, int,      \
-                                      size_t, int*, int, hipStream_t);                                            \
+  template void launch_source<V, LOG>(int, int, int, int, const V*, const V*, V*, uint32_t*, int, size_t, int*,   \
+                                      int, hipStream_t);                                                          \
   template void launch_check0<V, LOG>(int, int, int, int, int, const V*, const V*, const V*, const double*,      \
                                       const double*, double*, double*, double*, int, hipStream_t);               \
   template void launch_flows<V, LOG>(int, int, int, int, int, const int*, const int*, const V*, const double*,   \
                                      const V*, const V*, const V*, const V*, const double*, const double*,       \
                                      double*, double*, int, hipStream_t);                                        \
-  template void launch_prep_bwd<V, LOG>(int, int, const double*, double*, V*, const double*, hipStream_t);       \
-  template void launch_prep_fwd<V, LOG>(int, int, int, const double*, const double*, double*, const double*, V*, \
-                                        V*, double*, double*, hipStream_t);
+  template void launch_prep_bwd<V, LOG>(int, int, const double*, double*, V*, const double*, double*, uint32_t*,  \
+                                        int, hipStream_t);                                                       \
+  template void launch_prep_fwd<V, LOG>(int, int, int, const double*, double*, const double*, V*, V*, double*,    \
+                                        double*, double*, uint32_t*, int, hipStream_t);
 MMOT_INST(float, false)
 MMOT_INST(float, true)
 MMOT_INST(double, false)
