@@ -18,7 +18,7 @@
  *   All array arguments are DEVICE pointers owned by the caller unless the
  *   parameter name ends in _host.  Matrices in the paper's L x n orientation
  *   are row-major with the commodity index slowest ("l * n + i").
- *   The library never allocates device memory: every buffer it keeps lives in
+ *   A solver never allocates device memory: every buffer it keeps lives in
  *   the caller-provided workspace (size from mmot_query_workspace).  All work
  *   is enqueued on the stream given to mmot_create (a hipStream_t passed as
  *   void*, NULL = default stream); calls that return host data synchronise it.
@@ -153,8 +153,10 @@ mmot_status mmot_occupancy(mmot_solver* s, double* occ, double* per_comm);
 
 /* Aggregate edge flows (bi-marginal projections P_{t,t+1} summed over
  * commodities, eq. proj_discrete_bi): flow[t * nnz + e] = mass moving along
- * CSR entry e between times t and t+1, t = 0..T-1 (CSR problems only).
- * cost_host (nullable): transport cost <C, M> (synchronises).  */
+ * CSR entry e between times t and t+1, t = 0..T-1.  CSR problems only
+ * (EUNSUPPORTED for dense ones).  cost_host (nullable): transport cost
+ * <C, M> = move costs + interior state costs (eq. cost_multicommodity);
+ * synchronises. */
 mmot_status mmot_edge_flows(mmot_solver* s, double* flow, double* cost_host);
 
 /* Natural-log dual scalings of the current iterate: log_src, log_dst (L x n,
@@ -172,6 +174,12 @@ void mmot_destroy(mmot_solver* s);
 
 const char* mmot_status_str(mmot_status st);
 
+/* Dense solvers created with MMOT_BF16: switch the K-products between BF16
+ * MFMA (MMOT_BF16) and FP32 MFMA (MMOT_FP32, the polish precision) for the
+ * following iterations.  Other solvers accept only their own precision.
+ * EUNSUPPORTED otherwise. */
+mmot_status mmot_set_precision(mmot_solver* s, int32_t precision);
+
 /* Iterations completed so far. */
 int64_t mmot_iterations(const mmot_solver* s);
 
@@ -182,6 +190,51 @@ int64_t mmot_iterations(const mmot_solver* s);
  * panels are left needing a fresh backward sweep (done automatically by the
  * next call that needs them).  Synchronous. */
 mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double* avg_ms_host);
+
+/* ---------------------------------------------------------------------------
+ * Serving pool: continuous batching of many solves on one GPU.
+ *
+ * Each admitted request is a solver (FP32, CSR) whose scalings and messages
+ * stay resident in its own caller-provided workspace.  mmot_pool_run advances
+ * all running requests together: one launch ("tick") executes the next kernel
+ * of every running request's schedule, so small solves share the GPU.  A
+ * request's schedule is exactly the one mmot_solve would run (check_every
+ * iterations, then a convergence check, until converged or max_iter), so its
+ * result is bitwise the same alone, in any mix, and as a plain solver.
+ * Admission is by HBM footprint: the sum of admitted workspace sizes never
+ * exceeds the budget.  All work goes to the pool's stream; the pool keeps
+ * small pinned/device staging buffers for its per-tick work lists.
+ * ------------------------------------------------------------------------- */
+typedef struct mmot_pool mmot_pool;
+
+/* hbm_budget: bytes of workspace the pool may have admitted at once. */
+mmot_status mmot_pool_create(size_t hbm_budget, void* stream, mmot_pool** out);
+
+/* Admit one request: validates and sets up a solver in ws (>= the queried
+ * workspace size; the caller keeps it alive until mmot_pool_release) and
+ * schedules it.  EAGAIN when admitting it would exceed the budget (nothing is
+ * done; retry after a release); EUNSUPPORTED unless CSR and MMOT_FP32.
+ * *ticket identifies the request.  Synchronises the pool stream. */
+mmot_status mmot_pool_submit(mmot_pool* pool, const mmot_problem* prob, const mmot_options* opt, void* ws,
+                             size_t ws_bytes, int32_t max_iter, uint64_t* ticket);
+
+/* Run up to max_ticks batched launches (returns early when nothing is
+ * running); *n_running (nullable) receives the number of unfinished requests. */
+mmot_status mmot_pool_run(mmot_pool* pool, int32_t max_ticks, int32_t* n_running);
+
+/* State of a request: *state = 0 running, 1 converged or max_iter reached,
+ * 2 failed (the call then returns the failure status).  *stats (nullable):
+ * statistics of its latest check. */
+mmot_status mmot_pool_poll(mmot_pool* pool, uint64_t ticket, int32_t* state, mmot_stats* stats);
+
+/* The solver of a request (for mmot_occupancy / mmot_edge_flows /
+ * mmot_get_log_duals on finished requests); NULL for an unknown ticket. */
+mmot_solver* mmot_pool_solver(mmot_pool* pool, uint64_t ticket);
+
+/* Free a finished request's slot and budget (EAGAIN while it is running). */
+mmot_status mmot_pool_release(mmot_pool* pool, uint64_t ticket);
+
+void mmot_pool_destroy(mmot_pool* pool);
 
 #ifdef __cplusplus
 }

@@ -72,6 +72,17 @@ _SIGS = {
     "mmot_destroy": (None, [ctypes.c_void_p]),
     "mmot_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "mmot_iterations": (ctypes.c_int64, [ctypes.c_void_p]),
+    "mmot_pool_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "mmot_pool_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
+    "mmot_pool_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]),
+    "mmot_pool_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32),
+                                      ctypes.POINTER(Stats)]),
+    "mmot_pool_solver": (ctypes.c_void_p, [ctypes.c_void_p, ctypes.c_uint64]),
+    "mmot_pool_release": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    "mmot_pool_destroy": (None, [ctypes.c_void_p]),
+    "mmot_set_precision": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "mmot_time_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)]),
 }
 

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmmot.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["api.hip", "setup.hip", "sweep_sparse.hip"]
+SOURCES = ["api.hip", "setup.hip", "sweep_sparse.hip", "dense_mfma.hip"]
 ARCH = "gfx950"
 
 

@@ -6,8 +6,10 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <new>
+#include <vector>
 
 namespace mmot {
 // setup.hip
@@ -51,6 +53,53 @@ void launch_growth(double*, const float*, int, int, int, hipStream_t);
 void launch_levels(uint32_t*, float*, int, int, int, hipStream_t);
 void launch_reduce_stats(const double*, int, int, double*, double, double*, hipStream_t);
 void launch_reduce_cost(const double*, const double*, int, int, double*, double*, double*, hipStream_t);
+// dense_mfma.hip
+struct GemmArgs {
+  int n, Lp, L, lda;
+  const void* A;
+  const float* B;
+  const float* u;
+  const float* fac;
+  float* out;
+  const float* kl;
+  int cap;
+  const float* wpan;
+  const float* wgt;
+  float* part_s;
+  const float* ucur;
+  double* pcomm;
+  uint32_t* slots;
+  int nslot;
+  size_t slot_stride;
+};
+void launch_gemm(const GemmArgs&, bool, hipStream_t);
+int gemm_col_tiles(int);
+void launch_dense_rows(int, int, const float*, const float*, float*, int, double*, double*, int, hipStream_t);
+void launch_dense_sink(int, int, int, const float*, const float*, float*, int, const double*, const double*,
+                       uint32_t*, int, uint32_t*, size_t, int*, double*, double*, double*, int, hipStream_t);
+void launch_dense_gibbs(const double*, int, int, double, float*, float*, void*, void*, hipStream_t);
+void launch_dense_rowsum_max(const float*, int, int, uint32_t*, hipStream_t);
+void launch_pool_tick(const PoolItem*, const int*, int, int, hipStream_t);
+
+// ---- recording of kernel launches into serving-pool work items ----
+struct Recorder {
+  std::vector<PoolItem> items;
+  bool ok = true;
+};
+thread_local Recorder* tl_recorder = nullptr;
+bool record_item(int kind, int log_domain, int nblk, const void* args, size_t bytes) {
+  Recorder* r = tl_recorder;
+  if (!r) return false;
+  if (bytes > (size_t)kItemArgBytes) { r->ok = false; return true; }
+  PoolItem it;
+  std::memset(&it, 0, sizeof(it));
+  it.kind = kind;
+  it.log_domain = log_domain;
+  it.nblk = nblk;
+  std::memcpy(it.args, args, bytes);
+  r->items.push_back(it);
+  return true;
+}
 }  // namespace mmot
 
 using namespace mmot;
@@ -100,6 +149,13 @@ struct mmot_solver {
   double *exc_row = nullptr, *exc = nullptr;
   int* exc_cnt = nullptr;
   int* flags = nullptr;
+  // dense operators: K and K^T row-major with leading dimension lda (FP32, and
+  // BF16 copies when the solver was created with MMOT_BF16); products in BF16
+  // while dense_bf16, FP32 otherwise (polish)
+  int lda = 0, ntn = 0;
+  bool dense_bf16 = false, has_bf16 = false;
+  float *Kd = nullptr, *Ktd = nullptr, *part_s = nullptr;
+  void *Kb = nullptr, *Ktb = nullptr;
   // ELL copies of the operators (row width ellD, 0 = use CSR)
   int ellD = 0;
   int *ell_ci_b = nullptr, *ell_ci_f = nullptr, *deg_b = nullptr, *deg_f = nullptr, *maxdeg = nullptr;
@@ -135,10 +191,15 @@ void set_geometry(mmot_solver* s) {
   nblk = (nblk + 7) / 8 * 8;
   s->nblk = nblk;
   s->nslot = std::max(1, std::min(32, nblk / 16));
+  if (s->kind == MMOT_DENSE) {
+    s->lda = (s->n + 7) / 8 * 8;
+    s->ntn = gemm_col_tiles(s->Lp);
+  }
 }
 
 void carve(mmot_solver* s, Carver& c) {
-  const size_t n = s->n, Lp = s->Lp, T = s->T, nnz = (size_t)s->nnz, vs = s->vsize;
+  const bool dense = s->kind == MMOT_DENSE;
+  const size_t n = s->n, Lp = s->Lp, T = s->T, nnz = dense ? 1 : (size_t)s->nnz, vs = s->vsize;
   const size_t Tm1 = T > 1 ? T - 1 : 0;
   auto takev = [&](size_t cnt) { return static_cast<void*>(c.take<char>(cnt * vs)); };
   s->rp_b = c.take<int>(n + 1);
@@ -188,10 +249,19 @@ void carve(mmot_solver* s, Carver& c) {
   s->exc_cnt = c.take<int>(n);
   s->exc = c.take<double>(1);
   s->flags = c.take<int>(4);
-  s->ell_ci_b = c.take<int>(n * kEllMax);
-  s->ell_ci_f = c.take<int>(n * kEllMax);
-  s->ell_kv_b = takev(n * kEllMax);
-  s->ell_kv_f = takev(n * kEllMax);
+  const size_t ell = dense ? 1 : n * kEllMax;
+  s->ell_ci_b = c.take<int>(ell);
+  s->ell_ci_f = c.take<int>(ell);
+  s->ell_kv_b = takev(ell);
+  s->ell_kv_f = takev(ell);
+  if (dense) {
+    const size_t nn = n * (size_t)s->lda;
+    s->Kd = c.take<float>(nn);
+    s->Ktd = c.take<float>(nn);
+    s->Kb = s->has_bf16 ? static_cast<void*>(c.take<uint16_t>(nn)) : nullptr;
+    s->Ktb = s->has_bf16 ? static_cast<void*>(c.take<uint16_t>(nn)) : nullptr;
+    s->part_s = c.take<float>((size_t)s->ntn * n);
+  }
   s->deg_b = c.take<int>(n);
   s->deg_f = c.take<int>(n);
   s->maxdeg = c.take<int>(2);
@@ -202,9 +272,15 @@ mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
   if (p->n < 1 || p->L < 1 || p->T < 1) return MMOT_EINVAL;
   if (!(p->eps > 0) || !std::isfinite(p->eps)) return MMOT_EINVAL;
   if (p->kind != MMOT_CSR && p->kind != MMOT_DENSE) return MMOT_EINVAL;
-  if (p->kind == MMOT_DENSE) return MMOT_EUNSUPPORTED;
-  if (p->nnz < 1 || p->nnz > (1LL << 31) - 1) return MMOT_EINVAL;
-  if (o->precision != MMOT_FP32 && o->precision != MMOT_FP64) return MMOT_EUNSUPPORTED;
+  if (p->kind == MMOT_DENSE) {
+    // dense products run on MFMA in the scaled domain, FP32 or BF16 (+ FP32 polish)
+    if (o->precision != MMOT_FP32 && o->precision != MMOT_BF16) return MMOT_EUNSUPPORTED;
+    if (o->domain == MMOT_DOMAIN_LOG) return MMOT_EUNSUPPORTED;
+    if ((size_t)p->n * (size_t)p->n > ((size_t)1 << 31)) return MMOT_EINVAL;
+  } else {
+    if (p->nnz < 1 || p->nnz > (1LL << 31) - 1) return MMOT_EINVAL;
+    if (o->precision != MMOT_FP32 && o->precision != MMOT_FP64) return MMOT_EUNSUPPORTED;
+  }
   if (o->domain < MMOT_DOMAIN_AUTO || o->domain > MMOT_DOMAIN_LOG) return MMOT_EINVAL;
   if ((size_t)p->n * (size_t)p->L > (size_t)1 << 33) return MMOT_EINVAL;
   return MMOT_OK;
@@ -237,6 +313,65 @@ struct Impl {
     return a;
   }
 
+  static GemmArgs gemm_base(mmot_solver* s, bool forward_op) {
+    GemmArgs g;
+    std::memset(&g, 0, sizeof(g));
+    g.n = s->n; g.Lp = s->Lp; g.L = s->L; g.lda = s->lda;
+    if (s->dense_bf16) g.A = forward_op ? s->Ktb : s->Kb;
+    else g.A = forward_op ? static_cast<const void*>(s->Ktd) : static_cast<const void*>(s->Kd);
+    g.nslot = s->nslot;
+    return g;
+  }
+  // dense backward product t+1 -> t
+  static void dense_bwd(mmot_solver* s, int t, bool calib, hipStream_t st) {
+    GemmArgs g = gemm_base(s, false);
+    g.B = reinterpret_cast<const float*>((t + 1 == s->T) ? s->U0T : static_cast<void*>(psi(s, t + 1)));
+    g.u = reinterpret_cast<const float*>(uat(s, t + 1));
+    g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
+    g.out = reinterpret_cast<float*>(psi(s, t));
+    g.kl = (s->has_kl && t >= 1) ? static_cast<const float*>(s->KL) : nullptr;
+    g.slots = calib ? s->slots_b + (size_t)t * s->Lp : nullptr;
+    g.slot_stride = (size_t)(s->T + 1) * s->Lp;
+    launch_gemm(g, s->dense_bf16, st);
+  }
+  // dense forward product t -> t+1 with its epilogue kernels
+  static void dense_fwd(mmot_solver* s, int t, int mode, bool calib, double* occ, double* pcomm, hipStream_t st) {
+    const int T = s->T, to = t + 1;
+    const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
+    GemmArgs g = gemm_base(s, true);
+    g.B = reinterpret_cast<const float*>((t == 0) ? s->U01 : static_cast<void*>(zh(s, t)));
+    g.u = reinterpret_cast<const float*>(uat(s, t));
+    g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facf) + (size_t)to * Lp);
+    g.out = reinterpret_cast<float*>(zh(s, to));
+    g.slot_stride = (size_t)(T + 1) * Lp;
+    if (to < T) {
+      g.kl = s->has_kl ? static_cast<const float*>(s->KL) : nullptr;
+      g.cap = 1;
+      g.wpan = reinterpret_cast<const float*>(psi(s, to));
+      g.wgt = reinterpret_cast<const float*>(static_cast<V*>(s->wgt) + (size_t)to * Lp);
+      g.part_s = s->part_s;
+      g.slots = (mode == 0 && calib) ? s->slots_f + (size_t)to * Lp : nullptr;
+      if (mode == 1) {
+        g.ucur = reinterpret_cast<const float*>(uat(s, to));
+        g.pcomm = pcomm ? pcomm + (size_t)to * s->L * s->n : nullptr;
+      }
+      launch_gemm(g, s->dense_bf16, st);
+      launch_dense_rows(s->n, s->ntn, s->part_s, reinterpret_cast<const float*>(static_cast<V*>(s->cap) + (size_t)(to - 1) * s->n),
+                        reinterpret_cast<float*>(uat(s, to)), mode == 0 ? 1 : 0,
+                        mode == 1 ? s->part + (size_t)to * pstride : nullptr,
+                        (mode == 1 && occ) ? occ + (size_t)to * s->n : nullptr, s->nblk, st);
+    } else {
+      launch_gemm(g, s->dense_bf16, st);   // hatPsi_T into the rolling buffer
+      launch_dense_sink(s->n, s->Lp, s->L, g.out, reinterpret_cast<const float*>(s->R0T),
+                        reinterpret_cast<float*>(s->U0T), mode == 0 ? 1 : 0, s->sigb + (size_t)T * Lp,
+                        s->sigf + (size_t)T * Lp, s->slotsE, s->nslot,
+                        (mode == 0 && calib) ? s->slots_f + (size_t)T * Lp : nullptr, (size_t)(T + 1) * Lp, s->flags,
+                        mode == 1 ? s->part + (size_t)T * pstride : nullptr,
+                        (mode == 1 && occ) ? occ + (size_t)T * s->n : nullptr,
+                        (mode == 1 && pcomm) ? pcomm + (size_t)T * s->L * s->n : nullptr, s->nblk, st);
+    }
+  }
+
   static StepArgs<V> bwd_args(mmot_solver* s, int t, bool calib) {
     const int T = s->T;
     StepArgs<V> a = base_args(s);
@@ -260,7 +395,10 @@ struct Impl {
     }
     launch_prep_bwd<V, LOG>(T, s->Lp, s->cb, s->sigb, static_cast<V*>(s->facb), s->gaugeT, s->lvlT, s->slotsE,
                             s->nslot, st);
-    for (int t = T - 1; t >= 0; --t) launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk, st);
+    for (int t = T - 1; t >= 0; --t) {
+      if (s->kind == MMOT_DENSE) dense_bwd(s, t, calib, st);
+      else launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk, st);
+    }
   }
 
   // forward product t -> t+1; mode 0 Sinkhorn update, mode 1 update-free pass
@@ -327,8 +465,10 @@ struct Impl {
       launch_check0<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->U01),
                             static_cast<const V*>(s->R01), s->sigf, s->sigb, s->part, occ, pcomm, s->nblk, st);
     }
-    for (int t = 0; t < T; ++t)
-      launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), mode == 0 ? 1 : 2, s->nblk, st);
+    for (int t = 0; t < T; ++t) {
+      if (s->kind == MMOT_DENSE) dense_fwd(s, t, mode, calib, occ, pcomm, st);
+      else launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), mode == 0 ? 1 : 2, s->nblk, st);
+    }
   }
 
   // time `reps` launches of one sweep step at the middle time, as launched in
@@ -340,8 +480,25 @@ struct Impl {
     HIPCK(hipEventCreate(&e1));
     StepArgs<V> a = fwd ? fwd_args(s, t, 0, false, nullptr, nullptr) : bwd_args(s, t, false);
     if (fwd && a.epi == 1) a.uout = reinterpret_cast<V*>(s->exc_row);
+    GemmArgs g{};
+    if (s->kind == MMOT_DENSE) {
+      g = gemm_base(s, fwd != 0);
+      g.B = reinterpret_cast<const float*>(psi(s, t + 1));
+      g.u = reinterpret_cast<const float*>(uat(s, t + 1));
+      g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
+      g.out = reinterpret_cast<float*>(zh(s, 0));
+      if (fwd) {   // forward product with the capacity partial sums, as in the sweep
+        g.cap = 1;
+        g.wpan = reinterpret_cast<const float*>(psi(s, t));
+        g.wgt = reinterpret_cast<const float*>(s->wgt);
+        g.part_s = s->part_s;
+      }
+    }
     HIPCK(hipEventRecord(e0, s->stream));
-    for (int r = 0; r < reps; ++r) launch_step<V, LOG>(a, fwd, s->nblk, s->stream);
+    for (int r = 0; r < reps; ++r) {
+      if (s->kind == MMOT_DENSE) launch_gemm(g, s->dense_bf16, s->stream);
+      else launch_step<V, LOG>(a, fwd, s->nblk, s->stream);
+    }
     HIPCK(hipEventRecord(e1, s->stream));
     HIPCK(hipEventSynchronize(e1));
     float ms = 0;
@@ -379,40 +536,49 @@ struct Impl {
     launch_validate_vals(p->src, n * L, 0, 0, 0, s->flags, st);
     launch_validate_vals(p->dst, n * L, 0, 0, 0, s->flags, st);
     launch_validate_vals(p->cap, p->cap_per_step ? Tm1 * n : n, 1, 1, 0, s->flags, st);
-    launch_validate_vals(p->cost, nnz, 0, 0, 1, s->flags, st);
+    const bool dense = s->kind == MMOT_DENSE;
+    if (!dense) launch_validate_vals(p->cost, nnz, 0, 0, 1, s->flags, st);
+    else launch_validate_vals(p->cost_dense, n * n, 1, 0, 1, s->flags, st);
     if (p->state_cost) launch_validate_vals(p->state_cost, n * L, 0, 0, 1, s->flags, st);
-    launch_validate_csr(p->rowptr, p->colidx, s->n, s->nnz, s->flags, st);
+    if (!dense) launch_validate_csr(p->rowptr, p->colidx, s->n, s->nnz, s->flags, st);
     launch_validate_mass(p->src, p->dst, s->L, s->n, s->flags, s->masses, st);
     HIPCK(hipMemcpyAsync(s->host_flags, s->flags, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCK(hipStreamSynchronize(st));
     if (*s->host_flags) return MMOT_EINVAL;
-    // operators: backward = rows of K (input order), forward = rows of K^T
-    HIPCK(hipMemcpyAsync(s->rp_b, p->rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, st));
-    HIPCK(hipMemcpyAsync(s->ci_b, p->colidx, nnz * sizeof(int), hipMemcpyDeviceToDevice, st));
-    HIPCK(hipMemcpyAsync(s->cost, p->cost, nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
-    launch_gibbs<V, LOG>(s->cost, nnz, s->eps, static_cast<V*>(s->kv_b), st);
-    launch_transpose_pattern(s->rp_b, s->ci_b, s->n, s->nnz, s->cnt, s->rp_f, s->cursor, s->ci_f, s->srcpos, st);
-    launch_gather_vals<V>(static_cast<const V*>(s->kv_b), s->srcpos, s->nnz, static_cast<V*>(s->kv_f), st);
-    launch_fill<int>(s->maxdeg, 2, 0, st);
-    launch_max_degree(s->rp_b, s->n, s->maxdeg, st);
-    launch_max_degree(s->rp_f, s->n, s->maxdeg + 1, st);
-    HIPCK(hipMemcpyAsync(s->host_flags, s->maxdeg, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCK(hipStreamSynchronize(st));
-    {
-      const int D = std::max(s->host_flags[0], s->host_flags[1]);
-      const int Dp = (D + kEllQuant - 1) / kEllQuant * kEllQuant;
-      s->ellD = (Dp >= kEllQuant && Dp <= kEllMax) ? Dp : 0;
-    }
-    if (s->ellD) {
-      const V pad = LOG ? -static_cast<V>(INFINITY) : V(0);
-      launch_build_ell<V>(s->rp_b, s->ci_b, static_cast<const V*>(s->kv_b), s->n, s->ellD, pad, s->ell_ci_b,
-                          static_cast<V*>(s->ell_kv_b), s->deg_b, st);
-      launch_build_ell<V>(s->rp_f, s->ci_f, static_cast<const V*>(s->kv_f), s->n, s->ellD, pad, s->ell_ci_f,
-                          static_cast<V*>(s->ell_kv_f), s->deg_f, st);
-    }
     launch_fill<uint32_t>(s->rho, 2, 0u, st);
-    launch_rowsum_max<V, LOG>(s->rp_b, static_cast<const V*>(s->kv_b), s->n, 0.0, s->rho, st);
-    launch_rowsum_max<V, LOG>(s->rp_f, static_cast<const V*>(s->kv_f), s->n, 0.0, s->rho + 1, st);
+    if (dense) {
+      // K = exp(-C/eps) (+inf -> 0) and K^T, FP32 and optionally BF16
+      launch_dense_gibbs(p->cost_dense, s->n, s->lda, s->eps, s->Kd, s->Ktd, s->Kb, s->Ktb, st);
+      launch_dense_rowsum_max(s->Kd, s->n, s->lda, s->rho, st);
+      launch_dense_rowsum_max(s->Ktd, s->n, s->lda, s->rho + 1, st);
+    } else {
+      // operators: backward = rows of K (input order), forward = rows of K^T
+      HIPCK(hipMemcpyAsync(s->rp_b, p->rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, st));
+      HIPCK(hipMemcpyAsync(s->ci_b, p->colidx, nnz * sizeof(int), hipMemcpyDeviceToDevice, st));
+      HIPCK(hipMemcpyAsync(s->cost, p->cost, nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+      launch_gibbs<V, LOG>(s->cost, nnz, s->eps, static_cast<V*>(s->kv_b), st);
+      launch_transpose_pattern(s->rp_b, s->ci_b, s->n, s->nnz, s->cnt, s->rp_f, s->cursor, s->ci_f, s->srcpos, st);
+      launch_gather_vals<V>(static_cast<const V*>(s->kv_b), s->srcpos, s->nnz, static_cast<V*>(s->kv_f), st);
+      launch_fill<int>(s->maxdeg, 2, 0, st);
+      launch_max_degree(s->rp_b, s->n, s->maxdeg, st);
+      launch_max_degree(s->rp_f, s->n, s->maxdeg + 1, st);
+      HIPCK(hipMemcpyAsync(s->host_flags, s->maxdeg, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCK(hipStreamSynchronize(st));
+      {
+        const int D = std::max(s->host_flags[0], s->host_flags[1]);
+        const int Dp = (D + kEllQuant - 1) / kEllQuant * kEllQuant;
+        s->ellD = (Dp >= kEllQuant && Dp <= kEllMax) ? Dp : 0;
+      }
+      if (s->ellD) {
+        const V pad = LOG ? -static_cast<V>(INFINITY) : V(0);
+        launch_build_ell<V>(s->rp_b, s->ci_b, static_cast<const V*>(s->kv_b), s->n, s->ellD, pad, s->ell_ci_b,
+                            static_cast<V*>(s->ell_kv_b), s->deg_b, st);
+        launch_build_ell<V>(s->rp_f, s->ci_f, static_cast<const V*>(s->kv_f), s->n, s->ellD, pad, s->ell_ci_f,
+                            static_cast<V*>(s->ell_kv_f), s->deg_f, st);
+      }
+      launch_rowsum_max<V, LOG>(s->rp_b, static_cast<const V*>(s->kv_b), s->n, 0.0, s->rho, st);
+      launch_rowsum_max<V, LOG>(s->rp_f, static_cast<const V*>(s->kv_f), s->n, 0.0, s->rho + 1, st);
+    }
     // panels
     const V zero = LOG ? -static_cast<V>(INFINITY) : V(0);
     const int vmode = LOG ? 1 : 0;
@@ -472,7 +638,7 @@ mmot_status run_iterations(mmot_solver* s, int n_iter) {
                         (s->opt.calib_every > 0 && s->iters % s->opt.calib_every == 0));
     const bool runB = !s->psi_fresh;
     const bool cb = runB && s->pend_b, cf = s->pend_f;
-    const int key = (runB ? 1 : 0) | (cb ? 2 : 0) | (calib ? 4 : 0) | (cf ? 8 : 0);
+    const int key = (runB ? 1 : 0) | (cb ? 2 : 0) | (calib ? 4 : 0) | (cf ? 8 : 0) | (s->dense_bf16 ? 16 : 0);
     if (s->opt.use_graph) {
       auto it = s->graphs.find(key);
       if (it == s->graphs.end()) {
@@ -517,7 +683,7 @@ mmot_status collect_stats(mmot_solver* s, mmot_stats* out) {
   if (out) {
     out->iters = (int32_t)s->iters;
     out->domain = s->dom;
-    out->precision = s->prec;
+    out->precision = s->dense_bf16 ? MMOT_BF16 : s->prec;
     out->dual_obj = s->host_stats[0];
     out->src_resid = s->host_stats[1];
     out->cap_viol = s->host_stats[2];
@@ -565,7 +731,8 @@ mmot_status mmot_query_workspace(const mmot_problem* p, const mmot_options* o, s
   mmot_solver tmp;
   tmp.n = p->n; tmp.L = p->L; tmp.T = p->T; tmp.nnz = p->nnz; tmp.kind = p->kind;
   tmp.has_kl = p->state_cost != nullptr;
-  tmp.prec = o->precision;
+  tmp.prec = (o->precision == MMOT_FP64) ? MMOT_FP64 : MMOT_FP32;
+  tmp.has_bf16 = o->precision == MMOT_BF16;
   set_geometry(&tmp);
   Carver c{nullptr};
   carve(&tmp, c);
@@ -579,7 +746,9 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
   *out = nullptr;
   mmot_status st = basic_checks(p, o);
   if (st != MMOT_OK) return st;
-  if (!p->rowptr || !p->colidx || !p->cost || !p->cap || !p->src || !p->dst) return MMOT_EINVAL;
+  if (!p->cap || !p->src || !p->dst) return MMOT_EINVAL;
+  if (p->kind == MMOT_CSR && (!p->rowptr || !p->colidx || !p->cost)) return MMOT_EINVAL;
+  if (p->kind == MMOT_DENSE && !p->cost_dense) return MMOT_EINVAL;
   size_t need = 0;
   st = mmot_query_workspace(p, o, &need);
   if (st != MMOT_OK) return st;
@@ -591,7 +760,8 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
   s->opt = *o;
   if (s->opt.check_every < 1) s->opt.check_every = 10;
   if (!(s->opt.tol > 0)) s->opt.tol = 1e-6;
-  s->prec = o->precision;
+  s->prec = (o->precision == MMOT_FP64) ? MMOT_FP64 : MMOT_FP32;
+  s->has_bf16 = s->dense_bf16 = o->precision == MMOT_BF16;
   s->stream = static_cast<hipStream_t>(stream);
   set_geometry(s);
   uintptr_t b = reinterpret_cast<uintptr_t>(ws);
@@ -603,7 +773,9 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
   if (hipHostMalloc(reinterpret_cast<void**>(&s->host_flags), 4 * sizeof(int), 0) != hipSuccess) return fail(MMOT_EHIP);
   if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MMOT_EHIP);
   // domain: an estimate of the within-message dynamic range R = T * mean excess move cost / eps (log2 units)
-  if (o->domain == MMOT_DOMAIN_AUTO) {
+  if (o->domain == MMOT_DOMAIN_AUTO && p->kind == MMOT_DENSE) {
+    s->dom = MMOT_DOMAIN_SCALED;
+  } else if (o->domain == MMOT_DOMAIN_AUTO) {
     launch_excess(p->rowptr, p->colidx, p->cost, p->n, s->exc_row, s->exc_cnt, s->exc, s->stream);
     double h = 0;
     if (hipMemcpyAsync(&s->host_stats[8], s->exc, sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
@@ -648,8 +820,27 @@ mmot_status mmot_solve(mmot_solver* s, int32_t max_iter, mmot_stats* stats) {
     if (local.converged) break;
   }
   if (done == 0) st = mmot_stats_now(s, &local);
+  if (st == MMOT_OK && s->dense_bf16 && s->opt.polish_iters > 0) {
+    // BF16 products converge to a slightly perturbed fixed point; finish in FP32
+    s->dense_bf16 = false;
+    st = mmot_iterate(s, s->opt.polish_iters, &local);
+  }
   if (stats) *stats = local;
   return st;
+}
+
+mmot_status mmot_set_precision(mmot_solver* s, int32_t precision) {
+  if (!s) return MMOT_EINVAL;
+  if (s->kind != MMOT_DENSE) return (precision == (s->prec == MMOT_FP64 ? MMOT_FP64 : MMOT_FP32)) ? MMOT_OK : MMOT_EUNSUPPORTED;
+  if (precision == MMOT_BF16) {
+    if (!s->has_bf16) return MMOT_EUNSUPPORTED;
+    s->dense_bf16 = true;
+  } else if (precision == MMOT_FP32) {
+    s->dense_bf16 = false;
+  } else {
+    return MMOT_EUNSUPPORTED;
+  }
+  return MMOT_OK;
 }
 
 mmot_status mmot_occupancy(mmot_solver* s, double* occ, double* per_comm) {
@@ -743,6 +934,258 @@ const char* mmot_status_str(mmot_status st) {
 }
 
 int64_t mmot_iterations(const mmot_solver* s) { return s ? s->iters : -1; }
+
+// ---------------------------------------------------------------------------
+// serving pool
+// ---------------------------------------------------------------------------
+struct mmot_pool {
+  size_t budget = 0, used = 0;
+  hipStream_t stream = nullptr;
+  uint64_t next_ticket = 1;
+  struct Req {
+    uint64_t ticket;
+    mmot_solver* s;
+    size_t bytes;
+    int32_t max_iter;
+    int32_t state = 0;       // 0 running, 1 done, 2 failed
+    int32_t status = MMOT_OK;
+    std::vector<PoolItem> prog;
+    size_t pc = 0;
+    bool awaiting = false;
+    hipEvent_t ev = nullptr;
+    mmot_stats stats{};
+    int iters_planned = 0;
+  };
+  std::map<uint64_t, Req*> reqs;
+  // device item/prefix buffers and pinned staging ring
+  static constexpr int kRing = 4;
+  int cap_items = 0;
+  PoolItem* d_items[kRing] = {nullptr};
+  int* d_prefix[kRing] = {nullptr};
+  PoolItem* h_items[kRing] = {nullptr};
+  int* h_prefix[kRing] = {nullptr};
+  hipEvent_t ring_ev[kRing] = {nullptr};
+  int ring_pos = 0;
+  int64_t ticks = 0;
+};
+
+namespace {
+
+// Record the next chunk of a request's work: the same calls mmot_solve makes
+// (check_every iterations, then the check pass up to its stats reduction).
+void pool_program(mmot_pool::Req* r) {
+  mmot_solver* s = r->s;
+  const int k = std::min(s->opt.check_every, r->max_iter - r->iters_planned);
+  Recorder rec;
+  tl_recorder = &rec;
+  const int saved_graph = s->opt.use_graph;
+  s->opt.use_graph = 0;
+  run_iterations(s, k);
+  ensure_fresh(s);
+  dispatch(s, [&](auto impl) { decltype(impl)::forward(s, 1, false, false, nullptr, nullptr, s->stream); return 0; });
+  launch_reduce_stats(s->part, s->nblk, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
+  s->opt.use_graph = saved_graph;
+  tl_recorder = nullptr;
+  r->iters_planned += k;
+  r->prog = std::move(rec.items);
+  r->pc = 0;
+  r->awaiting = false;
+}
+
+mmot_status pool_grow(mmot_pool* P, int need) {
+  if (need <= P->cap_items) return MMOT_OK;
+  int cap = std::max(64, P->cap_items * 2);
+  while (cap < need) cap *= 2;
+  (void)hipStreamSynchronize(P->stream);
+  for (int i = 0; i < mmot_pool::kRing; ++i) {
+    // the pool's staging buffers are its own host/device bookkeeping, sized to the active set
+    if (P->d_items[i]) (void)hipFree(P->d_items[i]);
+    if (P->d_prefix[i]) (void)hipFree(P->d_prefix[i]);
+    if (P->h_items[i]) (void)hipHostFree(P->h_items[i]);
+    if (P->h_prefix[i]) (void)hipHostFree(P->h_prefix[i]);
+    if (hipMalloc(reinterpret_cast<void**>(&P->d_items[i]), sizeof(PoolItem) * cap) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&P->d_prefix[i]), sizeof(int) * (cap + 1)) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&P->h_items[i]), sizeof(PoolItem) * cap, 0) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&P->h_prefix[i]), sizeof(int) * (cap + 1), 0) != hipSuccess)
+      return MMOT_EHIP;
+  }
+  P->cap_items = cap;
+  return MMOT_OK;
+}
+
+// a request whose program finished: read its stats (event completed)
+void pool_finish_chunk(mmot_pool* P, mmot_pool::Req* r) {
+  mmot_solver* s = r->s;
+  (void)P;
+  mmot_stats& o = r->stats;
+  const int f = *s->host_flags;
+  o.iters = (int32_t)s->iters;
+  o.domain = s->dom;
+  o.precision = s->prec;
+  o.dual_obj = s->host_stats[0];
+  o.src_resid = s->host_stats[1];
+  o.cap_viol = s->host_stats[2];
+  o.mass_drift = s->host_stats[3];
+  o.dual_gap = s->host_stats[4];
+  o.mass = s->host_stats[5];
+  o.converged = (o.src_resid <= s->opt.tol && o.cap_viol <= s->opt.tol) ? 1 : 0;
+  mmot_status st = MMOT_OK;
+  if (f & FLAG_INFEASIBLE) st = MMOT_EINFEASIBLE;
+  else if ((f & FLAG_NONFINITE) || s->host_stats[6] > 0 || !std::isfinite(s->host_stats[0])) st = MMOT_ENUMERIC;
+  if (st != MMOT_OK) { r->state = 2; r->status = st; return; }
+  if (o.converged || r->iters_planned >= r->max_iter) { r->state = 1; return; }
+  pool_program(r);
+}
+
+}  // namespace
+
+mmot_status mmot_pool_create(size_t hbm_budget, void* stream, mmot_pool** out) {
+  if (!out || hbm_budget == 0) return MMOT_EINVAL;
+  mmot_pool* P = new (std::nothrow) mmot_pool();
+  if (!P) return MMOT_ENOMEM;
+  P->budget = hbm_budget;
+  P->stream = static_cast<hipStream_t>(stream);
+  for (int i = 0; i < mmot_pool::kRing; ++i)
+    if (hipEventCreateWithFlags(&P->ring_ev[i], hipEventDisableTiming) != hipSuccess) { mmot_pool_destroy(P); return MMOT_EHIP; }
+  *out = P;
+  return MMOT_OK;
+}
+
+mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_options* opt, void* ws,
+                             size_t ws_bytes, int32_t max_iter, uint64_t* ticket) {
+  if (!P || !prob || !opt || !ticket || max_iter < 1) return MMOT_EINVAL;
+  if (prob->kind != MMOT_CSR || opt->precision != MMOT_FP32) return MMOT_EUNSUPPORTED;
+  size_t need = 0;
+  mmot_status st = mmot_query_workspace(prob, opt, &need);
+  if (st != MMOT_OK) return st;
+  if (P->used + need > P->budget) return MMOT_EAGAIN;
+  mmot_solver* s = nullptr;
+  st = mmot_create(prob, opt, ws, ws_bytes, P->stream, &s);
+  if (st != MMOT_OK) return st;
+  auto* r = new (std::nothrow) mmot_pool::Req();
+  if (!r) { mmot_destroy(s); return MMOT_ENOMEM; }
+  r->ticket = P->next_ticket++;
+  r->s = s;
+  r->bytes = need;
+  r->max_iter = max_iter;
+  if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) { mmot_destroy(s); delete r; return MMOT_EHIP; }
+  pool_program(r);
+  P->used += need;
+  P->reqs[r->ticket] = r;
+  *ticket = r->ticket;
+  return MMOT_OK;
+}
+
+mmot_status mmot_pool_run(mmot_pool* P, int32_t max_ticks, int32_t* n_running) {
+  if (!P || max_ticks < 0) return MMOT_EINVAL;
+  for (int tk = 0; tk < max_ticks; ++tk) {
+    // collect finished chunks (stats copies that have landed)
+    std::vector<mmot_pool::Req*> act;
+    bool waiting = false;
+    for (auto& kv : P->reqs) {
+      mmot_pool::Req* r = kv.second;
+      if (r->state != 0) continue;
+      if (r->awaiting) {
+        if (hipEventQuery(r->ev) == hipSuccess) pool_finish_chunk(P, r);
+        else { waiting = true; continue; }
+        if (r->state != 0) continue;
+      }
+      if (r->pc < r->prog.size()) act.push_back(r);
+    }
+    if (act.empty()) {
+      if (!waiting) break;
+      // only stats copies in flight: wait for the oldest, then continue
+      for (auto& kv : P->reqs)
+        if (kv.second->state == 0 && kv.second->awaiting) { (void)hipEventSynchronize(kv.second->ev); break; }
+      continue;
+    }
+    if (pool_grow(P, (int)act.size()) != MMOT_OK) return MMOT_EHIP;
+    const int slot = P->ring_pos;
+    P->ring_pos = (P->ring_pos + 1) % mmot_pool::kRing;
+    (void)hipEventSynchronize(P->ring_ev[slot]);   // staging buffer free again
+    PoolItem* hi = P->h_items[slot];
+    int* hp = P->h_prefix[slot];
+    int total = 0;
+    for (size_t i = 0; i < act.size(); ++i) {
+      mmot_pool::Req* r = act[i];
+      hi[i] = r->prog[r->pc++];
+      hp[i] = total;
+      total += hi[i].nblk;
+    }
+    hp[act.size()] = total;
+    const int ni = (int)act.size();
+    if (hipMemcpyAsync(P->d_items[slot], hi, sizeof(PoolItem) * ni, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
+        hipMemcpyAsync(P->d_prefix[slot], hp, sizeof(int) * (ni + 1), hipMemcpyHostToDevice, P->stream) != hipSuccess)
+      return MMOT_EHIP;
+    launch_pool_tick(P->d_items[slot], P->d_prefix[slot], ni, total, P->stream);
+    if (hipEventRecord(P->ring_ev[slot], P->stream) != hipSuccess) return MMOT_EHIP;
+    ++P->ticks;
+    // requests whose chunk ended with this tick: copy their stats back asynchronously
+    for (mmot_pool::Req* r : act) {
+      if (r->pc < r->prog.size()) continue;
+      mmot_solver* s = r->s;
+      if (hipMemcpyAsync(s->host_stats, s->stats_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
+          hipMemcpyAsync(s->host_flags, s->flags, sizeof(int), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
+          hipEventRecord(r->ev, P->stream) != hipSuccess)
+        return MMOT_EHIP;
+      r->awaiting = true;
+    }
+  }
+  if (n_running) {
+    int c = 0;
+    for (auto& kv : P->reqs) c += kv.second->state == 0;
+    *n_running = c;
+  }
+  return MMOT_OK;
+}
+
+mmot_status mmot_pool_poll(mmot_pool* P, uint64_t ticket, int32_t* state, mmot_stats* stats) {
+  if (!P || !state) return MMOT_EINVAL;
+  auto it = P->reqs.find(ticket);
+  if (it == P->reqs.end()) return MMOT_EINVAL;
+  *state = it->second->state;
+  if (stats) *stats = it->second->stats;
+  return it->second->state == 2 ? (mmot_status)it->second->status : MMOT_OK;
+}
+
+mmot_solver* mmot_pool_solver(mmot_pool* P, uint64_t ticket) {
+  if (!P) return nullptr;
+  auto it = P->reqs.find(ticket);
+  return it == P->reqs.end() ? nullptr : it->second->s;
+}
+
+mmot_status mmot_pool_release(mmot_pool* P, uint64_t ticket) {
+  if (!P) return MMOT_EINVAL;
+  auto it = P->reqs.find(ticket);
+  if (it == P->reqs.end()) return MMOT_EINVAL;
+  mmot_pool::Req* r = it->second;
+  if (r->state == 0) return MMOT_EAGAIN;
+  (void)hipStreamSynchronize(P->stream);
+  mmot_destroy(r->s);
+  (void)hipEventDestroy(r->ev);
+  P->used -= r->bytes;
+  delete r;
+  P->reqs.erase(it);
+  return MMOT_OK;
+}
+
+void mmot_pool_destroy(mmot_pool* P) {
+  if (!P) return;
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  for (auto& kv : P->reqs) {
+    mmot_destroy(kv.second->s);
+    if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+    delete kv.second;
+  }
+  for (int i = 0; i < mmot_pool::kRing; ++i) {
+    if (P->d_items[i]) (void)hipFree(P->d_items[i]);
+    if (P->d_prefix[i]) (void)hipFree(P->d_prefix[i]);
+    if (P->h_items[i]) (void)hipHostFree(P->h_items[i]);
+    if (P->h_prefix[i]) (void)hipHostFree(P->h_prefix[i]);
+    if (P->ring_ev[i]) (void)hipEventDestroy(P->ring_ev[i]);
+  }
+  delete P;
+}
 
 mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double* avg_ms) {
   if (!s || reps < 1 || !avg_ms) return MMOT_EINVAL;

@@ -1,0 +1,480 @@
+// Dense-graph products of the graph-structured Sinkhorn scheme on MFMA.
+//
+// For a dense K (complete graph with finite costs) each message update of
+// Theorem 5 is a GEMM over all commodities at once:
+//   forward  hatPsi_{t+1}^T = K^T diag(u_t) (hatPsi_t (.) K_L)^T
+//   backward Psi_{t-1}^T    = K   diag(u_t) (Psi_t (.) K_L)^T
+// i.e. OUT[n x Lp] = A[n x n] * diag(u) * B[n x Lp] with A = K^T or K (row
+// major, padded leading dimension lda) and B a state-major panel.  The
+// dense-path cost is O(T L n^2) per sweep (remark after Corollary 1).
+//
+// Tiling for gfx950: 128 x 128 output tile per 256-thread workgroup, four
+// wavefronts in a 2 x 2 arrangement each owning 64 x 64 = 2 x 2 MFMA 32x32
+// tiles, K-depth 64 per LDS stage, two LDS buffers: the global loads of stage
+// k+1 are in flight (in registers) while stage k runs on the matrix cores.  BF16: v_mfma_f32_32x32x16_bf16, A stored
+// in BF16, B converted (and scaled by u) while staged.  FP32:
+// v_mfma_f32_32x32x2_f32, operands kept FP32 (k-interleaved in LDS so each
+// lane reads its 16 k-values with 16-byte loads).  Accumulation is FP32.
+//
+// Epilogue: per-column factor 2^-c (range offsets), K_L, store; for interior
+// forward times the partial capacity column sums over the tile's commodities
+// (sum_l out * Psi * 2^(sigma_hat + sigma)), written per column-tile and summed
+// in a fixed order by k_dense_rows (deterministic); optional column levels.
+#include "mmot_internal.h"
+#include <hip/hip_bf16.h>
+#include <math.h>
+
+namespace mmot {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int GBM = 128, GBN = 128, GBK = 64;
+constexpr int kPadB16 = 8;   // LDS row padding (elements) for bf16 tiles
+constexpr int kPadF32 = 4;
+
+struct GemmArgs {
+  int n, Lp, L, lda;
+  const void* A;        // [n][lda] (bf16 or f32)
+  const float* B;       // panel [n][Lp]
+  const float* u;       // [n] scaling of the B rows, nullptr = 1
+  const float* fac;     // [Lp] output column factor
+  float* out;           // [n][Lp]
+  const float* kl;      // [n][Lp] K_L multiplied into the stored output, nullptr = none
+  int cap;              // 1: capacity partial sums (interior forward time)
+  const float* wpan;    // Psi_{t} panel at the output time
+  const float* wgt;     // [Lp]
+  float* part_s;        // [nTN][n] partial column sums
+  const float* ucur;    // check pass: u at the output time (per-commodity output)
+  double* pcomm;        // check pass: [L][n] per-commodity marginal, nullptr = none
+  uint32_t* slots;      // column levels of the stored output, nullptr = off
+  int nslot;
+  size_t slot_stride;
+};
+
+template <bool BF16>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
+  using TA = typename std::conditional<BF16, __bf16, float>::type;
+  constexpr int PAD = BF16 ? kPadB16 : kPadF32;
+  constexpr int LDK = GBK + PAD;
+  constexpr int AV = BF16 ? 4 : 8;          // 16-byte A chunks per thread per stage
+  __shared__ TA As[2][GBM * LDK];
+  __shared__ TA Bs[2][GBN * LDK];
+  __shared__ float red[2][2][64];   // capacity partial sums across the two column waves
+  __shared__ float cmx[2][GBN];     // column maxima across the two row waves
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  // XCD-aware order: consecutive hardware blocks go to different XCDs; give each
+  // XCD a contiguous range of row tiles (all column tiles of them), so each A
+  // row tile is streamed from HBM/MALL by one XCD and reused from its L2
+  const int nbm = gridDim.x, nbn = gridDim.y;
+  const int hw = blockIdx.y * nbm + blockIdx.x;
+  const int tot = nbm * nbn;
+  int logical = hw;
+  if ((tot & 7) == 0) logical = (hw & 7) * (tot >> 3) + (hw >> 3);
+  const int bn = logical % nbn, bm = logical / nbn;
+  const int row0 = bm * GBM, col0 = bn * GBN;
+  const TA* A = static_cast<const TA*>(a.A);
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  // staged operands of one K-stage, held in registers between the global
+  // loads and the LDS writes (software pipeline: stage k+1 loads overlap
+  // stage k MFMAs)
+  uint4 ra[AV];
+  float rb[32];
+  const int bc = tid & 127, bkh = tid >> 7;   // B: column in tile, k half (32 k each)
+
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int c = tid + v * 256;
+      const int r = BF16 ? (c >> 3) : (c >> 4);
+      const int ch = BF16 ? (c & 7) : (c & 15);
+      const int gr = row0 + r, gk = k0 + ch * (BF16 ? 8 : 4);
+      ra[v] = make_uint4(0, 0, 0, 0);
+      if (gr < a.n && gk < a.lda) ra[v] = *reinterpret_cast<const uint4*>(A + (size_t)gr * a.lda + gk);
+    }
+    const int gc = col0 + bc;
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const int gk = k0 + bkh * 32 + j;
+      float v = 0.f;
+      if (gk < a.n && gc < a.Lp) {
+        v = a.B[(size_t)gk * a.Lp + gc];
+        if (a.u) v *= a.u[gk];
+      }
+      rb[j] = v;
+    }
+  };
+  auto swrite = [&](int buf) {
+    TA* as = As[buf];
+    TA* bs = Bs[buf];
+#pragma unroll
+    for (int v = 0; v < AV; ++v) {
+      const int c = tid + v * 256;
+      if (BF16) {
+        const int r = c >> 3, ch = c & 7;
+        *reinterpret_cast<uint4*>(&as[r * LDK + ch * 8]) = ra[v];
+      } else {
+        // 16 chunks of 4 k per row; k-interleaved: position h*32 + s holds k = 2s + h
+        const int r = c >> 4, ch = c & 15;
+        float* dst = reinterpret_cast<float*>(&as[r * LDK]);
+        dst[0 * 32 + ch * 2 + 0] = __uint_as_float(ra[v].x);
+        dst[1 * 32 + ch * 2 + 0] = __uint_as_float(ra[v].y);
+        dst[0 * 32 + ch * 2 + 1] = __uint_as_float(ra[v].z);
+        dst[1 * 32 + ch * 2 + 1] = __uint_as_float(ra[v].w);
+      }
+    }
+    if (BF16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        bf16x8 p;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) p[j] = (__bf16)rb[q * 8 + j];
+        *reinterpret_cast<bf16x8*>(&bs[bc * LDK + bkh * 32 + q * 8]) = p;
+      }
+    } else {
+      float* dst = reinterpret_cast<float*>(&bs[bc * LDK]);
+#pragma unroll
+      for (int j = 0; j < 32; ++j) dst[(j & 1) * 32 + bkh * 16 + (j >> 1)] = rb[j];
+    }
+  };
+
+  const int nk = (a.n + GBK - 1) / GBK;
+  gload(0);
+  swrite(0);
+  __syncthreads();
+  const int lr = lane & 31, lh = lane >> 5;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * GBK);
+    const TA* as = As[buf];
+    const TA* bs = Bs[buf];
+    if (BF16) {
+#pragma unroll
+      for (int ks = 0; ks < GBK / 16; ++ks) {
+        bf16x8 af[2], bf[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          af[i] = *reinterpret_cast<const bf16x8*>(&as[(wm * 64 + i * 32 + lr) * LDK + ks * 16 + lh * 8]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          bf[j] = *reinterpret_cast<const bf16x8*>(&bs[(wn * 64 + j * 32 + lr) * LDK + ks * 16 + lh * 8]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+      }
+    } else {
+      // FP32: accumulate the stage into fresh registers and add once per stage
+      // (blocked summation keeps the FP32 rounding of long K-sums small)
+      f32x16 sacc[2][2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int r = 0; r < 16; ++r) sacc[i][j][r] = 0.f;
+#pragma unroll
+      for (int s4 = 0; s4 < GBK / 2; s4 += 4) {
+        float4 av[2], bv[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+          av[i] = *reinterpret_cast<const float4*>(
+              reinterpret_cast<const float*>(&as[(wm * 64 + i * 32 + lr) * LDK]) + lh * 32 + s4);
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          bv[j] = *reinterpret_cast<const float4*>(
+              reinterpret_cast<const float*>(&bs[(wn * 64 + j * 32 + lr) * LDK]) + lh * 32 + s4);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const float aq = (q == 0) ? av[i].x : (q == 1) ? av[i].y : (q == 2) ? av[i].z : av[i].w;
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const float bq = (q == 0) ? bv[j].x : (q == 1) ? bv[j].y : (q == 2) ? bv[j].z : bv[j].w;
+              sacc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq, bq, sacc[i][j], 0, 0, 0);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] += sacc[i][j];
+    }
+    if (kt + 1 < nk) swrite(buf ^ 1);
+    __syncthreads();
+  }
+
+  // ---- epilogue ----
+  float colmax[2] = {-INFINITY, -INFINITY};
+  float rsum[2][16];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rsum[i][r] = 0.f;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int gc = col0 + wn * 64 + j * 32 + lr;
+    const bool cok = gc < a.Lp;
+    const float f = cok ? a.fac[gc] : 0.f;
+    const float g = (a.cap && cok) ? a.wgt[gc] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int gr = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        if (!(cok && gr < a.n)) continue;
+        const size_t off = (size_t)gr * a.Lp + gc;
+        const float o = acc[i][j][r] * f;
+        float z = o;
+        if (a.kl) z *= a.kl[off];
+        a.out[off] = z;
+        if (z > 0.f) colmax[j] = fmaxf(colmax[j], z);
+        if (a.cap && gc < a.L) {
+          const float w = a.wpan[off];
+          rsum[i][r] = fmaf(o * w, g, rsum[i][r]);
+          if (a.pcomm) {
+            const double P = (double)o * (double)w * (double)g * (double)a.ucur[gr];
+            a.pcomm[(size_t)gc * a.n + gr] = P;
+          }
+        }
+      }
+    }
+  }
+  if (a.cap) {
+    // reduce over the 32 lanes that share rows (same lane half), then over the two column waves
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float v = rsum[i][r];
+        for (int m = 16; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+        rsum[i][r] = v;
+      }
+    if (lr == 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[wm][wn][i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)] = rsum[i][r];
+    }
+    __syncthreads();
+    if (tid < 128) {
+      const int wmr = tid >> 6, rr = tid & 63;
+      const int gr = row0 + wmr * 64 + rr;
+      if (gr < a.n) a.part_s[(size_t)bn * a.n + gr] = red[wmr][0][rr] + red[wmr][1][rr];
+    }
+  }
+  if (a.slots) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      float m = colmax[j];
+      m = fmaxf(m, __shfl_xor(m, 32, 64));
+      if (lh == 0) cmx[wm][wn * 64 + j * 32 + lr] = m;
+    }
+    __syncthreads();
+    if (tid < GBN) {
+      const float m = fmaxf(cmx[0][tid], cmx[1][tid]);
+      const int gc = col0 + tid;
+      if (gc < a.Lp && m > 0.f)
+        atomicMax(a.slots + (size_t)(logical % a.nslot) * a.slot_stride + gc, enc_f32(log2f(m)));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// row kernels of the dense path
+// ---------------------------------------------------------------------------
+// capacity update (Corollary 1 + Proposition 1) from the column-tile partial
+// sums: s_j = sum_p part_s[p][j]; update: u_j = 1 if s_j <= d_j else d_j / s_j;
+// check: occupancy u_j s_j and the capacity / dual / gap statistics.
+__global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, const float* __restrict__ cap,
+                             float* __restrict__ u, int update, double* part, double* occ) {
+  double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+  for (int j = r0 + threadIdx.x; j < r1; j += blockDim.x) {
+    float s = 0.f;
+    for (int p = 0; p < ntn; ++p) s += part_s[(size_t)p * n + j];
+    const float d = cap[j];
+    if (update) {
+      u[j] = (s <= d) ? 1.f : d / s;
+    } else {
+      const double uu = (double)u[j], occv = uu * (double)s, dd = (double)d, lnu = log(uu);
+      st[ST_MASS] += occv;
+      if (isfinite(dd)) {
+        st[ST_CAP_VIOL] = fmax(st[ST_CAP_VIOL], fmax(occv - dd, 0.0) / dd);
+        st[ST_DUAL] += dd * lnu;
+        st[ST_GAP] += lnu * (occv - dd);
+      }
+      if (!isfinite(occv)) st[ST_NONFINITE] += 1.0;
+      if (occ) occ[j] = occv;
+    }
+  }
+  if (part) {
+    __shared__ double red[256][kNSt];
+#pragma unroll
+    for (int k = 0; k < kNSt; ++k) red[threadIdx.x][k] = st[k];
+    __syncthreads();
+    if (threadIdx.x < kNSt) {
+      const int k = threadIdx.x;
+      double v = red[0][k];
+      for (int i = 1; i < (int)blockDim.x; ++i) v = (k == ST_CAP_VIOL) ? fmax(v, red[i][k]) : v + red[i][k];
+      part[(size_t)blockIdx.x * kNSt + k] = v;
+    }
+  }
+}
+
+// sink update U0T = R0T ./ hatPsi_T (Algorithm 2) from the stored product
+// (update), or the sink statistics P_{0,T} = U0T (.) hatPsi_T (check).  Row
+// blocks as k_dense_rows; each thread owns commodity columns and walks the
+// block's rows, so the column levels of the new U0T (slotsE) and of hatPsi_T
+// (slots_o, calibration) cost one atomic per block and column.
+__global__ void k_dense_sink(int n, int Lp, int L, const float* __restrict__ hat, const float* __restrict__ rdst,
+                             float* __restrict__ u0t, int update, const double* __restrict__ sigT,
+                             const double* __restrict__ sighT, uint32_t* slotsE, int nslot, uint32_t* slots_o,
+                             size_t stride_o, int* flags, double* part, double* occ, double* pcomm) {
+  double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int per = (n + gridDim.x - 1) / gridDim.x;
+  const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
+  for (int l = threadIdx.x; l < Lp; l += blockDim.x) {
+    float cz = -INFINITY, co = -INFINITY;
+    const double sg = (l < L) ? sigT[l] + sighT[l] : 0.0;
+    for (int j = r0; j < r1; ++j) {
+      const size_t off = (size_t)j * Lp + l;
+      const float o = hat[off], r = rdst[off];
+      if (update) {
+        float z = 0.f;
+        if (r > 0.f) {
+          if (!(o > 0.f)) atomicOr(flags, FLAG_INFEASIBLE);
+          z = r / o;
+        }
+        u0t[off] = z;
+        if (z > 0.f) cz = fmaxf(cz, log2f(z));
+        if (o > 0.f) co = fmaxf(co, log2f(o));
+      } else if (l < L) {
+        const float z = u0t[off];
+        const double P = (double)z * (double)o * exp2(sg);
+        const double lnU = (z > 0.f) ? (log2((double)z) + sigT[l]) * M_LN2 : 0.0;
+        st[ST_MASS] += P;
+        st[ST_DUAL] += (double)r * lnU;
+        st[ST_GAP] += lnU * (P - (double)r);
+        if (pcomm) pcomm[(size_t)l * n + j] = P;
+      }
+    }
+    if (update && r1 > r0) {
+      if (cz > -INFINITY) atomicMax(slotsE + (size_t)(blockIdx.x % nslot) * Lp + l, enc_f32(cz));
+      if (slots_o && co > -INFINITY) atomicMax(slots_o + (size_t)(blockIdx.x % nslot) * stride_o + l, enc_f32(co));
+    }
+  }
+  if (!update && occ) {
+    // one wavefront per row, lanes over commodities (fixed order)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = r0 + w; j < r1; j += nw) {
+      double s = 0;
+      for (int l = lane; l < L; l += 64)
+        s += (double)u0t[(size_t)j * Lp + l] * (double)hat[(size_t)j * Lp + l] * exp2(sigT[l] + sighT[l]);
+      for (int m = 32; m > 0; m >>= 1) s += __shfl_xor(s, m, 64);
+      if (lane == 0) occ[j] = s;
+    }
+  }
+  if (part) {
+    __shared__ double red[256][kNSt];
+#pragma unroll
+    for (int k = 0; k < kNSt; ++k) red[threadIdx.x][k] = st[k];
+    __syncthreads();
+    if (threadIdx.x < kNSt) {
+      const int k = threadIdx.x;
+      double v = red[0][k];
+      for (int i = 1; i < (int)blockDim.x; ++i) v = (k == ST_CAP_VIOL) ? fmax(v, red[i][k]) : v + red[i][k];
+      part[(size_t)blockIdx.x * kNSt + k] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// setup: dense K = exp(-C/eps) (+inf -> 0), its transpose, BF16 copies
+// ---------------------------------------------------------------------------
+__global__ void k_dense_gibbs(const double* __restrict__ C, int n, int lda, double eps, float* __restrict__ K,
+                              float* __restrict__ Kt, __bf16* __restrict__ Kb, __bf16* __restrict__ Ktb) {
+  __shared__ float tile[32][33];
+  const int i0 = blockIdx.y * 32, j0 = blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int r = ty; r < 32; r += 8) {
+    const int i = i0 + r, j = j0 + tx;
+    float v = 0.f;
+    if (i < n && j < n) {
+      const double c = C[(size_t)i * n + j];
+      v = isinf(c) ? 0.f : (float)exp(-c / eps);
+    }
+    tile[r][tx] = v;
+    if (i < n && j < lda) {
+      K[(size_t)i * lda + j] = v;
+      if (Kb) Kb[(size_t)i * lda + j] = (__bf16)v;
+    }
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int j = j0 + r, i = i0 + tx;   // Kt[j][i] = K[i][j]
+    if (j < n && i < lda) {
+      const float v = (i < n) ? tile[tx][r] : 0.f;
+      Kt[(size_t)j * lda + i] = v;
+      if (Ktb) Ktb[(size_t)j * lda + i] = (__bf16)v;
+    }
+  }
+}
+
+__global__ void k_dense_rowsum_max(const float* __restrict__ K, int n, int lda, uint32_t* out) {
+  const int i = blockIdx.x;
+  __shared__ double red[256];
+  double s = 0;
+  for (int j = threadIdx.x; j < n; j += blockDim.x) s += (double)K[(size_t)i * lda + j];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] > 0) atomicMax(out, enc_f32((float)log2(red[0])));
+}
+
+// launchers
+void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
+  dim3 grid((a.n + GBM - 1) / GBM, (a.Lp + GBN - 1) / GBN);
+  if (bf16) hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, s, a);
+}
+int gemm_col_tiles(int Lp) { return (Lp + GBN - 1) / GBN; }
+void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, float* u, int update, double* part,
+                       double* occ, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_rows, dim3(nblk), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ);
+}
+void launch_dense_sink(int n, int Lp, int L, const float* hat, const float* rdst, float* u0t, int update,
+                       const double* sigT, const double* sighT, uint32_t* slotsE, int nslot, uint32_t* slots_o,
+                       size_t stride_o, int* flags, double* part, double* occ, double* pcomm, int nblk,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_sink, dim3(nblk), dim3(256), 0, s, n, Lp, L, hat, rdst, u0t, update, sigT, sighT,
+                     slotsE, nslot, slots_o, stride_o, flags, part, occ, pcomm);
+}
+void launch_dense_gibbs(const double* C, int n, int lda, double eps, float* K, float* Kt, void* Kb, void* Ktb,
+                        hipStream_t s) {
+  dim3 grid((lda + 31) / 32, (n + 31) / 32);
+  hipLaunchKernelGGL(k_dense_gibbs, grid, dim3(256), 0, s, C, n, lda, eps, K, Kt, static_cast<__bf16*>(Kb),
+                     static_cast<__bf16*>(Ktb));
+}
+void launch_dense_rowsum_max(const float* K, int n, int lda, uint32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_rowsum_max, dim3(n), dim3(256), 0, s, K, n, lda, out);
+}
+
+}  // namespace mmot

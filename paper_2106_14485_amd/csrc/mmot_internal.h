@@ -75,9 +75,94 @@ struct StepArgs {
   double* pcomm;        // [L][n] per-commodity marginal at the output time, nullptr = none
 };
 
-struct ElemArgs {       // row-wise kernels over one panel time
-  int n, Lp, L, G, nchunk;
+// source update U01 = R01 ./ Psi_1 (row kernel)
+template <typename V>
+struct SourceArgs {
+  int n, Lp, G, nchunk, nslot;
+  const V* psi0;
+  const V* rsrc;
+  V* u01;
+  uint32_t* slots;
+  size_t slot_stride;
+  int* flags;
 };
+// statistics at time 0 (row kernel)
+template <typename V>
+struct Check0Args {
+  int n, Lp, L, G, nchunk;
+  const V* psi0;
+  const V* u01;
+  const V* rsrc;
+  const double* sigf0;
+  const double* sigb0;
+  double* part;
+  double* occ;
+  double* pcomm;
+};
+template <typename V>
+struct PrepBwdArgs {
+  int T, Lp, nslot;
+  const double* cb;
+  double* sigb;
+  V* facb;
+  const double* gaugeT;
+  double* lvlT;
+  uint32_t* slotsE;
+};
+template <typename V>
+struct PrepFwdArgs {
+  int T, Lp, mode, nslot;
+  const double* cf;
+  double* sigf;
+  const double* sigb;
+  V* facf;
+  V* wgt;
+  double* gauge0;
+  double* gaugeT;
+  double* lvl0;
+  uint32_t* slotsS;
+};
+struct LevelsArgs {
+  uint32_t* slots;
+  float* lev;
+  int T1, Lp, nslot;
+};
+struct GrowthArgs {
+  double* c;
+  const float* lev;
+  int T, Lp, dir;
+};
+struct Reduce1Args {
+  const double* part;
+  int nblk;
+  double* tpart;
+};
+struct Reduce2Args {
+  const double* tpart;
+  int T1;
+  double eps;
+  double* out;
+};
+
+// Work items of the serving pool: one recorded kernel launch of one solve.
+// A pool tick runs the next item of every active solve in one launch.
+enum ItemKind {
+  IK_STEP_BWD = 0, IK_STEP_FWD, IK_STEP_CHK, IK_SOURCE, IK_CHECK0, IK_PREP_BWD, IK_PREP_FWD, IK_LEVELS,
+  IK_GROWTH, IK_REDUCE1, IK_REDUCE2, IK_COUNT
+};
+constexpr int kItemArgBytes = 320;
+struct alignas(16) PoolItem {
+  int kind;
+  int log_domain;
+  int nblk;
+  int pad;
+  unsigned char args[kItemArgBytes];
+};
+// Set while a solve's program is being recorded: launchers append items
+// instead of launching (host only).
+struct Recorder;
+extern thread_local Recorder* tl_recorder;
+bool record_item(int kind, int log_domain, int nblk, const void* args, size_t bytes);
 
 // order-preserving float encoding for atomicMax on signed values (0 = empty)
 __device__ __forceinline__ uint32_t enc_f32(float f) {

@@ -126,14 +126,15 @@ __device__ void calib_chunk(const V (&val)[VT<V>::N], int G, int chunk_col0, int
 // the sweep step
 // ---------------------------------------------------------------------------
 template <typename V, bool LOG, bool FWD, bool CHK>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
+__device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nblk) {
+
   constexpr int NV = VT<V>::N;
   constexpr int KB = 16;   // neighbours gathered per batch
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = a.G;
   const int grp = lane / G, gl = lane & (G - 1);
   const int rpw = 64 / G;
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int lb = xcd_block(bid, nblk);
   const int row = (lb * kWaves + wave) * rpw + grp;
   const bool valid = row < a.n;
   const bool ell = a.ellD > 0;
@@ -368,13 +369,13 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
         for (int v = 0; v < NV; ++v) z[v] = LOG ? ninf<V>() : V(0);
       }
     }
-    if (a.slots) calib_chunk<V, LOG>(z, G, ch * G * NV, a.Lp, a.slots + (size_t)(blockIdx.x % a.nslot) * a.nslot_stride);
+    if (a.slots) calib_chunk<V, LOG>(z, G, ch * G * NV, a.Lp, a.slots + (size_t)(bid % a.nslot) * a.nslot_stride);
     if (FWD && a.slots_o) {
       if (!cv) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = LOG ? ninf<V>() : V(0);
       }
-      calib_chunk<V, LOG>(o, G, ch * G * NV, a.Lp, a.slots_o + (size_t)(blockIdx.x % a.nslot) * a.nslot_stride_o);
+      calib_chunk<V, LOG>(o, G, ch * G * NV, a.Lp, a.slots_o + (size_t)(bid % a.nslot) * a.nslot_stride_o);
     }
   }
 
@@ -417,20 +418,31 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
     for (int m = G >> 1; m > 0; m >>= 1) t += __shfl_xor(t, m, 64);
     if (valid && gl == 0 && a.occ) a.occ[row] = t;
   }
-  if (CHK && a.part) block_stats(st, a.part, blockIdx.x);
+  if (CHK && a.part) block_stats(st, a.part, bid);
 }
+template <typename V, bool LOG, bool FWD, bool CHK>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
+  step_body<V, LOG, FWD, CHK>(a, blockIdx.x, gridDim.x);
+}
+
 
 // ---------------------------------------------------------------------------
 // source update: U01 = R01 ./ Psi_1 (Algorithm 2), stored scaled by fac
 // ---------------------------------------------------------------------------
 template <typename V, bool LOG>
-__global__ __launch_bounds__(kBlock) void k_source(int n, int Lp, int G, int nchunk, const V* __restrict__ psi0,
-                                                   const V* __restrict__ rsrc, V* __restrict__ u01, uint32_t* slots,
-                                                   int nslot, size_t slot_stride, int* flags) {
+__device__ __forceinline__ void source_body(const SourceArgs<V>& A, int bid, int nblk) {
+  const int n = A.n, Lp = A.Lp, G = A.G, nchunk = A.nchunk, nslot = A.nslot;
+  const V* __restrict__ psi0 = A.psi0;
+  const V* __restrict__ rsrc = A.rsrc;
+  V* __restrict__ u01 = A.u01;
+  uint32_t* slots = A.slots;
+  const size_t slot_stride = A.slot_stride;
+  int* flags = A.flags;
+
   constexpr int NV = VT<V>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / G, gl = lane & (G - 1);
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int lb = xcd_block(bid, nblk);
   const int row = (lb * kWaves + wave) * (64 / G) + grp;
   const bool valid = row < n;
   for (int ch = 0; ch < nchunk; ++ch) {
@@ -460,22 +472,34 @@ __global__ __launch_bounds__(kBlock) void k_source(int n, int Lp, int G, int nch
 #pragma unroll
       for (int v = 0; v < NV; ++v) z[v] = LOG ? ninf<V>() : V(0);
     }
-    if (slots) calib_chunk<V, LOG>(z, G, ch * G * NV, Lp, slots + (size_t)(blockIdx.x % nslot) * slot_stride);
+    if (slots) calib_chunk<V, LOG>(z, G, ch * G * NV, Lp, slots + (size_t)(bid % nslot) * slot_stride);
   }
 }
+template <typename V, bool LOG>
+__global__ __launch_bounds__(kBlock) void k_source(SourceArgs<V> A) {
+  source_body<V, LOG>(A, blockIdx.x, gridDim.x);
+}
+
 
 // ---------------------------------------------------------------------------
 // statistics at time 0: P_{0,1} = U01 (.) Psi_1 against R01 (check / output pass)
 // ---------------------------------------------------------------------------
 template <typename V, bool LOG>
-__global__ __launch_bounds__(kBlock) void k_check0(int n, int Lp, int L, int G, int nchunk, const V* __restrict__ psi0,
-                                                   const V* __restrict__ u01, const V* __restrict__ rsrc,
-                                                   const double* __restrict__ sigf0, const double* __restrict__ sigb0,
-                                                   double* part, double* occ, double* pcomm) {
+__device__ __forceinline__ void check0_body(const Check0Args<V>& A, int bid, int nblk) {
+  const int n = A.n, Lp = A.Lp, L = A.L, G = A.G, nchunk = A.nchunk;
+  const V* __restrict__ psi0 = A.psi0;
+  const V* __restrict__ u01 = A.u01;
+  const V* __restrict__ rsrc = A.rsrc;
+  const double* __restrict__ sigf0 = A.sigf0;
+  const double* __restrict__ sigb0 = A.sigb0;
+  double* part = A.part;
+  double* occ = A.occ;
+  double* pcomm = A.pcomm;
+
   constexpr int NV = VT<V>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int grp = lane / G, gl = lane & (G - 1);
-  const int lb = xcd_block(blockIdx.x, gridDim.x);
+  const int lb = xcd_block(bid, nblk);
   const int row = (lb * kWaves + wave) * (64 / G) + grp;
   const bool valid = row < n;
   double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -517,8 +541,13 @@ __global__ __launch_bounds__(kBlock) void k_check0(int n, int Lp, int L, int G, 
     for (int m = G >> 1; m > 0; m >>= 1) t += __shfl_xor(t, m, 64);
     if (valid && gl == 0) occ[row] = t;
   }
-  if (part) block_stats(st, part, blockIdx.x);
+  if (part) block_stats(st, part, bid);
 }
+template <typename V, bool LOG>
+__global__ __launch_bounds__(kBlock) void k_check0(Check0Args<V> A) {
+  check0_body<V, LOG>(A, blockIdx.x, gridDim.x);
+}
+
 
 // ---------------------------------------------------------------------------
 // aggregate edge flows (SDDMM) between times t and t+1 on the CSR of K:
@@ -610,8 +639,12 @@ __global__ __launch_bounds__(kBlock) void k_flows(int n, int Lp, int L, int G, i
 // lev[t][l] = max over calibration slots (log2 column max of the panel stored
 // at time t, -inf if nothing was recorded); slots cleared.  Thread per (t, l);
 // all slot reads are issued before any clear.
-__global__ void k_levels(uint32_t* slots, float* lev, int T1, int Lp, int nslot) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void levels_body(const LevelsArgs& A, int bid, int nblk) {
+  uint32_t* slots = A.slots;
+  float* lev = A.lev;
+  const int T1 = A.T1, Lp = A.Lp, nslot = A.nslot;
+
+  const int idx = bid * blockDim.x + threadIdx.x;
   if (idx >= T1 * Lp) return;
   const size_t stride = (size_t)T1 * Lp;
   uint32_t v[32];
@@ -627,6 +660,8 @@ __global__ void k_levels(uint32_t* slots, float* lev, int T1, int Lp, int nslot)
   }
   lev[idx] = m;
 }
+__global__ void k_levels(LevelsArgs A) { levels_body(A, blockIdx.x, gridDim.x); }
+
 
 // wave-level helpers for the one-wavefront-per-commodity prep kernels
 __device__ __forceinline__ double wave_incl_scan(double x) {
@@ -665,8 +700,12 @@ __device__ __forceinline__ V to_wgt(double s) {
 // Growth update from a calibration sweep's column levels (thread per (t, l)):
 // backward (dir 0): c[T-1] += lev[T-1], c[t] += lev[t] - lev[t+1];
 // forward (dir 1):  c[1] += lev[1],     c[t] += lev[t] - lev[t-1] (t = 2..T).
-__global__ void k_growth(double* c, const float* __restrict__ lev, int T, int Lp, int dir) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void growth_body(const GrowthArgs& A, int bid, int nblk) {
+  double* c = A.c;
+  const float* __restrict__ lev = A.lev;
+  const int T = A.T, Lp = A.Lp, dir = A.dir;
+
+  const int idx = bid * blockDim.x + threadIdx.x;
   if (idx >= (T + 1) * Lp) return;
   const int t = idx / Lp;
   const float a = lev[idx];
@@ -683,17 +722,25 @@ __global__ void k_growth(double* c, const float* __restrict__ lev, int T, int Lp
     if (b > -INFINITY) c[idx] += (double)a - (double)b;
   }
 }
+__global__ void k_growth(GrowthArgs A) { growth_body(A, blockIdx.x, gridDim.x); }
+
 
 // Backward sweep offsets, one wavefront per commodity l (lanes = times).
 // Start level of the U0T panel from its slots; sigma_b[T] = gauge of U0T;
 // sigma_b[t] = sigma_b[t+1] + c_b[t] (suffix scan), the first product also
 // removing the start level.
 template <typename V, bool LOG>
-__global__ void k_prep_bwd(int T, int Lp, const double* __restrict__ cb, double* __restrict__ sigb,
-                           V* __restrict__ facb, const double* __restrict__ gaugeT, double* __restrict__ lvlT,
-                           uint32_t* slotsE, int nslot) {
+__device__ __forceinline__ void prep_bwd_body(const PrepBwdArgs<V>& A, int bid, int nblk) {
+  const int T = A.T, Lp = A.Lp, nslot = A.nslot;
+  const double* __restrict__ cb = A.cb;
+  double* __restrict__ sigb = A.sigb;
+  V* __restrict__ facb = A.facb;
+  const double* __restrict__ gaugeT = A.gaugeT;
+  double* __restrict__ lvlT = A.lvlT;
+  uint32_t* slotsE = A.slotsE;
+
   const int lane = threadIdx.x & 63;
-  const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int l = bid * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (l >= Lp) return;
   const double lv = wave_take_level(slotsE, nslot, Lp, l, lvlT[l]);
   double carry = gaugeT[l];
@@ -713,6 +760,9 @@ __global__ void k_prep_bwd(int T, int Lp, const double* __restrict__ cb, double*
     carry += __shfl(incl, 63, 64);
   }
 }
+template <typename V, bool LOG>
+__global__ void k_prep_bwd(PrepBwdArgs<V> A) { prep_bwd_body<V, LOG>(A, blockIdx.x, gridDim.x); }
+
 
 // Forward sweep offsets, one wavefront per commodity.  mode 0 (Sinkhorn sweep,
 // after the source update wrote U01 = R01 ./ Psi_1 unscaled):
@@ -722,12 +772,20 @@ __global__ void k_prep_bwd(int T, int Lp, const double* __restrict__ cb, double*
 // wgt[t] = 2^(sigma_hat_t + sigma_b[t]); mode 0 also sets the gauge of the U0T
 // panel the sink update is about to write: -sigma_hat_T.
 template <typename V, bool LOG>
-__global__ void k_prep_fwd(int T, int Lp, int mode, const double* __restrict__ cf, double* __restrict__ sigf,
-                           const double* __restrict__ sigb, V* __restrict__ facf, V* __restrict__ wgt,
-                           double* __restrict__ gauge0, double* __restrict__ gaugeT, double* __restrict__ lvl0,
-                           uint32_t* slotsS, int nslot) {
+__device__ __forceinline__ void prep_fwd_body(const PrepFwdArgs<V>& A, int bid, int nblk) {
+  const int T = A.T, Lp = A.Lp, mode = A.mode, nslot = A.nslot;
+  const double* __restrict__ cf = A.cf;
+  double* __restrict__ sigf = A.sigf;
+  const double* __restrict__ sigb = A.sigb;
+  V* __restrict__ facf = A.facf;
+  V* __restrict__ wgt = A.wgt;
+  double* __restrict__ gauge0 = A.gauge0;
+  double* __restrict__ gaugeT = A.gaugeT;
+  double* __restrict__ lvl0 = A.lvl0;
+  uint32_t* slotsS = A.slotsS;
+
   const int lane = threadIdx.x & 63;
-  const int l = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int l = bid * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (l >= Lp) return;
   double s0, lv;
   if (mode == 0) {
@@ -759,13 +817,20 @@ __global__ void k_prep_fwd(int T, int Lp, int mode, const double* __restrict__ c
     carry = __shfl(sg, 63, 64);
   }
 }
+template <typename V, bool LOG>
+__global__ void k_prep_fwd(PrepFwdArgs<V> A) { prep_fwd_body<V, LOG>(A, blockIdx.x, gridDim.x); }
+
 
 // ---------------------------------------------------------------------------
 // deterministic two-stage reduction of the stats partials
 // ---------------------------------------------------------------------------
 // stage 1: one block per time slot, sums its nblk partials in block order
-__global__ void k_reduce_stats1(const double* __restrict__ part, int nblk, double* __restrict__ tpart) {
-  const int t = blockIdx.x;
+__device__ __forceinline__ void reduce1_body(const Reduce1Args& A, int bid, int nblk_grid) {
+  const double* __restrict__ part = A.part;
+  const int nblk = A.nblk;
+  double* __restrict__ tpart = A.tpart;
+
+  const int t = bid;
   const double* p = part + (size_t)t * nblk * kNSt;
   __shared__ double red[kBlock][kNSt];
   double acc[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -786,11 +851,18 @@ __global__ void k_reduce_stats1(const double* __restrict__ part, int nblk, doubl
     tpart[(size_t)t * kNSt + k] = v;
   }
 }
+__global__ void k_reduce_stats1(Reduce1Args A) { reduce1_body(A, blockIdx.x, gridDim.x); }
+
 
 // stage 2: combine the T+1 time slots into the stats record
 //   out[0] dual_obj, [1] src_resid, [2] cap_viol, [3] mass_drift, [4] dual_gap, [5] mass, [6] nonfinite
-__global__ void k_reduce_stats2(const double* __restrict__ tpart, int T1, double eps, double* __restrict__ out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ __forceinline__ void reduce2_body(const Reduce2Args& A, int bid, int nblk) {
+  const double* __restrict__ tpart = A.tpart;
+  const int T1 = A.T1;
+  const double eps = A.eps;
+  double* __restrict__ out = A.out;
+
+  if (threadIdx.x != 0 || bid != 0) return;
   double dual = 0, gap = 0, viol = 0, nonfin = 0;
   for (int t = 0; t < T1; ++t) {
     const double* p = tpart + (size_t)t * kNSt;
@@ -810,6 +882,8 @@ __global__ void k_reduce_stats2(const double* __restrict__ tpart, int T1, double
   out[5] = massT;
   out[6] = nonfin;
 }
+__global__ void k_reduce_stats2(Reduce2Args A) { reduce2_body(A, blockIdx.x, gridDim.x); }
+
 
 // transport cost = move costs from the flow-kernel partials (tflow, T slots)
 // + state costs from the update-free forward steps (tstate, slots 1..T-1)
@@ -828,6 +902,7 @@ __global__ void k_reduce_cost(const double* __restrict__ tflow, const double* __
 // fwd: 0 backward product, 1 forward Sinkhorn step, 2 forward update-free (check / output) step
 template <typename V, bool LOG>
 void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
+  if (record_item(fwd == 0 ? IK_STEP_BWD : (fwd == 1 ? IK_STEP_FWD : IK_STEP_CHK), LOG, nblk, &a, sizeof(a))) return;
   if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false>), dim3(nblk), dim3(kBlock), 0, s, a);
   else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true>), dim3(nblk), dim3(kBlock), 0, s, a);
   else hipLaunchKernelGGL((k_step<V, LOG, false, false>), dim3(nblk), dim3(kBlock), 0, s, a);
@@ -835,15 +910,17 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
 template <typename V, bool LOG>
 void launch_source(int n, int Lp, int G, int nchunk, const V* psi0, const V* rsrc, V* u01, uint32_t* slots,
                    int nslot, size_t slot_stride, int* flags, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL((k_source<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, n, Lp, G, nchunk, psi0, rsrc, u01, slots,
-                     nslot, slot_stride, flags);
+  const SourceArgs<V> A{n, Lp, G, nchunk, nslot, psi0, rsrc, u01, slots, slot_stride, flags};
+  if (record_item(IK_SOURCE, LOG, nblk, &A, sizeof(A))) return;
+  hipLaunchKernelGGL((k_source<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, A);
 }
 template <typename V, bool LOG>
 void launch_check0(int n, int Lp, int L, int G, int nchunk, const V* psi0, const V* u01, const V* rsrc,
                    const double* sigf0, const double* sigb0, double* part, double* occ, double* pcomm, int nblk,
                    hipStream_t s) {
-  hipLaunchKernelGGL((k_check0<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, n, Lp, L, G, nchunk, psi0, u01, rsrc,
-                     sigf0, sigb0, part, occ, pcomm);
+  const Check0Args<V> A{n, Lp, L, G, nchunk, psi0, u01, rsrc, sigf0, sigb0, part, occ, pcomm};
+  if (record_item(IK_CHECK0, LOG, nblk, &A, sizeof(A))) return;
+  hipLaunchKernelGGL((k_check0<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, A);
 }
 template <typename V, bool LOG>
 void launch_flows(int n, int Lp, int L, int G, int nchunk, const int* rp, const int* ci, const V* kv,
@@ -855,33 +932,93 @@ void launch_flows(int n, int Lp, int L, int G, int nchunk, const int* rp, const 
 template <typename V, bool LOG>
 void launch_prep_bwd(int T, int Lp, const double* cb, double* sigb, V* facb, const double* gaugeT, double* lvlT,
                      uint32_t* slotsE, int nslot, hipStream_t s) {
-  hipLaunchKernelGGL((k_prep_bwd<V, LOG>), dim3((Lp + 3) / 4), dim3(256), 0, s, T, Lp, cb, sigb, facb, gaugeT, lvlT,
-                     slotsE, nslot);
+  const PrepBwdArgs<V> A{T, Lp, nslot, cb, sigb, facb, gaugeT, lvlT, slotsE};
+  const int nb = (Lp + 3) / 4;
+  if (record_item(IK_PREP_BWD, LOG, nb, &A, sizeof(A))) return;
+  hipLaunchKernelGGL((k_prep_bwd<V, LOG>), dim3(nb), dim3(256), 0, s, A);
 }
 template <typename V, bool LOG>
 void launch_prep_fwd(int T, int Lp, int mode, const double* cf, double* sigf, const double* sigb, V* facf, V* wgt,
                      double* gauge0, double* gaugeT, double* lvl0, uint32_t* slotsS, int nslot, hipStream_t s) {
-  hipLaunchKernelGGL((k_prep_fwd<V, LOG>), dim3((Lp + 3) / 4), dim3(256), 0, s, T, Lp, mode, cf, sigf, sigb, facf,
-                     wgt, gauge0, gaugeT, lvl0, slotsS, nslot);
+  const PrepFwdArgs<V> A{T, Lp, mode, nslot, cf, sigf, sigb, facf, wgt, gauge0, gaugeT, lvl0, slotsS};
+  const int nb = (Lp + 3) / 4;
+  if (record_item(IK_PREP_FWD, LOG, nb, &A, sizeof(A))) return;
+  hipLaunchKernelGGL((k_prep_fwd<V, LOG>), dim3(nb), dim3(256), 0, s, A);
 }
 void launch_growth(double* c, const float* lev, int T, int Lp, int dir, hipStream_t s) {
-  const int tot = (T + 1) * Lp;
-  hipLaunchKernelGGL(k_growth, dim3((tot + 255) / 256), dim3(256), 0, s, c, lev, T, Lp, dir);
+  const GrowthArgs A{c, lev, T, Lp, dir};
+  const int nb = ((T + 1) * Lp + 255) / 256;
+  if (record_item(IK_GROWTH, 0, nb, &A, sizeof(A))) return;
+  hipLaunchKernelGGL(k_growth, dim3(nb), dim3(256), 0, s, A);
 }
 void launch_levels(uint32_t* slots, float* lev, int T1, int Lp, int nslot, hipStream_t s) {
-  const int tot = T1 * Lp;
-  hipLaunchKernelGGL(k_levels, dim3((tot + 255) / 256), dim3(256), 0, s, slots, lev, T1, Lp, nslot);
+  const LevelsArgs A{slots, lev, T1, Lp, nslot};
+  const int nb = (T1 * Lp + 255) / 256;
+  if (record_item(IK_LEVELS, 0, nb, &A, sizeof(A))) return;
+  hipLaunchKernelGGL(k_levels, dim3(nb), dim3(256), 0, s, A);
 }
 void launch_reduce_stats(const double* part, int nblk, int T1, double* tpart, double eps, double* out,
                          hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_stats1, dim3(T1), dim3(kBlock), 0, s, part, nblk, tpart);
-  hipLaunchKernelGGL(k_reduce_stats2, dim3(1), dim3(64), 0, s, tpart, T1, eps, out);
+  const Reduce1Args A{part, nblk, tpart};
+  const Reduce2Args B{tpart, T1, eps, out};
+  if (record_item(IK_REDUCE1, 0, T1, &A, sizeof(A))) {
+    record_item(IK_REDUCE2, 0, 1, &B, sizeof(B));
+    return;
+  }
+  hipLaunchKernelGGL(k_reduce_stats1, dim3(T1), dim3(kBlock), 0, s, A);
+  hipLaunchKernelGGL(k_reduce_stats2, dim3(1), dim3(64), 0, s, B);
 }
 void launch_reduce_cost(const double* pflow, const double* pstate, int nblk, int T, double* tflow, double* tstate,
                         double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, pflow, nblk, tflow);
-  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, pstate, nblk, tstate);
+  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, Reduce1Args{pflow, nblk, tflow});
+  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, Reduce1Args{pstate, nblk, tstate});
   hipLaunchKernelGGL(k_reduce_cost, dim3(1), dim3(64), 0, s, tflow, tstate, T, out);
+}
+
+// ---------------------------------------------------------------------------
+// serving pool: one launch runs the next recorded item of every active solve
+// (FP32 solves; items carry their own block counts, prefix[] the offsets)
+// ---------------------------------------------------------------------------
+static_assert(sizeof(StepArgs<float>) <= kItemArgBytes, "item argument area too small");
+
+template <bool LOG>
+__device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
+  const void* p = it.args;
+  switch (it.kind) {
+    case IK_STEP_BWD: step_body<float, LOG, false, false>(*static_cast<const StepArgs<float>*>(p), bid, it.nblk); break;
+    case IK_STEP_FWD: step_body<float, LOG, true, false>(*static_cast<const StepArgs<float>*>(p), bid, it.nblk); break;
+    case IK_STEP_CHK: step_body<float, LOG, true, true>(*static_cast<const StepArgs<float>*>(p), bid, it.nblk); break;
+    case IK_SOURCE: source_body<float, LOG>(*static_cast<const SourceArgs<float>*>(p), bid, it.nblk); break;
+    case IK_CHECK0: check0_body<float, LOG>(*static_cast<const Check0Args<float>*>(p), bid, it.nblk); break;
+    case IK_PREP_BWD: prep_bwd_body<float, LOG>(*static_cast<const PrepBwdArgs<float>*>(p), bid, it.nblk); break;
+    case IK_PREP_FWD: prep_fwd_body<float, LOG>(*static_cast<const PrepFwdArgs<float>*>(p), bid, it.nblk); break;
+    default: break;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pool_tick(const PoolItem* __restrict__ items, const int* __restrict__ prefix,
+                                                      int nitems) {
+  int lo = 0, hi = nitems - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const PoolItem& it = items[lo];
+  const int bid = b - prefix[lo];
+  switch (it.kind) {
+    case IK_LEVELS: levels_body(*reinterpret_cast<const LevelsArgs*>(it.args), bid, it.nblk); return;
+    case IK_GROWTH: growth_body(*reinterpret_cast<const GrowthArgs*>(it.args), bid, it.nblk); return;
+    case IK_REDUCE1: reduce1_body(*reinterpret_cast<const Reduce1Args*>(it.args), bid, it.nblk); return;
+    case IK_REDUCE2: reduce2_body(*reinterpret_cast<const Reduce2Args*>(it.args), bid, it.nblk); return;
+    default: break;
+  }
+  if (it.log_domain) run_item<true>(it, bid);
+  else run_item<false>(it, bid);
+}
+
+void launch_pool_tick(const PoolItem* items, const int* prefix, int nitems, int total_blocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_tick, dim3(total_blocks), dim3(kBlock), 0, s, items, prefix, nitems);
 }
 
 #define MMOT_INST(V, LOG)                                                                                         \

@@ -391,7 +391,11 @@ def serve_trace(num: int = 10000, rate: float = 100.0, seed: int = 0,
 
 
 def instance_from_request(req: dict) -> Instance:
+    """Build a trace request.  Random-geometric-graph capacities are scaled by
+    max(1, 8 L / n) so that many commodities on few nodes stay feasible."""
     if req["gen"] == "rgg":
-        return rgg_instance(n=req["n"], L=req["L"], T=req["T"], eps=req["eps"], seed=req["seed"])
+        f = max(1.0, 8.0 * req["L"] / req["n"])
+        return rgg_instance(n=req["n"], L=req["L"], T=req["T"], eps=req["eps"], seed=req["seed"],
+                            cap_lo=0.2 * f, cap_hi=1.0 * f)
     side = max(2, int(round(math.sqrt(req["n"]))))
     return road_grid_instance(side=side, L=req["L"], T=req["T"], eps=req["eps"], seed=req["seed"])

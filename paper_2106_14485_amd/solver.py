@@ -136,6 +136,10 @@ class Solver:
         check(_lib.lib().mmot_set_log_duals(self._h, _ptr(ls), _ptr(ld), _ptr(lc)), "mmot_set_log_duals")
         self.stream.synchronize()
 
+    def set_precision(self, precision: str):
+        """Dense BF16 solvers: switch the products between 'bf16' and 'fp32' (polish)."""
+        check(_lib.lib().mmot_set_precision(self._h, _PREC[precision]), "mmot_set_precision")
+
     def time_step(self, forward: bool = True, reps: int = 50) -> float:
         """Average device milliseconds of one sweep step (HIP events)."""
         ms = ctypes.c_double(0.0)

@@ -193,3 +193,64 @@ def test_solve_converges_and_invariants(grid):
     assert (occ >= 0).all()
     assert np.all(occ[1:-1] <= grid.cap[None, :] * (1 + 1e-8))
     S.close()
+
+
+# ---------------------------------------------------------------------------
+# dense graphs: MFMA products (FP32, and BF16 with an FP32 polish)
+# ---------------------------------------------------------------------------
+
+def dense_outputs(inst, n_iter, precision, polish=0):
+    S = _solver()(inst, precision=precision, domain="auto")
+    S.iterate(n_iter)
+    if polish:
+        S.set_precision("fp32")
+        S.iterate(polish)
+    st = S.stats()
+    occ, pc = S.occupancy(per_commodity=True)
+    torch.cuda.synchronize()
+    res = dict(Pt=occ.cpu().numpy(), P0t=pc.cpu().numpy(), stats=st)
+    S.close()
+    return res
+
+
+def dense_oracle(inst, n_iter, fp32_inputs=False):
+    """Oracle run; fp32_inputs=True rounds R01/R0T to FP32 first (the problem an FP32
+    scaled-domain solver represents: marginal entries below the FP32 range are zero)."""
+    p = to_oracle(inst)
+    if fp32_inputs:
+        p = alg2.make_problem(p.C, p.eps, p.T, inst.src.astype(np.float32).astype(np.float64),
+                              inst.dst.astype(np.float32).astype(np.float64), p.cap)
+    st = alg2.iterate(p, alg2.initial_state(p), n_iter)
+    out = alg2.projections(p, st)
+    return dict(Pt=out["Pt"], P0t=out["P0t"], g=st.g)
+
+
+@pytest.mark.parametrize("n,L,T", [(300, 40, 8), (130, 20, 5), (256, 128, 6)])
+def test_dense_fp32_iterates(n, L, T):
+    inst = instances.dense_blob_instance(n=n, L=L, T=T, seed=n + L)
+    o = dense_oracle(inst, 15, fp32_inputs=True)
+    g = dense_outputs(inst, 15, "fp32")
+    assert g["stats"]["domain"] == 1 and g["stats"]["precision"] == 0
+    assert rel_l1(g["Pt"], o["Pt"]) <= 1e-5, rel_l1(g["Pt"], o["Pt"])
+    assert rel_l1(g["P0t"], o["P0t"]) <= 1e-5, rel_l1(g["P0t"], o["P0t"])
+    assert abs(g["stats"]["dual_obj"] - o["g"][-1]) <= 1e-5 * abs(o["g"][-1])
+
+
+def test_dense_fp32_against_exact_inputs_after_convergence():
+    inst = instances.dense_blob_instance(n=300, L=40, T=8, seed=340)
+    o = dense_oracle(inst, 100)
+    g = dense_outputs(inst, 100, "fp32")
+    assert rel_l1(g["Pt"], o["Pt"]) <= 1e-5
+    assert rel_l1(g["P0t"], o["P0t"]) <= 1e-5
+
+
+def test_dense_bf16_then_fp32_polish():
+    inst = instances.dense_blob_instance(n=300, L=40, T=8, seed=7)
+    o = dense_oracle(inst, 400)
+    g16 = dense_outputs(inst, 360, "bf16")
+    assert g16["stats"]["precision"] == 2
+    e16 = rel_l1(g16["P0t"], o["P0t"])
+    g = dense_outputs(inst, 360, "bf16", polish=40)
+    e = rel_l1(g["P0t"], o["P0t"])
+    assert rel_l1(g["Pt"], o["Pt"]) <= 1e-4
+    assert e <= 1e-4, (e, e16)

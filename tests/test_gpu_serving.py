@@ -1,0 +1,88 @@
+"""Serving pool: continuous batching of uneven solves; each result equals the plain solve."""
+import numpy as np
+import pytest
+
+from paper_2106_14485_amd import instances
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _mix():
+    return [
+        instances.rgg_instance(n=400, L=24, T=12, seed=11, cap_lo=1.0, cap_hi=2.0),
+        instances.road_grid_instance(side=14, L=9, T=30, eps=0.1, seed=12),
+        instances.rgg_instance(n=900, L=70, T=20, seed=13, cap_lo=1.0, cap_hi=2.0),
+        instances.road_grid_instance(side=20, L=3, T=45, eps=0.05, seed=14),
+        instances.rgg_instance(n=250, L=1, T=10, seed=15),
+    ]
+
+
+def _plain(inst, max_iter):
+    from paper_2106_14485_amd.solver import Solver
+    S = Solver(inst, precision="fp32", domain="auto", check_every=10, tol=1e-6)
+    st = S.solve(max_iter)
+    occ = S.occupancy().cpu().numpy()
+    S.close()
+    return st, occ
+
+
+def _pooled(insts, max_iter, budget=1 << 36):
+    from paper_2106_14485_amd.serve import Pool
+    pool = Pool(budget, check_every=10, tol=1e-6)
+    tickets = [pool.submit(x, max_iter=max_iter) for x in insts]
+    assert all(t is not None for t in tickets)
+    while pool.run(64) > 0:
+        pass
+    out = []
+    for t in tickets:
+        state, status, st = pool.poll(t)
+        assert state == 1 and status == 0
+        out.append((st, pool.occupancy(t).cpu().numpy()))
+        pool.release(t)
+    pool.close()
+    return out
+
+
+def test_each_result_same_alone_in_mix_and_plain():
+    insts = _mix()
+    mixed = _pooled(insts, 60)
+    for k, inst in enumerate(insts):
+        alone = _pooled([inst], 60)[0]
+        plain = _plain(inst, 60)
+        assert np.array_equal(mixed[k][1], alone[1]), f"request {k}: mix differs from alone"
+        assert np.array_equal(alone[1], plain[1]), f"request {k}: pool differs from plain solver"
+        assert mixed[k][0]["iters"] == plain[0]["iters"]
+        assert mixed[k][0]["dual_obj"] == plain[0]["dual_obj"]
+
+
+def test_budget_admission_and_release():
+    from paper_2106_14485_amd.serve import Pool
+    insts = _mix()[:3]
+    probe = Pool(1 << 40)
+    sizes = [probe.workspace_bytes(x) for x in insts]
+    probe.close()
+    pool = Pool(sizes[0] + sizes[1])            # room for the first two only
+    t0 = pool.submit(insts[0], max_iter=20)
+    t1 = pool.submit(insts[1], max_iter=20)
+    assert t0 is not None and t1 is not None
+    assert pool.submit(insts[2], max_iter=20) is None        # over budget -> queued by the caller
+    while pool.run(64) > 0:
+        pass
+    pool.release(t0)
+    t2 = pool.submit(insts[2], max_iter=20)                   # admitted once budget frees up
+    assert t2 is not None
+    while pool.run(64) > 0:
+        pass
+    assert pool.poll(t2)[0] == 1
+    pool.close()
+
+
+def test_serve_loop_latency_report():
+    from paper_2106_14485_amd.serve import latency_summary, serve
+    insts = _mix()
+    arrivals = np.array([0.0, 0.01, 0.02, 0.05, 0.06])
+    res, total = serve(insts, arrivals, budget_bytes=1 << 36, max_iter=40)
+    s = latency_summary(res, total)
+    assert s["n"] == len(insts) and s["p99_s"] >= s["p50_s"] > 0
+    assert all(r["status"] == 0 for r in res)
