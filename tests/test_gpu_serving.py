@@ -58,7 +58,8 @@ def test_each_result_same_alone_in_mix_and_plain():
 
 def test_budget_admission_and_release():
     from paper_2106_14485_amd.serve import Pool
-    insts = _mix()[:3]
+    m = _mix()
+    insts = [m[2], m[0], m[4]]                    # large, medium, small workspace
     probe = Pool(1 << 40)
     sizes = [probe.workspace_bytes(x) for x in insts]
     probe.close()
