@@ -184,11 +184,13 @@ mmot_status mmot_set_precision(mmot_solver* s, int32_t precision);
 int64_t mmot_iterations(const mmot_solver* s);
 
 /* Profiling helper: average device time (ms, HIP events on the solver's
- * stream) of `reps` back-to-back launches of one sweep step at the middle
- * time, forward != 0: the forward product with its capacity-update epilogue
- * (the u it computes goes to scratch), else the backward product.  Message
- * panels are left needing a fresh backward sweep (done automatically by the
- * next call that needs them).  Synchronous. */
+ * stream) of `reps` back-to-back launches of one sweep step, cycling through
+ * the interior times as a sweep does; forward != 0: the forward product with
+ * its capacity-update epilogue (the u it computes goes to scratch), else the
+ * backward product.  Message panels are left needing a fresh backward sweep
+ * (done automatically by the next call that needs them).  Synchronous.
+ * EUNSUPPORTED for a forward step of a CSR problem with T = 1 (its only
+ * forward product is the sink update). */
 mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double* avg_ms_host);
 
 /* ---------------------------------------------------------------------------

@@ -474,31 +474,35 @@ struct Impl {
   // time `reps` launches of one sweep step at the middle time, as launched in
   // the sweep (forward: with the capacity update, its u written to scratch)
   static mmot_status time_step(mmot_solver* s, int fwd, int reps, double* avg_ms) {
-    const int t = std::max(0, std::min(s->T - 2, s->T / 2));
+    // cycle through the interior times, as a sweep does (each launch reads
+    // and writes other panels than the one before it)
+    const int t_lo = s->T >= 3 ? 1 : 0, t_hi = std::max(t_lo, s->T - 2);
+    if (fwd && s->T < 2 && s->kind != MMOT_DENSE) return MMOT_EUNSUPPORTED;   // the only product is the sink's
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
-    StepArgs<V> a = fwd ? fwd_args(s, t, 0, false, nullptr, nullptr) : bwd_args(s, t, false);
-    if (fwd && a.epi == 1) a.uout = reinterpret_cast<V*>(s->exc_row);
-    GemmArgs g{};
-    if (s->kind == MMOT_DENSE) {
-      g = gemm_base(s, fwd != 0);
-      g.B = reinterpret_cast<const float*>(psi(s, t + 1));
-      g.u = reinterpret_cast<const float*>(uat(s, t + 1));
-      g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
-      g.out = reinterpret_cast<float*>(zh(s, 0));
-      if (fwd) {   // forward product with the capacity partial sums, as in the sweep
-        g.cap = 1;
-        g.wpan = reinterpret_cast<const float*>(psi(s, t));
-        g.wgt = reinterpret_cast<const float*>(s->wgt);
-        g.part_s = s->part_s;
+    auto launch_at = [&](int t) {
+      if (s->kind == MMOT_DENSE) {
+        GemmArgs g = gemm_base(s, fwd != 0);
+        g.B = reinterpret_cast<const float*>(psi(s, t + 1));
+        g.u = reinterpret_cast<const float*>(uat(s, t + 1));
+        g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
+        g.out = reinterpret_cast<float*>(zh(s, t & 1));
+        if (fwd) {   // forward product with the capacity partial sums, as in the sweep
+          g.cap = 1;
+          g.wpan = reinterpret_cast<const float*>(psi(s, t));
+          g.wgt = reinterpret_cast<const float*>(s->wgt);
+          g.part_s = s->part_s;
+        }
+        launch_gemm(g, s->dense_bf16, s->stream);
+      } else {
+        StepArgs<V> a = fwd ? fwd_args(s, t, 0, false, nullptr, nullptr) : bwd_args(s, t, false);
+        if (fwd && a.epi == 1) a.uout = reinterpret_cast<V*>(s->exc_row);
+        launch_step<V, LOG>(a, fwd, s->nblk, s->stream);
       }
-    }
+    };
     HIPCK(hipEventRecord(e0, s->stream));
-    for (int r = 0; r < reps; ++r) {
-      if (s->kind == MMOT_DENSE) launch_gemm(g, s->dense_bf16, s->stream);
-      else launch_step<V, LOG>(a, fwd, s->nblk, s->stream);
-    }
+    for (int r = 0; r < reps; ++r) launch_at(t_lo + r % (t_hi - t_lo + 1));
     HIPCK(hipEventRecord(e1, s->stream));
     HIPCK(hipEventSynchronize(e1));
     float ms = 0;
@@ -773,6 +777,7 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
   if (hipHostMalloc(reinterpret_cast<void**>(&s->host_flags), 4 * sizeof(int), 0) != hipSuccess) return fail(MMOT_EHIP);
   if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MMOT_EHIP);
   // domain: an estimate of the within-message dynamic range R = T * mean excess move cost / eps (log2 units)
+  bool auto_probe = false;
   if (o->domain == MMOT_DOMAIN_AUTO && p->kind == MMOT_DENSE) {
     s->dom = MMOT_DOMAIN_SCALED;
   } else if (o->domain == MMOT_DOMAIN_AUTO) {
@@ -785,11 +790,33 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
     const double R = (double)p->T * h / p->eps;       // natural-log range estimate
     const double limit = (s->prec == MMOT_FP64) ? 600.0 : 60.0;
     s->dom = (R <= limit) ? MMOT_DOMAIN_SCALED : MMOT_DOMAIN_LOG;
+    auto_probe = s->dom == MMOT_DOMAIN_SCALED;
   } else {
     s->dom = o->domain;
   }
   st = dispatch(s, [&](auto impl) { return decltype(impl)::setup(s, p); });
   if (st != MMOT_OK) return fail(st);
+  if (auto_probe) {
+    // The cost estimate above misses the path-counting part of the range (a
+    // state many forced moves away from the sink sees only a few of the walks
+    // that a state next to it sees), so the scaled domain is confirmed by one
+    // iteration: a zero or non-finite message at a support entry means the
+    // within-commodity range exceeds the element type, and the solver switches
+    // to the log domain.  Either way it then restarts from the initial scalings.
+    const int g = s->opt.use_graph;
+    s->opt.use_graph = 0;
+    st = run_iterations(s, 1);
+    s->opt.use_graph = g;
+    if (st != MMOT_OK) return fail(st);
+    const mmot_status fs = read_flags(s);
+    if (fs == MMOT_EINFEASIBLE || fs == MMOT_ENUMERIC) s->dom = MMOT_DOMAIN_LOG;
+    else if (fs != MMOT_OK) return fail(fs);
+    s->iters = 0;
+    s->psi_fresh = s->pend_b = s->pend_f = false;
+    s->force_calib = 0;
+    st = dispatch(s, [&](auto impl) { return decltype(impl)::setup(s, p); });
+    if (st != MMOT_OK) return fail(st);
+  }
   *out = s;
   return MMOT_OK;
 }

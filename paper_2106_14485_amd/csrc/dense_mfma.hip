@@ -87,10 +87,21 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 
   // staged operands of one K-stage, held in registers between the global
   // loads and the LDS writes (software pipeline: stage k+1 loads overlap
-  // stage k MFMAs)
+  // stage k MFMAs).  All loads of a stage are unconditional (indices clamped,
+  // out-of-range values replaced by zero afterwards), so they issue back to
+  // back and the wave waits once per stage, not once per load.
   uint4 ra[AV];
-  float rb[32];
-  const int bc = tid & 127, bkh = tid >> 7;   // B: column in tile, k half (32 k each)
+  uint32_t aok = 0;   // bit v: chunk v of A lies inside the matrix (applied at the LDS write)
+  float4 rb[8];
+  float ru[8];
+  uint32_t bok = 0;   // bit e: k row e of the B chunk lies inside the matrix
+  // B: thread owns 4 consecutive columns (16-byte loads along the panel row)
+  // and 8 consecutive k of the stage
+  const int cq = tid & 31, kg = tid >> 5;
+  const int gcb = col0 + cq * 4;
+  const bool bcol_ok = gcb < a.Lp;            // Lp is a multiple of 4
+  const int gcb_c = bcol_ok ? gcb : 0;
+  const bool has_u = a.u != nullptr;
 
   auto gload = [&](int k0) {
 #pragma unroll
@@ -99,20 +110,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
       const int r = BF16 ? (c >> 3) : (c >> 4);
       const int ch = BF16 ? (c & 7) : (c & 15);
       const int gr = row0 + r, gk = k0 + ch * (BF16 ? 8 : 4);
-      ra[v] = make_uint4(0, 0, 0, 0);
-      if (gr < a.n && gk < a.lda) ra[v] = *reinterpret_cast<const uint4*>(A + (size_t)gr * a.lda + gk);
+      const int grc = gr < a.n ? gr : a.n - 1;
+      const int gkc = gk < a.lda ? gk : 0;
+      ra[v] = *reinterpret_cast<const uint4*>(A + (size_t)grc * a.lda + gkc);
+      if (v == 0) aok = 0;
+      aok |= (gr < a.n && gk < a.lda) ? (1u << v) : 0u;
     }
-    const int gc = col0 + bc;
 #pragma unroll
-    for (int j = 0; j < 32; ++j) {
-      const int gk = k0 + bkh * 32 + j;
-      float v = 0.f;
-      if (gk < a.n && gc < a.Lp) {
-        v = a.B[(size_t)gk * a.Lp + gc];
-        if (a.u) v *= a.u[gk];
-      }
-      rb[j] = v;
+    for (int e = 0; e < 8; ++e) {
+      const int gk = k0 + kg * 8 + e;
+      const int gkc = gk < a.n ? gk : a.n - 1;
+      rb[e] = *reinterpret_cast<const float4*>(a.B + (size_t)gkc * a.Lp + gcb_c);
+      ru[e] = has_u ? a.u[gkc] : 1.f;
     }
+    bok = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bok |= (k0 + kg * 8 + e < a.n && bcol_ok) ? (1u << e) : 0u;
   };
   auto swrite = [&](int buf) {
     TA* as = As[buf];
@@ -120,6 +133,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 #pragma unroll
     for (int v = 0; v < AV; ++v) {
       const int c = tid + v * 256;
+      if (!((aok >> v) & 1u)) ra[v] = make_uint4(0, 0, 0, 0);
       if (BF16) {
         const int r = c >> 3, ch = c & 7;
         *reinterpret_cast<uint4*>(&as[r * LDK + ch * 8]) = ra[v];
@@ -127,24 +141,30 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
         // 16 chunks of 4 k per row; k-interleaved: position h*32 + s holds k = 2s + h
         const int r = c >> 4, ch = c & 15;
         float* dst = reinterpret_cast<float*>(&as[r * LDK]);
-        dst[0 * 32 + ch * 2 + 0] = __uint_as_float(ra[v].x);
-        dst[1 * 32 + ch * 2 + 0] = __uint_as_float(ra[v].y);
-        dst[0 * 32 + ch * 2 + 1] = __uint_as_float(ra[v].z);
-        dst[1 * 32 + ch * 2 + 1] = __uint_as_float(ra[v].w);
+        *reinterpret_cast<float2*>(&dst[ch * 2]) = make_float2(__uint_as_float(ra[v].x), __uint_as_float(ra[v].z));
+        *reinterpret_cast<float2*>(&dst[32 + ch * 2]) =
+            make_float2(__uint_as_float(ra[v].y), __uint_as_float(ra[v].w));
       }
     }
-    if (BF16) {
+    // scale by u (zero outside the matrix) and store column-major: Bs[col][k]
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 4; ++q) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float b = (q == 0) ? rb[e].x : (q == 1) ? rb[e].y : (q == 2) ? rb[e].z : rb[e].w;
+        x[e] = ((bok >> e) & 1u) ? b * ru[e] : 0.f;
+      }
+      if (BF16) {
         bf16x8 p;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) p[j] = (__bf16)rb[q * 8 + j];
-        *reinterpret_cast<bf16x8*>(&bs[bc * LDK + bkh * 32 + q * 8]) = p;
+        for (int e = 0; e < 8; ++e) p[e] = (__bf16)x[e];
+        *reinterpret_cast<bf16x8*>(&bs[(cq * 4 + q) * LDK + kg * 8]) = p;
+      } else {
+        float* dst = reinterpret_cast<float*>(&bs[(cq * 4 + q) * LDK]);
+        *reinterpret_cast<float4*>(&dst[kg * 4]) = make_float4(x[0], x[2], x[4], x[6]);
+        *reinterpret_cast<float4*>(&dst[32 + kg * 4]) = make_float4(x[1], x[3], x[5], x[7]);
       }
-    } else {
-      float* dst = reinterpret_cast<float*>(&bs[bc * LDK]);
-#pragma unroll
-      for (int j = 0; j < 32; ++j) dst[(j & 1) * 32 + bkh * 16 + (j >> 1)] = rb[j];
     }
   };
 
@@ -228,27 +248,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   for (int j = 0; j < 2; ++j) {
     const int gc = col0 + wn * 64 + j * 32 + lr;
     const bool cok = gc < a.Lp;
-    const float f = cok ? a.fac[gc] : 0.f;
-    const float g = (a.cap && cok) ? a.wgt[gc] : 0.f;
+    const int gcc = cok ? gc : 0;
+    const float f = cok ? a.fac[gcc] : 0.f;
+    const bool capc = a.cap && gc < a.L;
+    const float g = capc ? a.wgt[gcc] : 0.f;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
+      // operands of the epilogue, loaded unconditionally (clamped) before use
+      float klv[16], wv[16];
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int gr = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-        if (!(cok && gr < a.n)) continue;
+        const size_t off = (size_t)(gr < a.n ? gr : a.n - 1) * a.Lp + gcc;
+        klv[r] = a.kl ? a.kl[off] : 1.f;
+        wv[r] = a.cap ? a.wpan[off] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int gr = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        const bool ok = cok && gr < a.n;
         const size_t off = (size_t)gr * a.Lp + gc;
         const float o = acc[i][j][r] * f;
-        float z = o;
-        if (a.kl) z *= a.kl[off];
-        a.out[off] = z;
-        if (z > 0.f) colmax[j] = fmaxf(colmax[j], z);
-        if (a.cap && gc < a.L) {
-          const float w = a.wpan[off];
-          rsum[i][r] = fmaf(o * w, g, rsum[i][r]);
-          if (a.pcomm) {
-            const double P = (double)o * (double)w * (double)g * (double)a.ucur[gr];
-            a.pcomm[(size_t)gc * a.n + gr] = P;
-          }
+        const float z = a.kl ? o * klv[r] : o;
+        if (ok) a.out[off] = z;
+        if (ok && z > 0.f) colmax[j] = fmaxf(colmax[j], z);
+        if (ok && capc) rsum[i][r] = fmaf(o * wv[r], g, rsum[i][r]);
+        if (a.pcomm && ok && capc) {
+          const double P = (double)o * (double)wv[r] * (double)g * (double)a.ucur[gr];
+          a.pcomm[(size_t)gc * a.n + gr] = P;
         }
       }
     }

@@ -170,36 +170,35 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       V acc[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] = 0;
-      if (cv) {
+      if (cv && e1 > e0) {
         for (int e = e0;; e += KB) {
           const int cnt = min(KB, e1 - e);
+          // All loads of a batch are unconditional, so the wave keeps them all in
+          // flight and a batch costs two memory latencies (entries, then rows and
+          // u).  Entries past the row end re-read the batch's first entry (CSR)
+          // or the padding (ELL rows are padded to a multiple of KB with the own
+          // index and a zero coefficient); their coefficient is masked to zero.
           int idx[KB];
-          V cf[KB];
-#pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            // ELL rows are padded to a multiple of KB: load without waiting for the row length
-            const bool in = ell || k < cnt;
-            idx[k] = in ? a.ci[e + k] : 0;
-            cf[k] = in ? a.kv[e + k] : V(0);
-            if (k >= cnt) cf[k] = V(0);
-          }
+          V cf[KB], uu[KB];
           V x[KB][NV];
 #pragma unroll
           for (int k = 0; k < KB; ++k) {
-            if (k < cnt) vld(a.xin + idx[k] * Lp + col, x[k]);
-            else {
-#pragma unroll
-              for (int v = 0; v < NV; ++v) x[k][v] = 0;
-            }
+            const int ek = (ell || k < cnt) ? e + k : e;
+            idx[k] = a.ci[ek];
+            cf[k] = a.kv[ek];
           }
+#pragma unroll
+          for (int k = 0; k < KB; ++k) vld(a.xin + idx[k] * Lp + col, x[k]);
           if (a.uin) {
 #pragma unroll
-            for (int k = 0; k < KB; ++k) if (k < cnt) cf[k] *= a.uin[idx[k]];
+            for (int k = 0; k < KB; ++k) uu[k] = a.uin[idx[k]];
           }
 #pragma unroll
           for (int k = 0; k < KB; ++k) {
+            const V ck = (ell || k < cnt) ? cf[k] : V(0);
+            const V c = a.uin ? ck * uu[k] : ck;
 #pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] = fma(cf[k], x[k][v], acc[v]);
+            for (int v = 0; v < NV; ++v) acc[v] = fma(c, x[k][v], acc[v]);
           }
           if (e + KB >= e1) break;
         }
@@ -213,30 +212,29 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       V m[NV], sm[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) { m[v] = ninf<V>(); sm[v] = 0; }
-      if (cv) {
+      if (cv && e1 > e0) {
         for (int e = e0;; e += KB) {
           const int cnt = min(KB, e1 - e);
+          // batch loads as in the linear domain (masked coefficient: -inf)
           int idx[KB];
-          V cf[KB];
-#pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            const bool in = ell || k < cnt;
-            idx[k] = in ? a.ci[e + k] : 0;
-            cf[k] = in ? a.kv[e + k] : ninf<V>();
-            if (k >= cnt) cf[k] = ninf<V>();
-          }
+          V cf[KB], uu[KB];
           V x[KB][NV];
 #pragma unroll
           for (int k = 0; k < KB; ++k) {
-            if (k < cnt) vld(a.xin + idx[k] * Lp + col, x[k]);
-            else {
-#pragma unroll
-              for (int v = 0; v < NV; ++v) x[k][v] = ninf<V>();
-            }
+            const int ek = (ell || k < cnt) ? e + k : e;
+            idx[k] = a.ci[ek];
+            cf[k] = a.kv[ek];
           }
+#pragma unroll
+          for (int k = 0; k < KB; ++k) vld(a.xin + idx[k] * Lp + col, x[k]);
           if (a.uin) {
 #pragma unroll
-            for (int k = 0; k < KB; ++k) if (k < cnt) cf[k] += a.uin[idx[k]];
+            for (int k = 0; k < KB; ++k) uu[k] = a.uin[idx[k]];
+          }
+#pragma unroll
+          for (int k = 0; k < KB; ++k) {
+            cf[k] = (ell || k < cnt) ? cf[k] : ninf<V>();
+            if (a.uin) cf[k] += uu[k];
           }
 #pragma unroll
           for (int v = 0; v < NV; ++v) {

@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import check
+from ._lib import MmotError, check
 from .solver import Solver, _ptr, default_options, device_problem
 
 
@@ -116,7 +116,12 @@ def serve(instances, arrivals, budget_bytes, max_iter=500, ticks_per_round=32, c
         now = time.perf_counter() - t0
         while pending and arrivals[pending[0]] <= now:
             i = pending[0]
-            tk = pool.submit(instances[i], max_iter=max_iter)
+            try:
+                tk = pool.submit(instances[i], max_iter=max_iter)
+            except MmotError as e:          # rejected at admission (e.g. invalid data)
+                pending.popleft()
+                done[i] = dict(latency=time.perf_counter() - t0 - arrivals[i], stats=None, status=e.status)
+                continue
             if tk is None:
                 break
             active[tk] = i
@@ -148,14 +153,22 @@ def serve_plain(instances, arrivals, max_iter=500, check_every=10, tol=1e-6):
         now = time.perf_counter() - t0
         if arrivals[i] > now:
             time.sleep(arrivals[i] - now)
-        S = Solver(instances[i], precision="fp32", domain="auto", check_every=check_every, tol=tol)
-        st = S.solve(max_iter)
-        S.close()
-        out[i] = dict(latency=time.perf_counter() - t0 - arrivals[i], stats=st, status=0)
+        st, status = None, 0
+        try:
+            S = Solver(instances[i], precision="fp32", domain="auto", check_every=check_every, tol=tol)
+            try:
+                st = S.solve(max_iter)
+            finally:
+                S.close()
+        except MmotError as e:              # the request fails; the service goes on
+            status = e.status
+        out[i] = dict(latency=time.perf_counter() - t0 - arrivals[i], stats=st, status=status)
     return out, time.perf_counter() - t0
 
 
 def latency_summary(results, total_s):
     lat = np.array([r["latency"] for r in results])
     return {"p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "solves_per_s": len(results) / total_s, "n": len(results)}
+            "mean_s": float(lat.mean()), "solves_per_s": len(results) / total_s, "n": len(results),
+            "failed": int(sum(1 for r in results if r["status"] != 0)),
+            "converged": int(sum(1 for r in results if r["stats"] and r["stats"]["converged"]))}

@@ -254,3 +254,80 @@ def test_dense_bf16_then_fp32_polish():
     e = rel_l1(g["P0t"], o["P0t"])
     assert rel_l1(g["Pt"], o["Pt"]) <= 1e-4
     assert e <= 1e-4, (e, e16)
+
+
+# ---------------------------------------------------------------------------
+# automatic domain choice: the scaled domain is confirmed by a probe iteration
+# ---------------------------------------------------------------------------
+
+def test_auto_probe_restarts_from_initial_scalings():
+    """AUTO keeping the scaled domain gives bit-identical iterates to SCALED."""
+    inst = instances.rgg_instance(n=400, L=32, T=10, seed=11)
+    a = gpu_outputs(inst, 10, "fp32", "auto")
+    b = gpu_outputs(inst, 10, "fp32", "scaled")
+    assert a["stats"]["domain"] == 1 and a["iters"] == 10
+    assert np.array_equal(a["Pt"], b["Pt"])
+    assert np.array_equal(a["flows"], b["flows"])
+    assert a["stats"]["dual_obj"] == b["stats"]["dual_obj"]
+
+
+def test_auto_switches_to_log_when_the_scaled_range_is_exceeded():
+    """A fine random geometric graph whose far commodities need ~50 forced moves:
+    the walk-count ratio between states exceeds FP32's exponent range, so the
+    scaled domain meets a zero message at a source entry; AUTO must run in the
+    log domain instead, identically to an explicit LOG solver."""
+    from paper_2106_14485_amd._lib import MmotError
+    reqs = instances.serve_trace(num=32, rate=1.0, seed=0, n_range=(200, 10000), L_range=(1, 512))
+    inst = instances.instance_from_request(reqs[10])
+    assert (inst.n, inst.L, inst.T) == (3876, 27, 55)
+    Solver = _solver()
+    S = Solver(inst, precision="fp32", domain="scaled")
+    S.iterate(1)
+    with pytest.raises(MmotError):
+        S.stats()
+    S.close()
+    a = gpu_outputs(inst, 5, "fp32", "auto")
+    b = gpu_outputs(inst, 5, "fp32", "log")
+    assert a["stats"]["domain"] == 2 and a["iters"] == 5
+    assert np.array_equal(a["Pt"], b["Pt"])
+    assert a["stats"]["dual_obj"] == b["stats"]["dual_obj"]
+
+
+# ---------------------------------------------------------------------------
+# road grid (Zipf origins/destinations, weak relays): log domain at scale
+# ---------------------------------------------------------------------------
+
+def test_road_grid_small_log_domain():
+    inst = instances.road_grid_instance(side=12, L=30, T=24, eps=0.05, seed=4)
+    o = oracle_outputs(inst, 20, log=True)
+    g = gpu_outputs(inst, 20, "fp32", "auto")
+    assert g["stats"]["domain"] == 2
+    compare(g, o, 1e-5)
+    g64 = gpu_outputs(inst, 20, "fp64", "log")
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+
+
+def test_road_grid_full_size_invariants():
+    """The 100 x 100 road grid with 2000 commodities and T = 120 (9.6 GB of stored
+    messages): too large for the oracle, so the properties every iterate has are
+    checked -- per-commodity mass equal at all times, the sink marginal exact
+    after the sink update, capacity scalings in (0, 1], non-negative occupancy,
+    and a dual objective that does not decrease (block coordinate ascent)."""
+    inst = instances.road_grid_instance()
+    Solver = _solver()
+    S = Solver(inst, precision="fp32", domain="auto")
+    g_prev = -np.inf
+    for _ in range(3):
+        S.iterate(1)
+        st = S.stats()
+        assert st["domain"] == 2
+        assert st["dual_obj"] >= g_prev - 1e-5 * abs(st["dual_obj"])
+        g_prev = st["dual_obj"]
+        assert st["mass_drift"] < 1e-4
+    occ = S.occupancy().cpu().numpy()
+    assert np.isfinite(occ).all() and (occ >= 0).all()
+    mass = inst.src.sum()
+    assert np.abs(occ.sum(axis=1) - mass).max() <= 1e-4 * mass
+    ls, ld, lc = (d.cpu().numpy() for d in S.log_duals())
+    assert (lc[np.isfinite(lc)] <= 1e-6).all()
+    S.close()
