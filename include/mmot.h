@@ -197,15 +197,24 @@ mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double
  * Serving pool: continuous batching of many solves on one GPU.
  *
  * Each admitted request is a solver (FP32, CSR) whose scalings and messages
- * stay resident in its own caller-provided workspace.  mmot_pool_run advances
- * all running requests together: one launch ("tick") executes the next kernel
- * of every running request's schedule, so small solves share the GPU.  A
- * request's schedule is exactly the one mmot_solve would run (check_every
- * iterations, then a convergence check, until converged or max_iter), so its
- * result is bitwise the same alone, in any mix, and as a plain solver.
- * Admission is by HBM footprint: the sum of admitted workspace sizes never
- * exceeds the budget.  All work goes to the pool's stream; the pool keeps
- * small pinned/device staging buffers for its per-tick work lists.
+ * stay resident in its own caller-provided workspace.  Requests run in one of
+ * two kinds of lane, chosen at admission from the size of one sweep step:
+ *  - batched lane (steps too small to fill the GPU): the request's schedule is
+ *    recorded as a list of kernel work items and kept on the device; one
+ *    launch ("tick", on the pool's stream) runs the next item of every batched
+ *    request at once, so many small solves share the GPU;
+ *  - dedicated lanes (steps that fill the GPU alone): the request runs its
+ *    own captured iteration graphs on one of three pool-owned streams, next to
+ *    the batched lane.
+ * Either way a request's schedule is exactly the one mmot_solve would run
+ * (check_every iterations, then a convergence check, until converged or
+ * max_iter), so its result is bitwise the same alone, in any mix, and as a
+ * plain solver.  Admission is by HBM footprint: the sum of admitted workspace
+ * sizes never exceeds the budget.  Set-up work (validation, operators, the
+ * domain probe) runs on a pool-owned stream and does not wait for queued
+ * ticks.  Besides the workspaces, the pool allocates small device and pinned
+ * buffers for each batched request's recorded work items (about 340 bytes per
+ * kernel of a check_every-iteration chunk) and frees them at release.
  * ------------------------------------------------------------------------- */
 typedef struct mmot_pool mmot_pool;
 
@@ -216,12 +225,16 @@ mmot_status mmot_pool_create(size_t hbm_budget, void* stream, mmot_pool** out);
  * workspace size; the caller keeps it alive until mmot_pool_release) and
  * schedules it.  EAGAIN when admitting it would exceed the budget (nothing is
  * done; retry after a release); EUNSUPPORTED unless CSR and MMOT_FP32.
- * *ticket identifies the request.  Synchronises the pool stream. */
+ * *ticket identifies the request.  Synchronous with respect to its own set-up
+ * only. */
 mmot_status mmot_pool_submit(mmot_pool* pool, const mmot_problem* prob, const mmot_options* opt, void* ws,
                              size_t ws_bytes, int32_t max_iter, uint64_t* ticket);
 
-/* Run up to max_ticks batched launches (returns early when nothing is
- * running); *n_running (nullable) receives the number of unfinished requests. */
+/* Collect finished chunks, schedule the next ones, and launch up to max_ticks
+ * ticks of the batched lane (returns early when no batched request has work
+ * ready; dedicated lanes run on their own).  The host runs at most 16 ticks
+ * ahead of the device.  *n_running (nullable) receives the number of
+ * unfinished requests. */
 mmot_status mmot_pool_run(mmot_pool* pool, int32_t max_ticks, int32_t* n_running);
 
 /* State of a request: *state = 0 running, 1 converged or max_iter reached,
@@ -230,7 +243,8 @@ mmot_status mmot_pool_run(mmot_pool* pool, int32_t max_ticks, int32_t* n_running
 mmot_status mmot_pool_poll(mmot_pool* pool, uint64_t ticket, int32_t* state, mmot_stats* stats);
 
 /* The solver of a request (for mmot_occupancy / mmot_edge_flows /
- * mmot_get_log_duals on finished requests); NULL for an unknown ticket. */
+ * mmot_get_log_duals on finished requests, which then run on the pool's
+ * stream); NULL for an unknown ticket. */
 mmot_solver* mmot_pool_solver(mmot_pool* pool, uint64_t ticket);
 
 /* Free a finished request's slot and budget (EAGAIN while it is running). */

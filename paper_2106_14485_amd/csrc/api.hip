@@ -37,7 +37,8 @@ template <typename V> void launch_build_ell(const int*, const int*, const V*, in
 // sweep_sparse.hip
 template <typename V, bool LOG> void launch_step(const StepArgs<V>&, int, int, hipStream_t);
 template <typename V, bool LOG>
-void launch_source(int, int, int, int, const V*, const V*, V*, uint32_t*, int, size_t, int*, int, hipStream_t);
+void launch_source(int, int, int, int, const V*, const V*, V*, uint32_t*, int, size_t, int*, unsigned long long*, int,
+                   size_t, int, hipStream_t);
 template <typename V, bool LOG>
 void launch_check0(int, int, int, int, int, const V*, const V*, const V*, const double*, const double*, double*,
                    double*, double*, int, hipStream_t);
@@ -51,6 +52,7 @@ void launch_prep_fwd(int, int, int, const double*, double*, const double*, V*, V
                      int, hipStream_t);
 void launch_growth(double*, const float*, int, int, int, hipStream_t);
 void launch_levels(uint32_t*, float*, int, int, int, hipStream_t);
+void launch_levels64(unsigned long long*, uint32_t*, float*, int, int, int, int, hipStream_t);
 void launch_reduce_stats(const double*, int, int, double*, double, double*, hipStream_t);
 void launch_reduce_cost(const double*, const double*, int, int, double*, double*, double*, hipStream_t);
 // dense_mfma.hip
@@ -79,7 +81,7 @@ void launch_dense_sink(int, int, int, const float*, const float*, float*, int, c
                        uint32_t*, int, uint32_t*, size_t, int*, double*, double*, double*, int, hipStream_t);
 void launch_dense_gibbs(const double*, int, int, double, float*, float*, void*, void*, hipStream_t);
 void launch_dense_rowsum_max(const float*, int, int, uint32_t*, hipStream_t);
-void launch_pool_tick(const PoolItem*, const int*, int, int, hipStream_t);
+void launch_pool_tick(const TickArgs&, hipStream_t);
 
 // ---- recording of kernel launches into serving-pool work items ----
 struct Recorder {
@@ -142,6 +144,9 @@ struct mmot_solver {
   double *cb = nullptr, *cf = nullptr, *sigb = nullptr, *sigf = nullptr, *gauge0 = nullptr, *gaugeT = nullptr;
   void *facb = nullptr, *facf = nullptr, *wgt = nullptr;
   uint32_t *slots_b = nullptr, *slots_f = nullptr, *slotsE = nullptr, *slotsS = nullptr, *rho = nullptr;
+  // log domain calibration keys (plan level, stored value), sparse path only
+  unsigned long long *cslots_b = nullptr, *cslots_f = nullptr;
+  int ncslot = 1;
   double *lvlT = nullptr, *lvl0 = nullptr;
   float *levb = nullptr, *levf = nullptr;
   double *part = nullptr, *tpart = nullptr, *stats_dev = nullptr, *masses = nullptr;
@@ -191,6 +196,7 @@ void set_geometry(mmot_solver* s) {
   nblk = (nblk + 7) / 8 * 8;
   s->nblk = nblk;
   s->nslot = std::max(1, std::min(32, nblk / 16));
+  s->ncslot = std::min(s->nslot, 8);
   if (s->kind == MMOT_DENSE) {
     s->lda = (s->n + 7) / 8 * 8;
     s->ntn = gemm_col_tiles(s->Lp);
@@ -234,6 +240,10 @@ void carve(mmot_solver* s, Carver& c) {
   s->slots_f = c.take<uint32_t>((size_t)s->nslot * (T + 1) * Lp);
   s->slotsE = c.take<uint32_t>((size_t)s->nslot * Lp);
   s->slotsS = c.take<uint32_t>((size_t)s->nslot * Lp);
+  if (!dense) {
+    s->cslots_b = c.take<unsigned long long>((size_t)s->ncslot * (T + 1) * Lp);
+    s->cslots_f = c.take<unsigned long long>((size_t)s->ncslot * (T + 1) * Lp);
+  }
   s->lvlT = c.take<double>(Lp);
   s->lvl0 = c.take<double>(Lp);
   s->levb = c.take<float>((T + 1) * Lp);
@@ -309,6 +319,8 @@ struct Impl {
     a.eps = s->eps;
     a.nslot = s->nslot;
     a.nslot_stride = (size_t)(s->T + 1) * s->Lp;
+    a.ncslot = s->ncslot;
+    a.cslot_stride = (size_t)(s->T + 1) * s->Lp;
     a.flags = s->flags;
     return a;
   }
@@ -383,14 +395,19 @@ struct Impl {
     a.out = psi(s, t);
     a.kl = (s->has_kl && t >= 1) ? static_cast<const V*>(s->KL) : nullptr;
     a.epi = 0;
-    a.slots = calib ? s->slots_b + (size_t)t * s->Lp : nullptr;
+    // log domain: the backward panels are calibrated on their values at the plan
+    // peak, recorded by the forward sweep (and the source update for t = 0)
+    a.slots = (calib && !LOG) ? s->slots_b + (size_t)t * s->Lp : nullptr;
     return a;
   }
 
   static void backward(mmot_solver* s, bool consume, bool calib, hipStream_t st) {
     const int T = s->T;
     if (consume) {
-      launch_levels(s->slots_b, s->levb, T + 1, s->Lp, s->nslot, st);
+      if (LOG && s->cslots_b)
+        launch_levels64(s->cslots_b, s->slots_b, s->levb, T + 1, s->Lp, s->ncslot, s->nslot, st);
+      else
+        launch_levels(s->slots_b, s->levb, T + 1, s->Lp, s->nslot, st);
       launch_growth(s->cb, s->levb, T, s->Lp, 0, st);
     }
     launch_prep_bwd<V, LOG>(T, s->Lp, s->cb, s->sigb, static_cast<V*>(s->facb), s->gaugeT, s->lvlT, s->slotsE,
@@ -426,7 +443,14 @@ struct Impl {
       a.wgt = static_cast<const V*>(s->wgt) + (size_t)to * Lp;
       a.cap = static_cast<const V*>(s->cap) + (size_t)(to - 1) * s->n;
       a.uout = static_cast<V*>(s->u) + (size_t)(to - 1) * s->n;
-      a.slots = (mode == 0 && calib) ? s->slots_f + (size_t)to * Lp : nullptr;
+      if (mode == 0 && calib) {
+        if (LOG) {
+          a.cslots_b = s->cslots_b + (size_t)to * Lp;
+          a.cslots_f = s->cslots_f + (size_t)to * Lp;
+        } else {
+          a.slots = s->slots_f + (size_t)to * Lp;
+        }
+      }
     } else {
       a.epi = 2;
       a.rdst = static_cast<const V*>(s->R0T);
@@ -436,8 +460,9 @@ struct Impl {
       if (mode == 0) {
         a.slots = s->slotsE;             // exact level of the new U0T panel, every iteration
         a.nslot_stride = Lp;
-        a.slots_o = calib ? s->slots_f + (size_t)T * Lp : nullptr;
+        a.slots_o = (calib && !LOG) ? s->slots_f + (size_t)T * Lp : nullptr;
         a.nslot_stride_o = (size_t)(T + 1) * Lp;
+        if (calib && LOG) a.cslots_f = s->cslots_f + (size_t)T * Lp;
       }
     }
     return a;
@@ -453,9 +478,13 @@ struct Impl {
     if (mode == 0) {
       // source update first: its output level feeds the offsets of the sweep
       launch_source<V, LOG>(s->n, s->Lp, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->R01),
-                            static_cast<V*>(s->U01), s->slotsS, s->nslot, Lp, s->flags, s->nblk, st);
+                            static_cast<V*>(s->U01), s->slotsS, s->nslot, Lp, s->flags,
+                            (LOG && calib) ? s->cslots_b : nullptr, s->ncslot, (size_t)(T + 1) * Lp, s->nblk, st);
       if (consume) {
-        launch_levels(s->slots_f, s->levf, T + 1, s->Lp, s->nslot, st);
+        if (LOG && s->cslots_f)
+          launch_levels64(s->cslots_f, s->slots_f, s->levf, T + 1, s->Lp, s->ncslot, s->nslot, st);
+        else
+          launch_levels(s->slots_f, s->levf, T + 1, s->Lp, s->nslot, st);
         launch_growth(s->cf, s->levf, T, s->Lp, 1, st);
       }
     }
@@ -602,6 +631,10 @@ struct Impl {
     launch_fill<uint32_t>(s->slots_f, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
     launch_fill<uint32_t>(s->slotsE, (size_t)s->nslot * Lp, 0u, st);
     launch_fill<uint32_t>(s->slotsS, (size_t)s->nslot * Lp, 0u, st);
+    if (s->cslots_b) {
+      launch_fill<uint32_t>(reinterpret_cast<uint32_t*>(s->cslots_b), 2 * (size_t)s->ncslot * (T + 1) * Lp, 0u, st);
+      launch_fill<uint32_t>(reinterpret_cast<uint32_t*>(s->cslots_f), 2 * (size_t)s->ncslot * (T + 1) * Lp, 0u, st);
+    }
     launch_fill<double>(s->lvlT, Lp, 0.0, st);
     launch_fill<double>(s->lvl0, Lp, 0.0, st);
     launch_init_offsets(s->cb, s->cf, s->gauge0, s->gaugeT, s->T, s->Lp, s->rho, st);
@@ -967,40 +1000,51 @@ int64_t mmot_iterations(const mmot_solver* s) { return s ? s->iters : -1; }
 // ---------------------------------------------------------------------------
 struct mmot_pool {
   size_t budget = 0, used = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;       // batched lane: the tick launches
+  hipStream_t setup = nullptr;        // admission work (validation, operators, probe)
+  static constexpr int kLanes = 3;    // dedicated lanes: solves whose steps fill the GPU alone
+  hipStream_t lanes[kLanes] = {nullptr, nullptr, nullptr};
+  int lane_rr = 0;
   uint64_t next_ticket = 1;
   struct Req {
-    uint64_t ticket;
-    mmot_solver* s;
-    size_t bytes;
-    int32_t max_iter;
+    uint64_t ticket = 0;
+    mmot_solver* s = nullptr;
+    size_t bytes = 0;
+    int32_t max_iter = 0;
     int32_t state = 0;       // 0 running, 1 done, 2 failed
     int32_t status = MMOT_OK;
-    std::vector<PoolItem> prog;
-    size_t pc = 0;
-    bool awaiting = false;
+    int lane = -1;           // -1: batched lane, else index of its dedicated stream
+    // batched lane: the current chunk's program, resident on the device
+    PoolItem* d_prog = nullptr;
+    PoolItem* h_prog = nullptr;
+    int prog_cap = 0, len = 0, maxblk = 0;
+    int64_t base = 0;        // tick that runs the chunk's first item
+    bool awaiting = false;   // chunk enqueued, its statistics not yet read
     hipEvent_t ev = nullptr;
     mmot_stats stats{};
     int iters_planned = 0;
   };
   std::map<uint64_t, Req*> reqs;
-  // device item/prefix buffers and pinned staging ring
-  static constexpr int kRing = 4;
-  int cap_items = 0;
-  PoolItem* d_items[kRing] = {nullptr};
-  int* d_prefix[kRing] = {nullptr};
-  PoolItem* h_items[kRing] = {nullptr};
-  int* h_prefix[kRing] = {nullptr};
-  hipEvent_t ring_ev[kRing] = {nullptr};
-  int ring_pos = 0;
   int64_t ticks = 0;
+  static constexpr int kLead = 16;    // ticks the host may run ahead of the device
+  hipEvent_t lead_ev[kLead] = {};
 };
 
 namespace {
 
-// Record the next chunk of a request's work: the same calls mmot_solve makes
-// (check_every iterations, then the check pass up to its stats reduction).
-void pool_program(mmot_pool::Req* r) {
+constexpr int kFillBlocks = 256;      // a step of at least this many blocks fills the GPU alone
+
+void free_prog(mmot_pool::Req* r) {
+  if (r->d_prog) (void)hipFree(r->d_prog);
+  if (r->h_prog) (void)hipHostFree(r->h_prog);
+  r->d_prog = r->h_prog = nullptr;
+  r->prog_cap = 0;
+}
+
+// Batched lane: record the next chunk of a request's work -- the same calls
+// mmot_solve makes (check_every iterations, then the check pass up to its
+// statistics reduction) -- and upload it; it starts at the next tick.
+mmot_status pool_program(mmot_pool* P, mmot_pool::Req* r) {
   mmot_solver* s = r->s;
   const int k = std::min(s->opt.check_every, r->max_iter - r->iters_planned);
   Recorder rec;
@@ -1014,36 +1058,58 @@ void pool_program(mmot_pool::Req* r) {
   s->opt.use_graph = saved_graph;
   tl_recorder = nullptr;
   r->iters_planned += k;
-  r->prog = std::move(rec.items);
-  r->pc = 0;
-  r->awaiting = false;
-}
-
-mmot_status pool_grow(mmot_pool* P, int need) {
-  if (need <= P->cap_items) return MMOT_OK;
-  int cap = std::max(64, P->cap_items * 2);
-  while (cap < need) cap *= 2;
-  (void)hipStreamSynchronize(P->stream);
-  for (int i = 0; i < mmot_pool::kRing; ++i) {
-    // the pool's staging buffers are its own host/device bookkeeping, sized to the active set
-    if (P->d_items[i]) (void)hipFree(P->d_items[i]);
-    if (P->d_prefix[i]) (void)hipFree(P->d_prefix[i]);
-    if (P->h_items[i]) (void)hipHostFree(P->h_items[i]);
-    if (P->h_prefix[i]) (void)hipHostFree(P->h_prefix[i]);
-    if (hipMalloc(reinterpret_cast<void**>(&P->d_items[i]), sizeof(PoolItem) * cap) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&P->d_prefix[i]), sizeof(int) * (cap + 1)) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&P->h_items[i]), sizeof(PoolItem) * cap, 0) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&P->h_prefix[i]), sizeof(int) * (cap + 1), 0) != hipSuccess)
+  const int n = (int)rec.items.size();
+  if (n > r->prog_cap) {
+    // the previous chunk has run to completion (its statistics were read), so
+    // no queued tick refers to the old buffers
+    free_prog(r);
+    if (hipMalloc(reinterpret_cast<void**>(&r->d_prog), sizeof(PoolItem) * n) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&r->h_prog), sizeof(PoolItem) * n, 0) != hipSuccess) {
+      free_prog(r);
       return MMOT_EHIP;
+    }
+    r->prog_cap = n;
   }
-  P->cap_items = cap;
+  int mb = 0;
+  for (int i = 0; i < n; ++i) { r->h_prog[i] = rec.items[i]; mb = std::max(mb, rec.items[i].nblk); }
+  if (hipMemcpyAsync(r->d_prog, r->h_prog, sizeof(PoolItem) * n, hipMemcpyHostToDevice, P->stream) != hipSuccess)
+    return MMOT_EHIP;
+  r->len = n;
+  r->maxblk = mb;
+  r->base = P->ticks;
+  r->awaiting = false;
   return MMOT_OK;
 }
 
-// a request whose program finished: read its stats (event completed)
-void pool_finish_chunk(mmot_pool* P, mmot_pool::Req* r) {
+// enqueue the copy of a request's statistics and flags behind its chunk
+mmot_status pool_fetch_stats(mmot_pool::Req* r, hipStream_t st) {
   mmot_solver* s = r->s;
-  (void)P;
+  if (hipMemcpyAsync(s->host_stats, s->stats_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(s->host_flags, s->flags, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipEventRecord(r->ev, st) != hipSuccess)
+    return MMOT_EHIP;
+  r->awaiting = true;
+  return MMOT_OK;
+}
+
+// Dedicated lane: enqueue the next chunk with the solver's own launches
+// (captured iteration graphs, then the check pass) on the lane's stream.
+mmot_status lane_chunk(mmot_pool::Req* r) {
+  mmot_solver* s = r->s;
+  const int k = std::min(s->opt.check_every, r->max_iter - r->iters_planned);
+  mmot_status st = run_iterations(s, k);
+  if (st != MMOT_OK) return st;
+  st = check_pass(s, nullptr, nullptr, nullptr);
+  if (st != MMOT_OK) return st;
+  launch_reduce_stats(s->part, s->nblk, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
+  r->iters_planned += k;
+  return pool_fetch_stats(r, s->stream);
+}
+
+// a chunk whose statistics have landed: decide, and schedule the next one
+mmot_status pool_finish_chunk(mmot_pool* P, mmot_pool::Req* r) {
+  mmot_solver* s = r->s;
+  r->awaiting = false;
   mmot_stats& o = r->stats;
   const int f = *s->host_flags;
   o.iters = (int32_t)s->iters;
@@ -1059,9 +1125,20 @@ void pool_finish_chunk(mmot_pool* P, mmot_pool::Req* r) {
   mmot_status st = MMOT_OK;
   if (f & FLAG_INFEASIBLE) st = MMOT_EINFEASIBLE;
   else if ((f & FLAG_NONFINITE) || s->host_stats[6] > 0 || !std::isfinite(s->host_stats[0])) st = MMOT_ENUMERIC;
-  if (st != MMOT_OK) { r->state = 2; r->status = st; return; }
-  if (o.converged || r->iters_planned >= r->max_iter) { r->state = 1; return; }
-  pool_program(r);
+  if (st == MMOT_OK && !o.converged && r->iters_planned < r->max_iter)
+    return r->lane >= 0 ? lane_chunk(r) : pool_program(P, r);
+  r->state = st == MMOT_OK ? 1 : 2;
+  r->status = st;
+  // finished: the solver's work has completed (its event fired); later output
+  // calls on it run on the pool's stream, ordered with the caller's work there
+  s->stream = P->stream;
+  return MMOT_OK;
+}
+
+void pool_sync_all(mmot_pool* P) {
+  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  for (int i = 0; i < mmot_pool::kLanes; ++i)
+    if (P->lanes[i]) (void)hipStreamSynchronize(P->lanes[i]);
 }
 
 }  // namespace
@@ -1072,8 +1149,12 @@ mmot_status mmot_pool_create(size_t hbm_budget, void* stream, mmot_pool** out) {
   if (!P) return MMOT_ENOMEM;
   P->budget = hbm_budget;
   P->stream = static_cast<hipStream_t>(stream);
-  for (int i = 0; i < mmot_pool::kRing; ++i)
-    if (hipEventCreateWithFlags(&P->ring_ev[i], hipEventDisableTiming) != hipSuccess) { mmot_pool_destroy(P); return MMOT_EHIP; }
+  bool ok = hipStreamCreateWithFlags(&P->setup, hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; ok && i < mmot_pool::kLanes; ++i)
+    ok = hipStreamCreateWithFlags(&P->lanes[i], hipStreamNonBlocking) == hipSuccess;
+  for (int i = 0; ok && i < mmot_pool::kLead; ++i)
+    ok = hipEventCreateWithFlags(&P->lead_ev[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) { mmot_pool_destroy(P); return MMOT_EHIP; }
   *out = P;
   return MMOT_OK;
 }
@@ -1086,8 +1167,10 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
   mmot_status st = mmot_query_workspace(prob, opt, &need);
   if (st != MMOT_OK) return st;
   if (P->used + need > P->budget) return MMOT_EAGAIN;
+  // set-up runs on the pool's own set-up stream and ends synchronised, so it
+  // never waits for queued ticks; the solver then moves to its lane
   mmot_solver* s = nullptr;
-  st = mmot_create(prob, opt, ws, ws_bytes, P->stream, &s);
+  st = mmot_create(prob, opt, ws, ws_bytes, P->setup, &s);
   if (st != MMOT_OK) return st;
   auto* r = new (std::nothrow) mmot_pool::Req();
   if (!r) { mmot_destroy(s); return MMOT_ENOMEM; }
@@ -1096,7 +1179,16 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
   r->bytes = need;
   r->max_iter = max_iter;
   if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) { mmot_destroy(s); delete r; return MMOT_EHIP; }
-  pool_program(r);
+  if (s->nblk >= kFillBlocks) {
+    r->lane = P->lane_rr;
+    P->lane_rr = (P->lane_rr + 1) % mmot_pool::kLanes;
+    s->stream = P->lanes[r->lane];
+    st = lane_chunk(r);
+  } else {
+    s->stream = P->stream;
+    st = pool_program(P, r);
+  }
+  if (st != MMOT_OK) { mmot_destroy(s); (void)hipEventDestroy(r->ev); free_prog(r); delete r; return st; }
   P->used += need;
   P->reqs[r->ticket] = r;
   *ticket = r->ticket;
@@ -1106,57 +1198,43 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
 mmot_status mmot_pool_run(mmot_pool* P, int32_t max_ticks, int32_t* n_running) {
   if (!P || max_ticks < 0) return MMOT_EINVAL;
   for (int tk = 0; tk < max_ticks; ++tk) {
-    // collect finished chunks (stats copies that have landed)
-    std::vector<mmot_pool::Req*> act;
-    bool waiting = false;
+    // chunks whose statistics have landed: decide and schedule the next chunk
     for (auto& kv : P->reqs) {
       mmot_pool::Req* r = kv.second;
-      if (r->state != 0) continue;
-      if (r->awaiting) {
-        if (hipEventQuery(r->ev) == hipSuccess) pool_finish_chunk(P, r);
-        else { waiting = true; continue; }
-        if (r->state != 0) continue;
+      if (r->state == 0 && r->awaiting && hipEventQuery(r->ev) == hipSuccess) {
+        const mmot_status st = pool_finish_chunk(P, r);
+        if (st != MMOT_OK) { r->state = 2; r->status = st; }
       }
-      if (r->pc < r->prog.size()) act.push_back(r);
     }
-    if (act.empty()) {
-      if (!waiting) break;
-      // only stats copies in flight: wait for the oldest, then continue
-      for (auto& kv : P->reqs)
-        if (kv.second->state == 0 && kv.second->awaiting) { (void)hipEventSynchronize(kv.second->ev); break; }
-      continue;
-    }
-    if (pool_grow(P, (int)act.size()) != MMOT_OK) return MMOT_EHIP;
-    const int slot = P->ring_pos;
-    P->ring_pos = (P->ring_pos + 1) % mmot_pool::kRing;
-    (void)hipEventSynchronize(P->ring_ev[slot]);   // staging buffer free again
-    PoolItem* hi = P->h_items[slot];
-    int* hp = P->h_prefix[slot];
+    // one tick of the batched lane: the next item of every batched request
+    TickArgs ta;
+    ta.nslot = 0;
     int total = 0;
-    for (size_t i = 0; i < act.size(); ++i) {
-      mmot_pool::Req* r = act[i];
-      hi[i] = r->prog[r->pc++];
-      hp[i] = total;
-      total += hi[i].nblk;
+    for (auto& kv : P->reqs) {
+      mmot_pool::Req* r = kv.second;
+      if (r->state != 0 || r->lane >= 0 || r->awaiting) continue;
+      const int64_t idx = P->ticks - r->base;
+      if (idx < 0 || idx >= r->len || ta.nslot == kTickSlots) continue;
+      ta.prefix[ta.nslot] = total;
+      ta.idx[ta.nslot] = (int)idx;
+      ta.prog[ta.nslot] = r->d_prog;
+      total += r->maxblk;
+      ++ta.nslot;
     }
-    hp[act.size()] = total;
-    const int ni = (int)act.size();
-    if (hipMemcpyAsync(P->d_items[slot], hi, sizeof(PoolItem) * ni, hipMemcpyHostToDevice, P->stream) != hipSuccess ||
-        hipMemcpyAsync(P->d_prefix[slot], hp, sizeof(int) * (ni + 1), hipMemcpyHostToDevice, P->stream) != hipSuccess)
-      return MMOT_EHIP;
-    launch_pool_tick(P->d_items[slot], P->d_prefix[slot], ni, total, P->stream);
-    if (hipEventRecord(P->ring_ev[slot], P->stream) != hipSuccess) return MMOT_EHIP;
+    ta.prefix[ta.nslot] = total;
+    if (ta.nslot == 0) break;   // nothing batched to run now: let the caller admit and poll
+    const int li = (int)(P->ticks % mmot_pool::kLead);
+    if (P->ticks >= mmot_pool::kLead) (void)hipEventSynchronize(P->lead_ev[li]);
+    launch_pool_tick(ta, P->stream);
+    if (hipEventRecord(P->lead_ev[li], P->stream) != hipSuccess) return MMOT_EHIP;
+    // requests whose chunk ended with this tick: fetch their statistics
+    for (auto& kv : P->reqs) {
+      mmot_pool::Req* r = kv.second;
+      if (r->state != 0 || r->lane >= 0 || r->awaiting) continue;
+      if (P->ticks - r->base == r->len - 1)
+        if (pool_fetch_stats(r, P->stream) != MMOT_OK) return MMOT_EHIP;
+    }
     ++P->ticks;
-    // requests whose chunk ended with this tick: copy their stats back asynchronously
-    for (mmot_pool::Req* r : act) {
-      if (r->pc < r->prog.size()) continue;
-      mmot_solver* s = r->s;
-      if (hipMemcpyAsync(s->host_stats, s->stats_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
-          hipMemcpyAsync(s->host_flags, s->flags, sizeof(int), hipMemcpyDeviceToHost, P->stream) != hipSuccess ||
-          hipEventRecord(r->ev, P->stream) != hipSuccess)
-        return MMOT_EHIP;
-      r->awaiting = true;
-    }
   }
   if (n_running) {
     int c = 0;
@@ -1170,9 +1248,14 @@ mmot_status mmot_pool_poll(mmot_pool* P, uint64_t ticket, int32_t* state, mmot_s
   if (!P || !state) return MMOT_EINVAL;
   auto it = P->reqs.find(ticket);
   if (it == P->reqs.end()) return MMOT_EINVAL;
-  *state = it->second->state;
-  if (stats) *stats = it->second->stats;
-  return it->second->state == 2 ? (mmot_status)it->second->status : MMOT_OK;
+  mmot_pool::Req* r = it->second;
+  if (r->state == 0 && r->awaiting && hipEventQuery(r->ev) == hipSuccess) {
+    const mmot_status st = pool_finish_chunk(P, r);
+    if (st != MMOT_OK) { r->state = 2; r->status = st; }
+  }
+  *state = r->state;
+  if (stats) *stats = r->stats;
+  return r->state == 2 ? (mmot_status)r->status : MMOT_OK;
 }
 
 mmot_solver* mmot_pool_solver(mmot_pool* P, uint64_t ticket) {
@@ -1187,9 +1270,10 @@ mmot_status mmot_pool_release(mmot_pool* P, uint64_t ticket) {
   if (it == P->reqs.end()) return MMOT_EINVAL;
   mmot_pool::Req* r = it->second;
   if (r->state == 0) return MMOT_EAGAIN;
-  (void)hipStreamSynchronize(P->stream);
+  (void)hipStreamSynchronize(r->s->stream);
   mmot_destroy(r->s);
   (void)hipEventDestroy(r->ev);
+  free_prog(r);
   P->used -= r->bytes;
   delete r;
   P->reqs.erase(it);
@@ -1198,19 +1282,18 @@ mmot_status mmot_pool_release(mmot_pool* P, uint64_t ticket) {
 
 void mmot_pool_destroy(mmot_pool* P) {
   if (!P) return;
-  if (P->stream) (void)hipStreamSynchronize(P->stream);
+  pool_sync_all(P);
   for (auto& kv : P->reqs) {
     mmot_destroy(kv.second->s);
     if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
+    free_prog(kv.second);
     delete kv.second;
   }
-  for (int i = 0; i < mmot_pool::kRing; ++i) {
-    if (P->d_items[i]) (void)hipFree(P->d_items[i]);
-    if (P->d_prefix[i]) (void)hipFree(P->d_prefix[i]);
-    if (P->h_items[i]) (void)hipHostFree(P->h_items[i]);
-    if (P->h_prefix[i]) (void)hipHostFree(P->h_prefix[i]);
-    if (P->ring_ev[i]) (void)hipEventDestroy(P->ring_ev[i]);
-  }
+  for (int i = 0; i < mmot_pool::kLead; ++i)
+    if (P->lead_ev[i]) (void)hipEventDestroy(P->lead_ev[i]);
+  for (int i = 0; i < mmot_pool::kLanes; ++i)
+    if (P->lanes[i]) (void)hipStreamDestroy(P->lanes[i]);
+  if (P->setup) (void)hipStreamDestroy(P->setup);
   delete P;
 }
 

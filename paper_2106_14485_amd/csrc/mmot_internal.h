@@ -67,6 +67,13 @@ struct StepArgs {
   int nslot;
   size_t nslot_stride;
   size_t nslot_stride_o;
+  // log domain, forward calibration sweeps: per column, the stored values of the
+  // backward panel (cslots_b) and of the forward output (cslots_f) at the state
+  // where the plan Psi_hat (.) Psi peaks, as 64-bit keys (plan level, value)
+  unsigned long long* cslots_b;
+  unsigned long long* cslots_f;
+  int ncslot;
+  size_t cslot_stride;
   int* flags;
   // check pass
   double* part;         // [nblk][kNSt] stats partials of this time (nullptr = no stats)
@@ -85,6 +92,9 @@ struct SourceArgs {
   uint32_t* slots;
   size_t slot_stride;
   int* flags;
+  unsigned long long* cslots;   // log domain calibration: Psi_1 at the plan peak (time 0)
+  int ncslot;
+  size_t cslot_stride;
 };
 // statistics at time 0 (row kernel)
 template <typename V>
@@ -127,6 +137,14 @@ struct LevelsArgs {
   float* lev;
   int T1, Lp, nslot;
 };
+// lev[t][l] = stored value carried by the largest 64-bit key over the slots
+// (-inf if none; falls back to the 32-bit column-max slots); slots cleared
+struct Levels64Args {
+  unsigned long long* cslots;
+  uint32_t* slots;
+  float* lev;
+  int T1, Lp, ncslot, nslot;
+};
 struct GrowthArgs {
   double* c;
   const float* lev;
@@ -148,15 +166,25 @@ struct Reduce2Args {
 // A pool tick runs the next item of every active solve in one launch.
 enum ItemKind {
   IK_STEP_BWD = 0, IK_STEP_FWD, IK_STEP_CHK, IK_SOURCE, IK_CHECK0, IK_PREP_BWD, IK_PREP_FWD, IK_LEVELS,
-  IK_GROWTH, IK_REDUCE1, IK_REDUCE2, IK_COUNT
+  IK_GROWTH, IK_REDUCE1, IK_REDUCE2, IK_LEVELS64, IK_COUNT
 };
-constexpr int kItemArgBytes = 320;
+constexpr int kItemArgBytes = 352;
 struct alignas(16) PoolItem {
   int kind;
   int log_domain;
   int nblk;
   int pad;
   unsigned char args[kItemArgBytes];
+};
+// One pool tick, passed by value: slot r runs item idx[r] of its
+// device-resident program prog[r] with blocks prefix[r] .. prefix[r+1]-1 of
+// the launch (blocks past the item's own count return at once).
+constexpr int kTickSlots = 64;
+struct TickArgs {
+  int nslot;
+  int prefix[kTickSlots + 1];
+  int idx[kTickSlots];
+  const PoolItem* prog[kTickSlots];
 };
 // Set while a solve's program is being recorded: launchers append items
 // instead of launching (host only).

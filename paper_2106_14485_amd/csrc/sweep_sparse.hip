@@ -122,6 +122,49 @@ __device__ void calib_chunk(const V (&val)[VT<V>::N], int G, int chunk_col0, int
   __syncthreads();
 }
 
+__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long x, int m) {
+  const unsigned hi = __shfl_xor((unsigned)(x >> 32), m, 64), lo = __shfl_xor((unsigned)x, m, 64);
+  return ((unsigned long long)hi << 32) | lo;
+}
+
+// Log domain calibration: per column of the chunk, the key (plan level, value)
+// maximised over this block's rows, then atomicMax into the slot, so the slot
+// keeps the stored value at the state where the plan peaks.  Entries with a
+// non-finite plan level or value are skipped.
+template <typename V>
+__device__ void corr_chunk(const V (&pl)[VT<V>::N], const V (&val)[VT<V>::N], int G, int chunk_col0, int Lp,
+                           unsigned long long* slot) {
+  constexpr int NV = VT<V>::N;
+  __shared__ unsigned long long ck[kWaves][64 * 4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gl = lane & (G - 1);
+  unsigned long long kk[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const float p = static_cast<float>(pl[v]), x = static_cast<float>(val[v]);
+    unsigned long long key =
+        (isfinite(p) && isfinite(x)) ? (((unsigned long long)enc_f32(p) << 32) | enc_f32(x)) : 0ull;
+    for (int m = G; m < 64; m <<= 1) {
+      const unsigned long long y = shfl_xor_u64(key, m);
+      key = y > key ? y : key;
+    }
+    kk[v] = key;
+  }
+  if (lane < G) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) ck[wave][gl * NV + v] = kk[v];
+  }
+  __syncthreads();
+  const int ncol = G * NV;
+  for (int k = threadIdx.x; k < ncol; k += kBlock) {
+    unsigned long long m = ck[0][k];
+    for (int w = 1; w < kWaves; ++w) m = ck[w][k] > m ? ck[w][k] : m;
+    const int col = chunk_col0 + k;
+    if (col < Lp && m) atomicMax(slot + col, m);
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // the sweep step
 // ---------------------------------------------------------------------------
@@ -262,11 +305,18 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
 
     // ---------------- epilogue ----------------
     V z[NV];   // value stored into the output panel (and calibrated on)
+    V plT[NV];  // log domain sink: plan level at time T (= R0T after the update)
+#pragma unroll
+    for (int v = 0; v < NV; ++v) plT[v] = ninf<V>();
     if (FWD && a.epi == 2) {
       // sink: U0T = R0T ./ hatPsi_T (Algorithm 2), zero off the support
       if (cv) {
         V r[NV], cur[NV];
         vld(a.rdst + row * Lp + col, r);
+        if (LOG) {
+#pragma unroll
+          for (int v = 0; v < NV; ++v) plT[v] = r[v];
+        }
         if (!CHK) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
@@ -368,6 +418,17 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       }
     }
     if (a.slots) calib_chunk<V, LOG>(z, G, ch * G * NV, a.Lp, a.slots + (size_t)(bid % a.nslot) * a.nslot_stride);
+    if (LOG && FWD && !CHK && a.epi == 1 && a.cslots_b) {
+      // plan level at the output time: hatPsi + (Psi (.) K_L), up to per-column constants
+      V pl[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) pl[v] = cv ? o[v] + w[v] : ninf<V>();
+      const size_t cs = (size_t)(bid % a.ncslot) * a.cslot_stride;
+      corr_chunk<V>(pl, w, G, ch * G * NV, a.Lp, a.cslots_b + cs);
+      corr_chunk<V>(pl, z, G, ch * G * NV, a.Lp, a.cslots_f + cs);
+    }
+    if (LOG && FWD && !CHK && a.epi == 2 && a.cslots_f)
+      corr_chunk<V>(plT, o, G, ch * G * NV, a.Lp, a.cslots_f + (size_t)(bid % a.ncslot) * a.cslot_stride);
     if (FWD && a.slots_o) {
       if (!cv) {
 #pragma unroll
@@ -446,11 +507,17 @@ __device__ __forceinline__ void source_body(const SourceArgs<V>& A, int bid, int
   for (int ch = 0; ch < nchunk; ++ch) {
     const int col = (ch * G + gl) * NV;
     const bool cv = valid && col < Lp;
-    V z[NV];
+    V z[NV], pl[NV], xs[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) { pl[v] = ninf<V>(); xs[v] = ninf<V>(); }
     if (cv) {
       V x[NV], r[NV];
       vld(psi0 + (size_t)row * Lp + col, x);
       vld(rsrc + (size_t)row * Lp + col, r);
+      if (LOG) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) { pl[v] = r[v]; xs[v] = x[v]; }
+      }
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
         if (!LOG) {
@@ -471,6 +538,9 @@ __device__ __forceinline__ void source_body(const SourceArgs<V>& A, int bid, int
       for (int v = 0; v < NV; ++v) z[v] = LOG ? ninf<V>() : V(0);
     }
     if (slots) calib_chunk<V, LOG>(z, G, ch * G * NV, Lp, slots + (size_t)(bid % nslot) * slot_stride);
+    // log domain calibration: Psi_1 at the plan peak (the plan at time 0 is R01)
+    if (LOG && A.cslots)
+      corr_chunk<V>(pl, xs, G, ch * G * NV, Lp, A.cslots + (size_t)(bid % A.ncslot) * A.cslot_stride);
   }
 }
 template <typename V, bool LOG>
@@ -659,6 +729,34 @@ __device__ __forceinline__ void levels_body(const LevelsArgs& A, int bid, int nb
   lev[idx] = m;
 }
 __global__ void k_levels(LevelsArgs A) { levels_body(A, blockIdx.x, gridDim.x); }
+
+// Log domain: lev[t][l] = the value carried by the largest (plan level, value)
+// key over the 64-bit slots; where none was recorded, the column maximum from
+// the 32-bit slots (or -inf).  Both slot sets are cleared.
+__device__ __forceinline__ void levels64_body(const Levels64Args& A, int bid, int nblk) {
+  const int T1 = A.T1, Lp = A.Lp, ncslot = A.ncslot, nslot = A.nslot;
+  const int idx = bid * blockDim.x + threadIdx.x;
+  if (idx >= T1 * Lp) return;
+  const size_t stride = (size_t)T1 * Lp;
+  unsigned long long best = 0;
+  for (int p = 0; p < ncslot; ++p) {
+    const unsigned long long k = A.cslots[p * stride + idx];
+    if (k) {
+      best = k > best ? k : best;
+      A.cslots[p * stride + idx] = 0ull;
+    }
+  }
+  float m = -INFINITY;
+  for (int p = 0; p < nslot; ++p) {
+    const uint32_t e = A.slots[p * stride + idx];
+    if (e) {
+      m = fmaxf(m, dec_f32(e));
+      A.slots[p * stride + idx] = 0u;
+    }
+  }
+  A.lev[idx] = best ? dec_f32((uint32_t)(best & 0xffffffffull)) : m;
+}
+__global__ void k_levels64(Levels64Args A) { levels64_body(A, blockIdx.x, gridDim.x); }
 
 
 // wave-level helpers for the one-wavefront-per-commodity prep kernels
@@ -907,8 +1005,10 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
 }
 template <typename V, bool LOG>
 void launch_source(int n, int Lp, int G, int nchunk, const V* psi0, const V* rsrc, V* u01, uint32_t* slots,
-                   int nslot, size_t slot_stride, int* flags, int nblk, hipStream_t s) {
-  const SourceArgs<V> A{n, Lp, G, nchunk, nslot, psi0, rsrc, u01, slots, slot_stride, flags};
+                   int nslot, size_t slot_stride, int* flags, unsigned long long* cslots, int ncslot,
+                   size_t cslot_stride, int nblk, hipStream_t s) {
+  const SourceArgs<V> A{n, Lp, G, nchunk, nslot, psi0, rsrc, u01, slots, slot_stride, flags, cslots, ncslot,
+                        cslot_stride};
   if (record_item(IK_SOURCE, LOG, nblk, &A, sizeof(A))) return;
   hipLaunchKernelGGL((k_source<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, A);
 }
@@ -948,6 +1048,13 @@ void launch_growth(double* c, const float* lev, int T, int Lp, int dir, hipStrea
   const int nb = ((T + 1) * Lp + 255) / 256;
   if (record_item(IK_GROWTH, 0, nb, &A, sizeof(A))) return;
   hipLaunchKernelGGL(k_growth, dim3(nb), dim3(256), 0, s, A);
+}
+void launch_levels64(unsigned long long* cslots, uint32_t* slots, float* lev, int T1, int Lp, int ncslot, int nslot,
+                     hipStream_t s) {
+  const Levels64Args A{cslots, slots, lev, T1, Lp, ncslot, nslot};
+  const int nb = (T1 * Lp + 255) / 256;
+  if (record_item(IK_LEVELS64, 0, nb, &A, sizeof(A))) return;
+  hipLaunchKernelGGL(k_levels64, dim3(nb), dim3(256), 0, s, A);
 }
 void launch_levels(uint32_t* slots, float* lev, int T1, int Lp, int nslot, hipStream_t s) {
   const LevelsArgs A{slots, lev, T1, Lp, nslot};
@@ -994,18 +1101,19 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_pool_tick(const PoolItem* __restrict__ items, const int* __restrict__ prefix,
-                                                      int nitems) {
-  int lo = 0, hi = nitems - 1;
+__global__ __launch_bounds__(kBlock) void k_pool_tick(const TickArgs ta) {
+  int lo = 0, hi = ta.nslot - 1;
   const int b = blockIdx.x;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
+    if (ta.prefix[mid] <= b) lo = mid; else hi = mid - 1;
   }
-  const PoolItem& it = items[lo];
-  const int bid = b - prefix[lo];
+  const PoolItem& it = ta.prog[lo][ta.idx[lo]];
+  const int bid = b - ta.prefix[lo];
+  if (bid >= it.nblk) return;
   switch (it.kind) {
     case IK_LEVELS: levels_body(*reinterpret_cast<const LevelsArgs*>(it.args), bid, it.nblk); return;
+    case IK_LEVELS64: levels64_body(*reinterpret_cast<const Levels64Args*>(it.args), bid, it.nblk); return;
     case IK_GROWTH: growth_body(*reinterpret_cast<const GrowthArgs*>(it.args), bid, it.nblk); return;
     case IK_REDUCE1: reduce1_body(*reinterpret_cast<const Reduce1Args*>(it.args), bid, it.nblk); return;
     case IK_REDUCE2: reduce2_body(*reinterpret_cast<const Reduce2Args*>(it.args), bid, it.nblk); return;
@@ -1015,14 +1123,15 @@ __global__ __launch_bounds__(kBlock) void k_pool_tick(const PoolItem* __restrict
   else run_item<false>(it, bid);
 }
 
-void launch_pool_tick(const PoolItem* items, const int* prefix, int nitems, int total_blocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_pool_tick, dim3(total_blocks), dim3(kBlock), 0, s, items, prefix, nitems);
+void launch_pool_tick(const TickArgs& ta, hipStream_t s) {
+  if (ta.nslot > 0 && ta.prefix[ta.nslot] > 0)
+    hipLaunchKernelGGL(k_pool_tick, dim3(ta.prefix[ta.nslot]), dim3(kBlock), 0, s, ta);
 }
 
 #define MMOT_INST(V, LOG)                                                                                         \
   template void launch_step<V, LOG>(const StepArgs<V>&, int, int, hipStream_t);                                       \
   template void launch_source<V, LOG>(int, int, int, int, const V*, const V*, V*, uint32_t*, int, size_t, int*,   \
-                                      int, hipStream_t);                                                          \
+                                      unsigned long long*, int, size_t, int, hipStream_t);                        \
   template void launch_check0<V, LOG>(int, int, int, int, int, const V*, const V*, const V*, const double*,      \
                                       const double*, double*, double*, double*, int, hipStream_t);               \
   template void launch_flows<V, LOG>(int, int, int, int, int, const int*, const int*, const V*, const double*,   \

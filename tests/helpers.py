@@ -48,3 +48,32 @@ def rel_l1(a, b):
     a = np.asarray(a, dtype=np.float64); b = np.asarray(b, dtype=np.float64)
     den = np.abs(b).sum()
     return float(np.abs(a - b).sum() / (den if den > 0 else 1.0))
+
+
+def fp32_log_floor(proj, T):
+    """Precision floor of an FP32 log-domain solve, from the oracle's log messages.
+
+    The GPU log domain stores log2-messages relative to per-commodity offsets
+    centred on the state where the plan peaks, so an entry whose log-message is
+    a distance g (nats) from its value there is held with an absolute rounding
+    error up to u g, u = 2^-24, i.e. a relative error u g in the linear value.
+    A plan entry carries that error from its backward and its forward message:
+    relative error u (g_b + g_f).  The plan-weighted mean of g_b + g_f over the
+    interior times gives the first-order relative-L1 error of the marginals;
+    the floor is four times it, covering the re-rounding along the T-step
+    recursions and the exp2 / log2 instruction errors.
+    """
+    P, lpsi, lh = proj["P0t"], proj["lpsi"], proj["lpsihat"]
+    num = den = 0.0
+    for t in range(1, T):
+        b, f = lpsi[t], lh[t]
+        plan = np.where(np.isfinite(b) & np.isfinite(f), b + f, -np.inf)
+        peak = plan.argmax(axis=1)
+        rows = np.arange(b.shape[0])
+        gaps = 0.0
+        for m in (b, f):
+            ref = m[rows, peak][:, None]
+            gaps = gaps + np.where(np.isfinite(m) & np.isfinite(ref), np.abs(m - ref), 0.0)
+        num += float((P[t] * gaps).sum())
+        den += float(P[t].sum())
+    return 4.0 * 2.0 ** -24 * (num / den if den > 0 else 0.0)

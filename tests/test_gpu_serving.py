@@ -15,6 +15,8 @@ def _mix():
         instances.rgg_instance(n=900, L=70, T=20, seed=13, cap_lo=1.0, cap_hi=2.0),
         instances.road_grid_instance(side=20, L=3, T=45, eps=0.05, seed=14),
         instances.rgg_instance(n=250, L=1, T=10, seed=15),
+        # steps of 300 blocks: runs in a dedicated lane next to the batched ones
+        instances.rgg_instance(n=1200, L=256, T=14, seed=16, cap_lo=1.0, cap_hi=2.0),
     ]
 
 
@@ -82,7 +84,7 @@ def test_budget_admission_and_release():
 def test_serve_loop_latency_report():
     from paper_2106_14485_amd.serve import latency_summary, serve
     insts = _mix()
-    arrivals = np.array([0.0, 0.01, 0.02, 0.05, 0.06])
+    arrivals = np.array([0.0, 0.01, 0.02, 0.05, 0.06, 0.03])
     res, total = serve(insts, arrivals, budget_bytes=1 << 36, max_iter=40)
     s = latency_summary(res, total)
     assert s["n"] == len(insts) and s["p99_s"] >= s["p50_s"] > 0
