@@ -168,7 +168,7 @@ __device__ void corr_chunk(const V (&pl)[VT<V>::N], const V (&val)[VT<V>::N], in
 // ---------------------------------------------------------------------------
 // the sweep step
 // ---------------------------------------------------------------------------
-template <typename V, bool LOG, bool FWD, bool CHK>
+template <typename V, bool LOG, bool FWD, bool CHK, bool ELL>
 __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nblk) {
 
   constexpr int NV = VT<V>::N;
@@ -180,13 +180,27 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   const int lb = xcd_block(bid, nblk);
   const int row = (lb * kWaves + wave) * rpw + grp;
   const bool valid = row < a.n;
-  const bool ell = a.ellD > 0;
-  int e0 = 0, e1 = 0;
-  if (valid) {
-    if (ell) { e0 = row * a.ellD; e1 = e0 + a.deg[row]; }
-    else { e0 = a.rp[row]; e1 = a.rp[row + 1]; }
+  constexpr bool ell = ELL;
+  // CSR batches need the row start at once (wave-uniform for whole-wave rows).
+  // ELL rows start at a fixed offset and padding makes every batch safe to load,
+  // so the row length is only read where a batch ends; it is loaded inside the
+  // batch, behind the entry loads (the empty asm on its address keeps the load
+  // from being hoisted to the kernel start, where the first wait would stall on it).
+  const int rowc = valid ? row : 0;
+  int e0 = 0, endv = 0;
+  if (ELL) {
+    e0 = rowc * a.ellD;
+  } else {
+    e0 = a.rp[rowc];
+    endv = a.rp[rowc + 1];
+    if (G == 64) { e0 = __builtin_amdgcn_readfirstlane(e0); endv = __builtin_amdgcn_readfirstlane(endv); }
   }
-  if (G == 64) { e0 = __builtin_amdgcn_readfirstlane(e0); e1 = __builtin_amdgcn_readfirstlane(e1); }
+  auto ell_len = [&]() -> int {
+    const int* dp = a.deg + rowc;
+    asm volatile("" : "+v"(dp));
+    return *dp;
+  };
+  auto row_end = [&]() -> int { return !valid ? e0 : endv; };
   const size_t Lp = (size_t)a.Lp;
 
   V ssum = 0;                       // scaled: capacity column sum (lane partial)
@@ -199,13 +213,16 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     const bool cv = valid && col < a.Lp;
     V o[NV];
     // operands of the epilogue that do not depend on the product: issue first
+    // (unconditional loads at clamped addresses: a wave waits for them only
+    // where they are used)
     V w[NV], g[NV], f[NV];
     const bool capepi = FWD && a.epi == 1 && cv;
-    if (capepi) {
-      vld(a.wpan + row * Lp + col, w);
-      vld(a.wgt + col, g);
+    const int colc = cv ? col : 0;
+    if (FWD && a.epi == 1) {
+      vld(a.wpan + rowc * Lp + colc, w);
+      vld(a.wgt + colc, g);
     }
-    if (cv) vld(a.fac + col, f);
+    vld(a.fac + colc, f);
     // ---------------- product ----------------
     // neighbours in batches of KB: all indices, then all u values and rows are
     // requested before any of them is used, so one batch costs ~one latency
@@ -213,9 +230,9 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       V acc[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] = 0;
-      if (cv && e1 > e0) {
+      if (cv && (ell || row_end() > e0)) {
         for (int e = e0;; e += KB) {
-          const int cnt = min(KB, e1 - e);
+          const int cnt = ell ? KB : min(KB, row_end() - e);
           // All loads of a batch are unconditional, so the wave keeps them all in
           // flight and a batch costs two memory latencies (entries, then rows and
           // u).  Entries past the row end re-read the batch's first entry (CSR)
@@ -230,6 +247,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             idx[k] = a.ci[ek];
             cf[k] = a.kv[ek];
           }
+          const int len = ELL ? ell_len() : 0;
 #pragma unroll
           for (int k = 0; k < KB; ++k) vld(a.xin + idx[k] * Lp + col, x[k]);
           if (a.uin) {
@@ -243,7 +261,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v] = fma(c, x[k][v], acc[v]);
           }
-          if (e + KB >= e1) break;
+          if (e + KB >= (ELL ? e0 + len : row_end())) break;
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = acc[v] * f[v];
@@ -255,9 +273,9 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       V m[NV], sm[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) { m[v] = ninf<V>(); sm[v] = 0; }
-      if (cv && e1 > e0) {
+      if (cv && (ell || row_end() > e0)) {
         for (int e = e0;; e += KB) {
-          const int cnt = min(KB, e1 - e);
+          const int cnt = ell ? KB : min(KB, row_end() - e);
           // batch loads as in the linear domain (masked coefficient: -inf)
           int idx[KB];
           V cf[KB], uu[KB];
@@ -268,6 +286,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             idx[k] = a.ci[ek];
             cf[k] = a.kv[ek];
           }
+          const int len = ELL ? ell_len() : 0;
 #pragma unroll
           for (int k = 0; k < KB; ++k) vld(a.xin + idx[k] * Lp + col, x[k]);
           if (a.uin) {
@@ -293,7 +312,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             sm[v] = acc;
             m[v] = nm;
           }
-          if (e + KB >= e1) break;
+          if (e + KB >= (ELL ? e0 + len : row_end())) break;
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = (sm[v] > V(0)) ? m[v] + xlog2(sm[v]) + f[v] : ninf<V>();
@@ -479,9 +498,9 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   }
   if (CHK && a.part) block_stats(st, a.part, bid);
 }
-template <typename V, bool LOG, bool FWD, bool CHK>
+template <typename V, bool LOG, bool FWD, bool CHK, bool ELL>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
-  step_body<V, LOG, FWD, CHK>(a, blockIdx.x, gridDim.x);
+  step_body<V, LOG, FWD, CHK, ELL>(a, blockIdx.x, gridDim.x);
 }
 
 
@@ -999,9 +1018,15 @@ __global__ void k_reduce_cost(const double* __restrict__ tflow, const double* __
 template <typename V, bool LOG>
 void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
   if (record_item(fwd == 0 ? IK_STEP_BWD : (fwd == 1 ? IK_STEP_FWD : IK_STEP_CHK), LOG, nblk, &a, sizeof(a))) return;
-  if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false>), dim3(nblk), dim3(kBlock), 0, s, a);
-  else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true>), dim3(nblk), dim3(kBlock), 0, s, a);
-  else hipLaunchKernelGGL((k_step<V, LOG, false, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+  if (a.ellD > 0) {
+    if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+    else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_step<V, LOG, false, false, true>), dim3(nblk), dim3(kBlock), 0, s, a);
+  } else {
+    if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+    else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_step<V, LOG, false, false, false>), dim3(nblk), dim3(kBlock), 0, s, a);
+  }
 }
 template <typename V, bool LOG>
 void launch_source(int n, int Lp, int G, int nchunk, const V* psi0, const V* rsrc, V* u01, uint32_t* slots,
@@ -1090,9 +1115,23 @@ template <bool LOG>
 __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
   const void* p = it.args;
   switch (it.kind) {
-    case IK_STEP_BWD: step_body<float, LOG, false, false>(*static_cast<const StepArgs<float>*>(p), bid, it.nblk); break;
-    case IK_STEP_FWD: step_body<float, LOG, true, false>(*static_cast<const StepArgs<float>*>(p), bid, it.nblk); break;
-    case IK_STEP_CHK: step_body<float, LOG, true, true>(*static_cast<const StepArgs<float>*>(p), bid, it.nblk); break;
+    case IK_STEP_BWD:
+    case IK_STEP_FWD:
+    case IK_STEP_CHK: {
+      const StepArgs<float>& sa = *static_cast<const StepArgs<float>*>(p);
+      const bool e = sa.ellD > 0;
+      if (it.kind == IK_STEP_BWD) {
+        if (e) step_body<float, LOG, false, false, true>(sa, bid, it.nblk);
+        else step_body<float, LOG, false, false, false>(sa, bid, it.nblk);
+      } else if (it.kind == IK_STEP_FWD) {
+        if (e) step_body<float, LOG, true, false, true>(sa, bid, it.nblk);
+        else step_body<float, LOG, true, false, false>(sa, bid, it.nblk);
+      } else {
+        if (e) step_body<float, LOG, true, true, true>(sa, bid, it.nblk);
+        else step_body<float, LOG, true, true, false>(sa, bid, it.nblk);
+      }
+      break;
+    }
     case IK_SOURCE: source_body<float, LOG>(*static_cast<const SourceArgs<float>*>(p), bid, it.nblk); break;
     case IK_CHECK0: check0_body<float, LOG>(*static_cast<const Check0Args<float>*>(p), bid, it.nblk); break;
     case IK_PREP_BWD: prep_bwd_body<float, LOG>(*static_cast<const PrepBwdArgs<float>*>(p), bid, it.nblk); break;

@@ -37,6 +37,9 @@ __all__ = [
     "serve_trace",
     "instance_from_request",
     "lp_feasible",
+    "edge_state_instance",
+    "sparse_grid_edge_instance",
+    "dense_random_edge_instance",
 ]
 
 
@@ -359,6 +362,148 @@ def road_grid_instance(side: int = 100, L: int = 2000, T: int = 120, eps: float 
     return Instance(name=f"road{side}x{side}", n=n, L=L, T=T, eps=eps, kind="csr",
                     src=src, dst=dst, cap=capv, rowptr=rowptr, colidx=colidx, cost=cost,
                     meta=dict(seed=seed, origins=o, destinations=z, weak=weak))
+
+
+# ----------------------------------------------------------------------------
+# edge-state lifts (the paper's own state spaces: flows on edges)
+# ----------------------------------------------------------------------------
+def edge_state_instance(nv: int, edges: np.ndarray, L: int, T: int, eps: float, edge_cost: np.ndarray,
+                        src_vertex: np.ndarray, dst_vertex: np.ndarray, mass: np.ndarray,
+                        cap_edge, terminals: str = "storage", cap_vertex=np.inf,
+                        name: str = "edges") -> Instance:
+    """Dynamic multi-commodity flow with flow on the edges of a directed graph.
+
+    The state at a time is the edge (or terminal) a unit of flow is on
+    (Section 3.1: the marginal P_t is the flow over the edges in one time
+    interval; the transition cost C is 0 where edge i leads to edge j -- the
+    head of i is the tail of j -- and +inf otherwise, eq. T_cost; the cost of
+    using an edge is the per-commodity state cost c^l, charged at interior
+    times).  edges: (m, 2) int array of (tail, head) vertices.  edge_cost:
+    (L, m).  cap_edge: scalar or (m,) capacity of the summed flow on an edge.
+
+    terminals = "storage" (Section 3.3, storage in the vertices): the state
+    space is augmented by the vertices, n = m + nv; a vertex leads to itself
+    (storage, cost 0) and to the edges leaving it, an edge leads to the edges
+    leaving its head and to its head vertex; commodities start and end at
+    vertices; vertex capacity cap_vertex.
+    terminals = "routing" (Section 3.3, eq. cost_traffic_routing): states are
+    the edges plus one source state per distinct source vertex and one sink
+    state per distinct sink vertex; flow may wait only in its source and sink
+    states, cannot re-enter a source and cannot leave a sink; a source state
+    leads to itself and the edges leaving its vertex, an edge entering a sink
+    vertex leads to that sink state.  Terminal states are uncapacitated.
+    """
+    edges = np.asarray(edges, dtype=np.int64)
+    m = len(edges)
+    tail, head = edges[:, 0], edges[:, 1]
+    out_of = [[] for _ in range(nv)]
+    for e in range(m):
+        out_of[tail[e]].append(e)
+    rows, cols = [], []
+    for e in range(m):                      # line graph: e -> every edge leaving head(e)
+        for f in out_of[head[e]]:
+            rows.append(e); cols.append(f)
+    src_vertex = np.asarray(src_vertex); dst_vertex = np.asarray(dst_vertex)
+    if terminals == "storage":
+        n = m + nv
+        for v in range(nv):
+            rows.append(m + v); cols.append(m + v)             # storage in the vertex
+            for f in out_of[v]:
+                rows.append(m + v); cols.append(f)             # depart along an edge
+        for e in range(m):
+            rows.append(e); cols.append(m + head[e])           # arrive at the head vertex
+        s_state = m + src_vertex
+        z_state = m + dst_vertex
+        cap = np.concatenate([np.broadcast_to(np.asarray(cap_edge, dtype=np.float64), (m,)),
+                              np.broadcast_to(np.asarray(cap_vertex, dtype=np.float64), (nv,))])
+    elif terminals == "routing":
+        srcs = np.unique(src_vertex); snks = np.unique(dst_vertex)
+        sid = {int(v): m + k for k, v in enumerate(srcs)}
+        zid = {int(v): m + len(srcs) + k for k, v in enumerate(snks)}
+        n = m + len(srcs) + len(snks)
+        for v, i in sid.items():
+            rows.append(i); cols.append(i)                     # wait in the source
+            for f in out_of[v]:
+                rows.append(i); cols.append(f)
+        for v, i in zid.items():
+            rows.append(i); cols.append(i)                     # wait in the sink
+        for e in range(m):
+            if int(head[e]) in zid:
+                rows.append(e); cols.append(zid[int(head[e])])
+        s_state = np.array([sid[int(v)] for v in src_vertex])
+        z_state = np.array([zid[int(v)] for v in dst_vertex])
+        cap = np.concatenate([np.broadcast_to(np.asarray(cap_edge, dtype=np.float64), (m,)),
+                              np.full(n - m, np.inf)])
+    else:
+        raise ValueError(f"unknown terminals {terminals!r}")
+    rows = np.array(rows); cols = np.array(cols)
+    rowptr, colidx, cost = _csr_from_pairs(n, rows, cols, np.zeros(len(rows)))
+    src = np.zeros((L, n)); dst = np.zeros((L, n))
+    np.add.at(src, (np.arange(L), s_state), mass)
+    np.add.at(dst, (np.arange(L), z_state), mass)
+    state_cost = np.zeros((L, n))
+    state_cost[:, :m] = edge_cost
+    return Instance(name=name, n=n, L=L, T=T, eps=eps, kind="csr", src=src, dst=dst, cap=cap,
+                    rowptr=rowptr, colidx=colidx, cost=cost, state_cost=state_cost,
+                    meta=dict(m=m, nv=nv, edges=edges, terminals=terminals, src_vertex=src_vertex,
+                              dst_vertex=dst_vertex))
+
+
+def _grid_edges(side: int) -> np.ndarray:
+    e = []
+    for r_ in range(side):
+        for c_ in range(side):
+            i = r_ * side + c_
+            if c_ + 1 < side:
+                e += [(i, i + 1), (i + 1, i)]
+            if r_ + 1 < side:
+                e += [(i, i + side), (i + side, i)]
+    return np.array(e, dtype=np.int64)
+
+
+def sparse_grid_edge_instance(side: int = 10, L: int = 50, T: int = 80, eps: float = 0.01,
+                              seed: int = 0) -> Instance:
+    """The shape of the paper's sparse-grid study (Section 5.1): a side x side grid
+    of two-way streets, every commodity (unit mass) from one corner to the
+    opposite corner, no storage on the streets, waiting only in the source and
+    the sink (the routing lift), edge capacity 1 (the terminals take all L),
+    per-commodity edge costs U[0, 1]."""
+    rng = np.random.default_rng(seed)
+    edges = _grid_edges(side)
+    m = len(edges)
+    cost = rng.uniform(0.0, 1.0, (L, m))
+    return edge_state_instance(side * side, edges, L, T, eps, cost,
+                               src_vertex=np.zeros(L, dtype=np.int64),
+                               dst_vertex=np.full(L, side * side - 1, dtype=np.int64),
+                               mass=np.ones(L), cap_edge=1.0, terminals="routing",
+                               name=f"gridedges{side}")
+
+
+def dense_random_edge_instance(nv: int = 40, p: float = 0.5, L: int = 100, T: int = 100,
+                               eps: float = 0.0025, seed: int = 0) -> Instance:
+    """The shape of the paper's dense-network study (Section 5.2): a directed edge
+    between each ordered vertex pair with probability p, storage in the
+    vertices (cost 0) but not on the edges, commodities of unit mass between
+    random distinct vertices, capacity 1 on edges and L on vertices,
+    per-commodity edge costs U[0, 1].  Draws whose sink is unreachable from
+    the source within T steps are redrawn."""
+    rng = np.random.default_rng(seed)
+    pairs = [(a, b) for a in range(nv) for b in range(nv) if a != b]
+    keep = rng.random(len(pairs)) < p
+    edges = np.array([pr for pr, k in zip(pairs, keep) if k], dtype=np.int64)
+    g = sp.csr_matrix((np.ones(len(edges)), (edges[:, 0], edges[:, 1])), shape=(nv, nv))
+    hop = csgraph.shortest_path(g, directed=True, unweighted=True)
+    s = np.empty(L, dtype=np.int64); z = np.empty(L, dtype=np.int64)
+    k = 0
+    while k < L:
+        a, b = rng.integers(0, nv, 2)
+        if a != b and 2 * hop[a, b] + 1 <= T:     # edge + vertex states alternate along a route
+            s[k], z[k] = a, b
+            k += 1
+    cost = rng.uniform(0.0, 1.0, (L, len(edges)))
+    return edge_state_instance(nv, edges, L, T, eps, cost, src_vertex=s, dst_vertex=z, mass=np.ones(L),
+                               cap_edge=1.0, terminals="storage", cap_vertex=float(L),
+                               name=f"denseedges{nv}")
 
 
 # ----------------------------------------------------------------------------

@@ -316,20 +316,23 @@ def test_road_grid_small_log_domain():
 def test_road_grid_full_size_invariants():
     """The 100 x 100 road grid with 2000 commodities and T = 120 (9.6 GB of stored
     messages): too large for the oracle, so the properties every iterate has are
-    checked -- per-commodity mass equal at all times, the sink marginal exact
-    after the sink update, capacity scalings in (0, 1], non-negative occupancy,
-    and a dual objective that does not decrease (block coordinate ascent)."""
+    checked -- per-commodity mass equal at all times (to the FP32 log-domain
+    floor once the offsets are calibrated, from the third iteration on), the
+    sink marginal exact after the sink update, capacity scalings in (0, 1],
+    non-negative occupancy, and a dual objective that does not decrease (block
+    coordinate ascent)."""
     inst = instances.road_grid_instance()
     Solver = _solver()
     S = Solver(inst, precision="fp32", domain="auto")
     g_prev = -np.inf
-    for _ in range(3):
-        S.iterate(1)
+    for k in range(5):
+        S.iterate(1 if k < 3 else 5)
         st = S.stats()
         assert st["domain"] == 2
-        assert st["dual_obj"] >= g_prev - 1e-5 * abs(st["dual_obj"])
+        assert st["dual_obj"] >= g_prev - 1e-6 * abs(st["dual_obj"])
         g_prev = st["dual_obj"]
-        assert st["mass_drift"] < 1e-4
+        if S.iterations >= 3:
+            assert st["mass_drift"] < 1e-4, (S.iterations, st["mass_drift"])
     occ = S.occupancy().cpu().numpy()
     assert np.isfinite(occ).all() and (occ >= 0).all()
     mass = inst.src.sum()
@@ -337,3 +340,33 @@ def test_road_grid_full_size_invariants():
     ls, ld, lc = (d.cpu().numpy() for d in S.log_duals())
     assert (lc[np.isfinite(lc)] <= 1e-6).all()
     S.close()
+
+
+# ---------------------------------------------------------------------------
+# edge-state lifts: flow on edges, per-commodity edge costs as state costs
+# ---------------------------------------------------------------------------
+
+def test_edge_lift_sparse_grid_full_size():
+    """The sparse-grid study's shape (Section 5.1): 10 x 10 two-way streets (362
+    states with the source and sink states), 50 unit commodities corner to
+    corner, edge capacity 1, per-commodity edge costs U[0, 1] / 0.01 -- a large
+    cost range, so AUTO runs the log domain."""
+    inst = instances.sparse_grid_edge_instance()
+    o = oracle_outputs(inst, 10, log=True)
+    g = gpu_outputs(inst, 10, "fp32", "auto")
+    assert g["stats"]["domain"] == 2
+    compare(g, o, max(1e-5, o["floor"]))
+    g64 = gpu_outputs(inst, 10, "fp64", "log")
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+
+
+def test_edge_lift_dense_random_network():
+    """The dense-network study's shape (Section 5.2), reduced: a random digraph
+    with storage in the vertices, unit commodities between random vertices."""
+    inst = instances.dense_random_edge_instance(nv=24, p=0.5, L=40, T=50, eps=0.0025, seed=1)
+    o = oracle_outputs(inst, 10, log=True)
+    g = gpu_outputs(inst, 10, "fp32", "auto")
+    assert g["stats"]["domain"] == 2
+    compare(g, o, max(1e-5, o["floor"]))
+    g64 = gpu_outputs(inst, 10, "fp64", "log")
+    compare(g64, o, 1e-12, duals_tol=1e-8)
