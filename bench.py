@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "e1b88b4cef25f855907233b9cfc387457260b235fee70728c80210e90120a279",
-                "fetch_kib": 2438.545, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "4334a6c07c829487143da52e784febbe8c1e2315890d14e35f46b273a162e88e",
+                "fetch_kib": 2428.403, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 

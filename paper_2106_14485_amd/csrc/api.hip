@@ -182,7 +182,6 @@ namespace {
 
 int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
 constexpr int kEllMax = 64;    // widest ELL row kept; wider graphs use CSR
-constexpr int kEllQuant = 16;  // ELL rows padded to a multiple of the gather batch
 
 void set_geometry(mmot_solver* s) {
   s->vsize = (s->prec == MMOT_FP64) ? 8 : 4;
@@ -599,8 +598,9 @@ struct Impl {
       HIPCK(hipStreamSynchronize(st));
       {
         const int D = std::max(s->host_flags[0], s->host_flags[1]);
-        const int Dp = (D + kEllQuant - 1) / kEllQuant * kEllQuant;
-        s->ellD = (Dp >= kEllQuant && Dp <= kEllMax) ? Dp : 0;
+        // rows of at most 8 entries (grids) gather in batches of 8, wider ones in 16s
+        const int Dp = D <= 8 ? 8 : (D + 15) / 16 * 16;
+        s->ellD = (D >= 1 && Dp <= kEllMax) ? Dp : 0;
       }
       if (s->ellD) {
         const V pad = LOG ? -static_cast<V>(INFINITY) : V(0);

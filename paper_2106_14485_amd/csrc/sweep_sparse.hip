@@ -168,11 +168,11 @@ __device__ void corr_chunk(const V (&pl)[VT<V>::N], const V (&val)[VT<V>::N], in
 // ---------------------------------------------------------------------------
 // the sweep step
 // ---------------------------------------------------------------------------
-template <typename V, bool LOG, bool FWD, bool CHK, bool ELL>
+// KB: neighbours gathered per batch (ELL rows are padded to a multiple of it)
+template <typename V, bool LOG, bool FWD, bool CHK, bool ELL, int KB>
 __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nblk) {
 
   constexpr int NV = VT<V>::N;
-  constexpr int KB = 16;   // neighbours gathered per batch
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = a.G;
   const int grp = lane / G, gl = lane & (G - 1);
@@ -498,9 +498,9 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   }
   if (CHK && a.part) block_stats(st, a.part, bid);
 }
-template <typename V, bool LOG, bool FWD, bool CHK, bool ELL>
+template <typename V, bool LOG, bool FWD, bool CHK, bool ELL, int KB>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
-  step_body<V, LOG, FWD, CHK, ELL>(a, blockIdx.x, gridDim.x);
+  step_body<V, LOG, FWD, CHK, ELL, KB>(a, blockIdx.x, gridDim.x);
 }
 
 
@@ -1018,15 +1018,18 @@ __global__ void k_reduce_cost(const double* __restrict__ tflow, const double* __
 template <typename V, bool LOG>
 void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
   if (record_item(fwd == 0 ? IK_STEP_BWD : (fwd == 1 ? IK_STEP_FWD : IK_STEP_CHK), LOG, nblk, &a, sizeof(a))) return;
-  if (a.ellD > 0) {
-    if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false, true>), dim3(nblk), dim3(kBlock), 0, s, a);
-    else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, true>), dim3(nblk), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_step<V, LOG, false, false, true>), dim3(nblk), dim3(kBlock), 0, s, a);
-  } else {
-    if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false, false>), dim3(nblk), dim3(kBlock), 0, s, a);
-    else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, false>), dim3(nblk), dim3(kBlock), 0, s, a);
-    else hipLaunchKernelGGL((k_step<V, LOG, false, false, false>), dim3(nblk), dim3(kBlock), 0, s, a);
-  }
+  // ELL rows padded to a multiple of 16 gather 16 neighbours per batch, to a
+  // multiple of 8 (low-degree graphs such as road grids) 8; CSR batches are 16
+#define MMOT_STEP_LAUNCH(E, K)                                                                               \
+  do {                                                                                                      \
+    if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false, E, K>), dim3(nblk), dim3(kBlock), 0, s, a); \
+    else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, E, K>), dim3(nblk), dim3(kBlock), 0, s, a); \
+    else hipLaunchKernelGGL((k_step<V, LOG, false, false, E, K>), dim3(nblk), dim3(kBlock), 0, s, a);       \
+  } while (0)
+  if (a.ellD > 0 && a.ellD % 16 == 0) MMOT_STEP_LAUNCH(true, 16);
+  else if (a.ellD > 0) MMOT_STEP_LAUNCH(true, 8);
+  else MMOT_STEP_LAUNCH(false, 16);
+#undef MMOT_STEP_LAUNCH
 }
 template <typename V, bool LOG>
 void launch_source(int n, int Lp, int G, int nchunk, const V* psi0, const V* rsrc, V* u01, uint32_t* slots,
@@ -1119,17 +1122,17 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
     case IK_STEP_FWD:
     case IK_STEP_CHK: {
       const StepArgs<float>& sa = *static_cast<const StepArgs<float>*>(p);
-      const bool e = sa.ellD > 0;
-      if (it.kind == IK_STEP_BWD) {
-        if (e) step_body<float, LOG, false, false, true>(sa, bid, it.nblk);
-        else step_body<float, LOG, false, false, false>(sa, bid, it.nblk);
-      } else if (it.kind == IK_STEP_FWD) {
-        if (e) step_body<float, LOG, true, false, true>(sa, bid, it.nblk);
-        else step_body<float, LOG, true, false, false>(sa, bid, it.nblk);
-      } else {
-        if (e) step_body<float, LOG, true, true, true>(sa, bid, it.nblk);
-        else step_body<float, LOG, true, true, false>(sa, bid, it.nblk);
-      }
+      const int e = sa.ellD <= 0 ? 0 : (sa.ellD % 16 == 0 ? 2 : 1);
+#define MMOT_STEP_ITEM(F, C)                                                                  \
+      do {                                                                                    \
+        if (e == 2) step_body<float, LOG, F, C, true, 16>(sa, bid, it.nblk);                  \
+        else if (e == 1) step_body<float, LOG, F, C, true, 8>(sa, bid, it.nblk);              \
+        else step_body<float, LOG, F, C, false, 16>(sa, bid, it.nblk);                        \
+      } while (0)
+      if (it.kind == IK_STEP_BWD) MMOT_STEP_ITEM(false, false);
+      else if (it.kind == IK_STEP_FWD) MMOT_STEP_ITEM(true, false);
+      else MMOT_STEP_ITEM(true, true);
+#undef MMOT_STEP_ITEM
       break;
     }
     case IK_SOURCE: source_body<float, LOG>(*static_cast<const SourceArgs<float>*>(p), bid, it.nblk); break;
