@@ -203,9 +203,10 @@ mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double
  *    recorded as a list of kernel work items and kept on the device; one
  *    launch ("tick", on the pool's stream) runs the next item of every batched
  *    request at once, so many small solves share the GPU;
- *  - dedicated lanes (steps that fill the GPU alone): the request runs its
- *    own captured iteration graphs on one of three pool-owned streams, next to
- *    the batched lane.
+ *  - dedicated lane (steps that fill the GPU alone): such requests run one at
+ *    a time, in admission order, with their own captured iteration graphs on
+ *    a pool-owned stream, next to the batched lane (two of them together would
+ *    only stretch both).
  * Either way a request's schedule is exactly the one mmot_solve would run
  * (check_every iterations, then a convergence check, until converged or
  * max_iter), so its result is bitwise the same alone, in any mix, and as a
@@ -232,7 +233,7 @@ mmot_status mmot_pool_submit(mmot_pool* pool, const mmot_problem* prob, const mm
 
 /* Collect finished chunks, schedule the next ones, and launch up to max_ticks
  * ticks of the batched lane (returns early when no batched request has work
- * ready; dedicated lanes run on their own).  The host runs at most 16 ticks
+ * ready; the dedicated lane runs on its own).  The host runs at most 16 ticks
  * ahead of the device.  *n_running (nullable) receives the number of
  * unfinished requests. */
 mmot_status mmot_pool_run(mmot_pool* pool, int32_t max_ticks, int32_t* n_running);

@@ -1004,7 +1004,10 @@ struct mmot_pool {
   hipStream_t setup = nullptr;        // admission work (validation, operators, probe)
   static constexpr int kLanes = 3;    // dedicated lanes: solves whose steps fill the GPU alone
   hipStream_t lanes[kLanes] = {nullptr, nullptr, nullptr};
-  int lane_rr = 0;
+  // Large solves run one at a time, in arrival order, beside the batched lane:
+  // each already fills the GPU, so running two together only stretches both.
+  static constexpr int kLaneActive = 1;
+  std::deque<uint64_t> lane_queue;    // admitted large solves waiting for a lane
   uint64_t next_ticket = 1;
   struct Req {
     uint64_t ticket = 0;
@@ -1013,7 +1016,7 @@ struct mmot_pool {
     int32_t max_iter = 0;
     int32_t state = 0;       // 0 running, 1 done, 2 failed
     int32_t status = MMOT_OK;
-    int lane = -1;           // -1: batched lane, else index of its dedicated stream
+    int lane = -1;           // -1: batched lane, -2: waiting for a dedicated lane, else its stream index
     // batched lane: the current chunk's program, resident on the device
     PoolItem* d_prog = nullptr;
     PoolItem* h_prog = nullptr;
@@ -1180,15 +1183,16 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
   r->max_iter = max_iter;
   if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) { mmot_destroy(s); delete r; return MMOT_EHIP; }
   if (s->nblk >= kFillBlocks) {
-    r->lane = P->lane_rr;
-    P->lane_rr = (P->lane_rr + 1) % mmot_pool::kLanes;
-    s->stream = P->lanes[r->lane];
-    st = lane_chunk(r);
+    r->lane = -2;                      // started by mmot_pool_run when a lane is free
+    P->lane_queue.push_back(r->ticket);
   } else {
     s->stream = P->stream;
     st = pool_program(P, r);
   }
-  if (st != MMOT_OK) { mmot_destroy(s); (void)hipEventDestroy(r->ev); free_prog(r); delete r; return st; }
+  if (st != MMOT_OK) {
+    if (r->lane == -2) P->lane_queue.pop_back();
+    mmot_destroy(s); (void)hipEventDestroy(r->ev); free_prog(r); delete r; return st;
+  }
   P->used += need;
   P->reqs[r->ticket] = r;
   *ticket = r->ticket;
@@ -1199,12 +1203,26 @@ mmot_status mmot_pool_run(mmot_pool* P, int32_t max_ticks, int32_t* n_running) {
   if (!P || max_ticks < 0) return MMOT_EINVAL;
   for (int tk = 0; tk < max_ticks; ++tk) {
     // chunks whose statistics have landed: decide and schedule the next chunk
+    int lanes_busy = 0;
     for (auto& kv : P->reqs) {
       mmot_pool::Req* r = kv.second;
       if (r->state == 0 && r->awaiting && hipEventQuery(r->ev) == hipSuccess) {
         const mmot_status st = pool_finish_chunk(P, r);
         if (st != MMOT_OK) { r->state = 2; r->status = st; }
       }
+      lanes_busy += (r->state == 0 && r->lane >= 0);
+    }
+    // start waiting large solves, oldest first, while lanes are free
+    while (lanes_busy < mmot_pool::kLaneActive && !P->lane_queue.empty()) {
+      auto it = P->reqs.find(P->lane_queue.front());
+      P->lane_queue.pop_front();
+      if (it == P->reqs.end() || it->second->state != 0) continue;
+      mmot_pool::Req* r = it->second;
+      r->lane = lanes_busy;
+      r->s->stream = P->lanes[r->lane];
+      const mmot_status st = lane_chunk(r);
+      if (st != MMOT_OK) { r->state = 2; r->status = st; r->s->stream = P->stream; continue; }
+      ++lanes_busy;
     }
     // one tick of the batched lane: the next item of every batched request
     TickArgs ta;

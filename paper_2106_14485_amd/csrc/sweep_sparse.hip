@@ -274,6 +274,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
 #pragma unroll
       for (int v = 0; v < NV; ++v) { m[v] = ninf<V>(); sm[v] = 0; }
       if (cv && (ell || row_end() > e0)) {
+        int batch = 0;
         for (int e = e0;; e += KB) {
           const int cnt = ell ? KB : min(KB, row_end() - e);
           // batch loads as in the linear domain (masked coefficient: -inf)
@@ -298,6 +299,11 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             cf[k] = (ell || k < cnt) ? cf[k] : ninf<V>();
             if (a.uin) cf[k] += uu[k];
           }
+          // terms that are exactly zero are not evaluated: the ELL padding of a row
+          // that the whole wave works on (exp2(-inf)), and the rescaled running sum
+          // in a row's first batch (it is empty)
+          int live = KB;
+          if (ELL && G == 64) live = __builtin_amdgcn_readfirstlane(min(KB, len - batch * KB));
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             V y[KB];
@@ -306,12 +312,15 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             for (int k = 0; k < KB; ++k) { y[k] = cf[k] + x[k][v]; bm = fmax(bm, y[k]); }
             const V nm = fmax(m[v], bm);
             const V b = (nm == ninf<V>()) ? V(0) : nm;
-            V acc = sm[v] * xexp2(m[v] - b);
+            V acc = V(0);
+            if (batch > 0) acc = sm[v] * xexp2(m[v] - b);
 #pragma unroll
-            for (int k = 0; k < KB; ++k) acc += xexp2(y[k] - b);
+            for (int k = 0; k < KB; ++k)
+              if (k < live) acc += xexp2(y[k] - b);
             sm[v] = acc;
             m[v] = nm;
           }
+          ++batch;
           if (e + KB >= (ELL ? e0 + len : row_end())) break;
         }
 #pragma unroll
