@@ -78,6 +78,12 @@ typedef struct mmot_problem {
   const double* cap;
   const double* src;
   const double* dst;
+  /* 1: a time-varying network (Section 3.3, one cost matrix C_tau per move
+   * tau -> tau+1): cost holds T x nnz values, row tau for the moves from time
+   * tau to tau+1, all with the pattern of rowptr/colidx; an entry may be +INF
+   * to close that move at that step.  CSR only (EUNSUPPORTED for dense).
+   * 0: cost holds nnz values used at every step (finite). */
+  int32_t cost_per_step;
 } mmot_problem;
 
 typedef struct mmot_options {

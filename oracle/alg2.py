@@ -7,7 +7,9 @@ T = TT - 1 transitions:
   tau = 1..T-1 interior marginals with capacity d_tau, scaling u_tau (n)
   tau = T      sink marginal, scaling U0T = U^(0,TT)            (L x n)
 K = exp(-C/eps) (n x n), KL = exp(-C_L/eps) (L x n), charged at interior
-times only (eq. cost_multicommodity).
+times only (eq. cost_multicommodity).  A time-varying network (Section 3.3:
+C replaced by one matrix C_tau per transition) is a list of T matrices; the
+move from time tau to tau+1 then uses K_tau = exp(-C_tau/eps).
 
 Messages (Theorem 5, eqs. psi_hat and psi):
   psi[tau]    = Psi_{tau+1}:  psi[T-1] = U0T K^T,
@@ -60,7 +62,8 @@ class InfeasibleError(RuntimeError):
 
 @dataclasses.dataclass
 class Problem:
-    C: object                 # scipy.sparse (finite entries = allowed moves) or dense ndarray (+inf = forbidden)
+    C: object                 # scipy.sparse (finite entries = allowed moves) or dense ndarray (+inf = forbidden),
+                              # or a list of T of them (C_tau for the move tau -> tau+1)
     eps: float
     T: int
     src: np.ndarray           # R^(0,1), (L, n)
@@ -83,23 +86,39 @@ def make_problem(C, eps, T, src, dst, cap, state_cost=None) -> Problem:
     cap = np.asarray(cap, dtype=np.float64)
     if cap.ndim == 1:
         cap = np.broadcast_to(cap, (max(T - 1, 0), n)).copy()
-    if sp.issparse(C):
-        C = sp.csr_matrix(C, dtype=np.float64)
+    def one(c):
+        return sp.csr_matrix(c, dtype=np.float64) if sp.issparse(c) else np.asarray(c, dtype=np.float64)
+    if isinstance(C, (list, tuple)):
+        assert len(C) == T, "a time-varying network needs one cost matrix per transition"
+        C = [one(c) for c in C]
     else:
-        C = np.asarray(C, dtype=np.float64)
+        C = one(C)
     sc = None if state_cost is None else np.asarray(state_cost, dtype=np.float64)
     return Problem(C=C, eps=float(eps), T=int(T), src=src,
                    dst=np.asarray(dst, dtype=np.float64), cap=cap, state_cost=sc)
 
 
-def gibbs(p: Problem):
-    """K = exp(-C/eps) (eq. K_multicommodity); a forbidden move gives K = 0."""
-    if sp.issparse(p.C):
-        K = p.C.copy()
-        K.data = np.exp(-K.data / p.eps)
+def _gibbs_one(C, eps):
+    if sp.issparse(C):
+        K = C.copy()
+        with np.errstate(over="ignore"):
+            K.data = np.exp(-K.data / eps)
         return K
     with np.errstate(over="ignore"):
-        return np.exp(-p.C / p.eps)
+        return np.exp(-C / eps)
+
+
+def gibbs(p: Problem):
+    """K = exp(-C/eps) (eq. K_multicommodity); a forbidden move gives K = 0.
+    A list of K_tau for a time-varying network."""
+    if isinstance(p.C, list):
+        return [_gibbs_one(c, p.eps) for c in p.C]
+    return _gibbs_one(p.C, p.eps)
+
+
+def _kat(K, tau):
+    """The kernel of the move tau -> tau+1."""
+    return K[tau] if isinstance(K, list) else K
 
 
 def gibbs_state(p: Problem):
@@ -140,9 +159,9 @@ def backward_sweep(p: Problem, st: State, K=None, KL=None) -> None:
     """Theorem 5, eq. psi: Psi_{TT-1} = U0T K^T, then (Psi_t (.) KL) diag(u_t) K^T."""
     K = gibbs(p) if K is None else K
     KL = gibbs_state(p) if KL is None else KL
-    st.psi[p.T - 1] = _right_t(st.U0T, K)
+    st.psi[p.T - 1] = _right_t(st.U0T, _kat(K, p.T - 1))
     for tau in range(p.T - 1, 0, -1):
-        st.psi[tau - 1] = _right_t(st.psi[tau] * KL * st.u[tau - 1][None, :], K)
+        st.psi[tau - 1] = _right_t(st.psi[tau] * KL * st.u[tau - 1][None, :], _kat(K, tau - 1))
 
 
 def _divide_support(R, msg, what):
@@ -171,7 +190,7 @@ def forward_sweep(p: Problem, st: State, K=None, KL=None, update: bool = True,
     """
     K = gibbs(p) if K is None else K
     KL = gibbs_state(p) if KL is None else KL
-    ph = _right(st.U01, K)
+    ph = _right(st.U01, _kat(K, 0))
     kept = [None, ph] if keep else None
     for tau in range(1, p.T):
         if update:
@@ -181,7 +200,7 @@ def forward_sweep(p: Problem, st: State, K=None, KL=None, update: bool = True,
             over = s > d
             u[over] = d[over] / s[over]
             st.u[tau - 1] = u
-        ph = _right(ph * KL * st.u[tau - 1][None, :], K)
+        ph = _right(ph * KL * st.u[tau - 1][None, :], _kat(K, tau))
         if keep:
             kept.append(ph)
     return (ph, kept) if keep else ph
@@ -253,21 +272,19 @@ def projections(p: Problem, st: State):
     P0t[T] = tmp.U0T * ph_T
     A = [tmp.U01] + [hats[tau] * KL * tmp.u[tau - 1][None, :] for tau in range(1, T)]
     B = [None] + [tmp.psi[tau] * KL * tmp.u[tau - 1][None, :] for tau in range(1, T)] + [tmp.U0T]
-    Ks = sp.csr_matrix(K) if not sp.issparse(K) else K.tocsr()
-    Kc = Ks.tocoo()
     flows = []
     for tau in range(T):
+        Kt = _kat(K, tau)
+        Kc = (sp.csr_matrix(Kt) if not sp.issparse(Kt) else Kt.tocsr()).tocoo()
         vals = Kc.data * np.einsum("li,li->i", A[tau][:, Kc.row], B[tau + 1][:, Kc.col])
         flows.append(sp.csr_matrix((vals, (Kc.row, Kc.col)), shape=(n, n)))
-    Cc = p.C if sp.issparse(p.C) else None
     cost = 0.0
     for tau in range(T):
         F = flows[tau].tocoo()
-        if Cc is not None:
-            cvals = np.asarray(Cc[F.row, F.col]).ravel()
-        else:
-            cvals = p.C[F.row, F.col]
-        cost += float((cvals * F.data).sum())
+        Ct = _kat(p.C, tau)
+        cvals = np.asarray(Ct[F.row, F.col]).ravel() if sp.issparse(Ct) else Ct[F.row, F.col]
+        m = F.data > 0                       # a closed move (+inf cost) carries no mass
+        cost += float((cvals[m] * F.data[m]).sum())
     if p.state_cost is not None:
         for tau in range(1, T):
             cost += float((p.state_cost * P0t[tau]).sum())
@@ -279,21 +296,28 @@ def projections(p: Problem, st: State):
 # log domain
 # ----------------------------------------------------------------------------
 
+def _log_kernel_csc_one(C, eps, transpose: bool):
+    if sp.issparse(C):
+        Cm = C.tocsr()
+    else:
+        fin = np.isfinite(C)
+        r, c = np.nonzero(fin)
+        Cm = sp.csr_matrix((C[r, c], (r, c)), shape=C.shape)
+    M = Cm.T.tocsr() if not transpose else Cm.tocsr()
+    M.sort_indices()
+    return M.indptr, M.indices, -M.data / eps
+
+
 def _log_kernel_csc(p: Problem, transpose: bool):
     """log K as (indptr, row-of-entry, value) grouped by output column.
 
     For out = LSE-product X K (transpose=False), out[:, j] gathers column j
-    of K; for X K^T it gathers row j of K.
+    of K; for X K^T it gathers row j of K.  A list of them (one per
+    transition) for a time-varying network.
     """
-    if sp.issparse(p.C):
-        Cm = p.C.tocsr()
-    else:
-        fin = np.isfinite(p.C)
-        r, c = np.nonzero(fin)
-        Cm = sp.csr_matrix((p.C[r, c], (r, c)), shape=p.C.shape)
-    M = Cm.T.tocsr() if not transpose else Cm.tocsr()
-    M.sort_indices()
-    return M.indptr, M.indices, -M.data / p.eps
+    if isinstance(p.C, list):
+        return [_log_kernel_csc_one(c, p.eps, transpose) for c in p.C]
+    return _log_kernel_csc_one(p.C, p.eps, transpose)
 
 
 def lse_matmul(logX, kern, chunk=128):
@@ -371,15 +395,15 @@ def iterate_log(p: Problem, st: LogState, n_iter: int) -> LogState:
     lKL = np.zeros((p.L, p.n)) if p.state_cost is None else -p.state_cost / p.eps
     lcap = _log_cap(p)
     for _ in range(n_iter):
-        st.lpsi[p.T - 1] = lse_matmul(st.lU0T, kb)
+        st.lpsi[p.T - 1] = lse_matmul(st.lU0T, _kat(kb, p.T - 1))
         for tau in range(p.T - 1, 0, -1):
-            st.lpsi[tau - 1] = lse_matmul(st.lpsi[tau] + lKL + st.lu[tau - 1][None, :], kb)
+            st.lpsi[tau - 1] = lse_matmul(st.lpsi[tau] + lKL + st.lu[tau - 1][None, :], _kat(kb, tau - 1))
         st.lU01 = _log_divide_support(p.src, st.lpsi[0], "source")
-        lph = lse_matmul(st.lU01, kf)
+        lph = lse_matmul(st.lU01, _kat(kf, 0))
         for tau in range(1, p.T):
             ls = _lse_rows(lph + st.lpsi[tau] + lKL)
             st.lu[tau - 1] = np.minimum(lcap[tau - 1] - ls, 0.0)
-            lph = lse_matmul(lph + lKL + st.lu[tau - 1][None, :], kf)
+            lph = lse_matmul(lph + lKL + st.lu[tau - 1][None, :], _kat(kf, tau))
         st.lU0T = _log_divide_support(p.dst, lph, "sink")
         mass = float(np.exp(_lse_rows((st.lU0T + lph).reshape(-1, 1))[0]))
         st.g.append(_dual_log(p, st, mass))
@@ -405,12 +429,12 @@ def projections_log(p: Problem, st: LogState, want_flows: bool = True):
     lKL = np.zeros((p.L, p.n)) if p.state_cost is None else -p.state_cost / p.eps
     T, L, n = p.T, p.L, p.n
     lpsi = np.full((T, L, n), -np.inf)
-    lpsi[T - 1] = lse_matmul(st.lU0T, kb)
+    lpsi[T - 1] = lse_matmul(st.lU0T, _kat(kb, T - 1))
     for tau in range(T - 1, 0, -1):
-        lpsi[tau - 1] = lse_matmul(lpsi[tau] + lKL + st.lu[tau - 1][None, :], kb)
-    lhats = [None, lse_matmul(st.lU01, kf)]
+        lpsi[tau - 1] = lse_matmul(lpsi[tau] + lKL + st.lu[tau - 1][None, :], _kat(kb, tau - 1))
+    lhats = [None, lse_matmul(st.lU01, _kat(kf, 0))]
     for tau in range(1, T):
-        lhats.append(lse_matmul(lhats[tau] + lKL + st.lu[tau - 1][None, :], kf))
+        lhats.append(lse_matmul(lhats[tau] + lKL + st.lu[tau - 1][None, :], _kat(kf, tau)))
     P0t = np.zeros((T + 1, L, n))
     P0t[0] = np.exp(st.lU01 + lpsi[0])
     for tau in range(1, T):
@@ -418,22 +442,21 @@ def projections_log(p: Problem, st: LogState, want_flows: bool = True):
     P0t[T] = np.exp(st.lU0T + lhats[T])
     out = dict(P0t=P0t, Pt=P0t.sum(axis=1), mass=P0t.sum(axis=2), lpsi=lpsi, lpsihat=lhats)
     if want_flows:
-        Cm = p.C.tocoo() if sp.issparse(p.C) else sp.coo_matrix(np.where(np.isfinite(p.C), 1.0, 0.0))
-        rows, cols = Cm.row, Cm.col
-        if sp.issparse(p.C):
-            cvals = Cm.data
-        else:
-            cvals = p.C[rows, cols]
-        lk = -cvals / p.eps
         lA = [st.lU01] + [lhats[tau] + lKL + st.lu[tau - 1][None, :] for tau in range(1, T)]
         lB = [None] + [lpsi[tau] + lKL + st.lu[tau - 1][None, :] for tau in range(1, T)] + [st.lU0T]
         flows = []
         cost = 0.0
         for tau in range(T):
+            Ct = _kat(p.C, tau)
+            Cm = Ct.tocoo() if sp.issparse(Ct) else sp.coo_matrix(np.where(np.isfinite(Ct), 1.0, 0.0))
+            rows, cols = Cm.row, Cm.col
+            cvals = Cm.data if sp.issparse(Ct) else Ct[rows, cols]
+            lk = -cvals / p.eps
             Z = lA[tau][:, rows] + lB[tau + 1][:, cols] + lk[None, :]
             vals = np.exp(_lse_rows(Z))
             flows.append(sp.csr_matrix((vals, (rows, cols)), shape=(n, n)))
-            cost += float((cvals * vals).sum())
+            m = vals > 0                     # a closed move (+inf cost) carries no mass
+            cost += float((cvals[m] * vals[m]).sum())
         if p.state_cost is not None:
             for tau in range(1, T):
                 cost += float((p.state_cost * P0t[tau]).sum())

@@ -3,10 +3,11 @@
 The multi-commodity tensor has one commodity mode and T+1 state modes
 (times 0..T).  Its entries are (eqs. K_multicommodity and U_multicommodity)
 
-  (K (.) U)[l, i_0, ..., i_T] = U01[l, i_0] * prod_{tau=0}^{T-1} K[i_tau, i_tau+1]
+  (K (.) U)[l, i_0, ..., i_T] = U01[l, i_0] * prod_{tau=0}^{T-1} K_tau[i_tau, i_tau+1]
                                 * prod_{tau=1}^{T-1} KL[l, i_tau] u_tau[i_tau]
                                 * U0T[l, i_T]
 
+(K_tau = K for a fixed network, one kernel per move for a time-varying one.)
 Projections are plain sums over the other modes (eqs. proj_discrete and
 proj_discrete_bi).  The generic Sinkhorn updates of Proposition 1 are applied
 to the explicit tensor, in the block order of Algorithm 2.  Everything here
@@ -24,11 +25,13 @@ def full_tensor(K, KL, U01, U0T, u, T):
     L, n = U01.shape
     M = U01.reshape((L, n) + (1,) * T).astype(np.float64).copy()
     for tau in range(1, T + 1):
-        # factor K[i_{tau-1}, i_tau] spans state axes tau-1 and tau (array axes tau, tau+1)
+        # factor K[i_{tau-1}, i_tau] spans state axes tau-1 and tau (array axes tau, tau+1);
+        # a list holds one kernel per move (time-varying network)
         shapeK = [1] * (T + 2)
         shapeK[tau] = n
         shapeK[tau + 1] = n
-        M = M * K.reshape(shapeK)
+        Kt = K[tau - 1] if isinstance(K, (list, tuple)) else K
+        M = M * Kt.reshape(shapeK)
         if tau < T:
             shapeS = [1] * (T + 2)
             shapeS[0] = L

@@ -24,22 +24,32 @@ __all__ = ["lp_optimum", "walk_counts"]
 
 
 def lp_optimum(C, T, src, dst, cap, state_cost=None):
-    """Optimal value of the unregularised problem; C scipy sparse (allowed moves)."""
-    Cc = sp.coo_matrix(C)
-    ei, ej, ec = Cc.row, Cc.col, Cc.data
+    """Optimal value of the unregularised problem; C scipy sparse (allowed moves),
+    or a list of T of them with one sparsity pattern (costs of the move tau ->
+    tau+1; +inf closes a move at that step)."""
+    steps = C if isinstance(C, (list, tuple)) else [C] * T
+    Cc = sp.coo_matrix(steps[0])
+    ei, ej = Cc.row, Cc.col
     E = len(ei)
+    ecs = [sp.coo_matrix(c).data for c in steps]
+    for c in steps:
+        cc = sp.coo_matrix(c)
+        assert np.array_equal(cc.row, ei) and np.array_equal(cc.col, ej), "one sparsity pattern for all steps"
     L, n = src.shape
     cap = np.asarray(cap, dtype=np.float64)
     if cap.ndim == 1:
         cap = np.broadcast_to(cap, (max(T - 1, 0), n))
     nv = L * T * E
     cost = np.zeros(nv)
+    closed = np.zeros(nv, dtype=bool)
     for l in range(L):
         for tau in range(T):
-            c = ec.copy()
+            c = ecs[tau].copy()
             if state_cost is not None and tau + 1 < T:
                 c = c + state_cost[l, ej]       # state cost at the arrival time (interior only)
-            cost[(l * T + tau) * E:(l * T + tau + 1) * E] = c
+            blk = slice((l * T + tau) * E, (l * T + tau + 1) * E)
+            closed[blk] = ~np.isfinite(c)
+            cost[blk] = np.where(np.isfinite(c), c, 0.0)
     out_of = [np.nonzero(ei == i)[0] for i in range(n)]
     into = [np.nonzero(ej == j)[0] for j in range(n)]
     R, Cl, V, b = [], [], [], []
@@ -73,28 +83,35 @@ def lp_optimum(C, T, src, dst, cap, state_cost=None):
             b.append(cap[tau - 1, i]); r += 1
     Aub = sp.csr_matrix((V, (R, Cl)), shape=(r, nv)) if r else None
     bub = np.array(b) if r else None
-    res = linprog(cost, A_ub=Aub, b_ub=bub, A_eq=Aeq, b_eq=beq, bounds=(0, None), method="highs")
+    bounds = [(0, 0) if c else (0, None) for c in closed]     # a closed move carries no flow
+    res = linprog(cost, A_ub=Aub, b_ub=bub, A_eq=Aeq, b_eq=beq, bounds=bounds, method="highs")
     if res.status != 0:
         raise RuntimeError(f"LP failed: {res.message}")
     return float(res.fun)
 
 
 def walk_counts(C, T, sources, sinks):
-    """Number of length-T walks along allowed moves from each source to its sink (exact ints)."""
-    pat = sp.coo_matrix(C)
-    n = pat.shape[0]
-    adj = [[] for _ in range(n)]
-    for i, j in zip(pat.row, pat.col):
-        adj[i].append(j)
+    """Number of length-T walks along allowed moves from each source to its sink
+    (exact ints); C may be a list of T per-step matrices (+inf = closed)."""
+    steps = C if isinstance(C, (list, tuple)) else [C] * T
+    adjs = []
+    for c in steps:
+        pat = sp.coo_matrix(c)
+        n = pat.shape[0]
+        adj = [[] for _ in range(n)]
+        for i, j, v in zip(pat.row, pat.col, pat.data):
+            if np.isfinite(v):
+                adj[i].append(j)
+        adjs.append(adj)
     counts = []
     for s, z in zip(sources, sinks):
         v = [0] * n
         v[s] = 1
-        for _ in range(T):
+        for tau in range(T):
             w = [0] * n
             for i in range(n):
                 if v[i]:
-                    for j in adj[i]:
+                    for j in adjs[tau][i]:
                         w[j] += v[i]
             v = w
         counts.append(v[z])

@@ -24,6 +24,7 @@ class Problem(ctypes.Structure):
         ("rowptr", ctypes.c_void_p), ("colidx", ctypes.c_void_p), ("cost", ctypes.c_void_p),
         ("cost_dense", ctypes.c_void_p), ("state_cost", ctypes.c_void_p), ("cap", ctypes.c_void_p),
         ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
+        ("cost_per_step", ctypes.c_int32),
     ]
 
 

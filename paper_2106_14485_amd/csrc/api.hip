@@ -56,27 +56,10 @@ void launch_levels64(unsigned long long*, uint32_t*, float*, int, int, int, int,
 void launch_reduce_stats(const double*, int, int, double*, double, double*, hipStream_t);
 void launch_reduce_cost(const double*, const double*, int, int, double*, double*, double*, hipStream_t);
 // dense_mfma.hip
-struct GemmArgs {
-  int n, Lp, L, lda;
-  const void* A;
-  const float* B;
-  const float* u;
-  const float* fac;
-  float* out;
-  const float* kl;
-  int cap;
-  const float* wpan;
-  const float* wgt;
-  float* part_s;
-  const float* ucur;
-  double* pcomm;
-  uint32_t* slots;
-  int nslot;
-  size_t slot_stride;
-};
 void launch_gemm(const GemmArgs&, bool, hipStream_t);
 int gemm_col_tiles(int);
-void launch_dense_rows(int, int, const float*, const float*, float*, int, double*, double*, int, hipStream_t);
+void launch_dense_rows(int, int, const float*, const float*, float*, int, double*, double*, const float*, uint16_t*, int,
+                       int, hipStream_t);
 void launch_dense_sink(int, int, int, const float*, const float*, float*, int, const double*, const double*,
                        uint32_t*, int, uint32_t*, size_t, int*, double*, double*, double*, int, hipStream_t);
 void launch_dense_gibbs(const double*, int, int, double, float*, float*, void*, void*, hipStream_t);
@@ -138,6 +121,7 @@ struct mmot_solver {
   int *rp_b = nullptr, *ci_b = nullptr, *rp_f = nullptr, *ci_f = nullptr;
   int *cnt = nullptr, *cursor = nullptr, *srcpos = nullptr;
   void *kv_b = nullptr, *kv_f = nullptr;
+  int steps_k = 1;                 // operator value sets: T for a time-varying network, else 1
   double* cost = nullptr;
   void *KL = nullptr, *cap = nullptr, *R01 = nullptr, *R0T = nullptr, *U01 = nullptr, *U0T = nullptr;
   void *psi = nullptr, *zh = nullptr, *u = nullptr;
@@ -161,6 +145,8 @@ struct mmot_solver {
   bool dense_bf16 = false, has_bf16 = false;
   float *Kd = nullptr, *Ktd = nullptr, *part_s = nullptr;
   void *Kb = nullptr, *Ktb = nullptr;
+  uint16_t* Bbuf[2] = {nullptr, nullptr};   // BF16 products: next operand, u-scaled, k-blocked (rows padded to 64)
+  int n8 = 0;
   // ELL copies of the operators (row width ellD, 0 = use CSR)
   int ellD = 0;
   int *ell_ci_b = nullptr, *ell_ci_f = nullptr, *deg_b = nullptr, *deg_f = nullptr, *maxdeg = nullptr;
@@ -197,7 +183,7 @@ void set_geometry(mmot_solver* s) {
   s->nslot = std::max(1, std::min(32, nblk / 16));
   s->ncslot = std::min(s->nslot, 8);
   if (s->kind == MMOT_DENSE) {
-    s->lda = (s->n + 7) / 8 * 8;
+    s->lda = (s->n + 63) / 64 * 64;   // K extent zero-padded to whole 64-deep product stages
     s->ntn = gemm_col_tiles(s->Lp);
   }
 }
@@ -207,13 +193,14 @@ void carve(mmot_solver* s, Carver& c) {
   const size_t n = s->n, Lp = s->Lp, T = s->T, nnz = dense ? 1 : (size_t)s->nnz, vs = s->vsize;
   const size_t Tm1 = T > 1 ? T - 1 : 0;
   auto takev = [&](size_t cnt) { return static_cast<void*>(c.take<char>(cnt * vs)); };
+  const size_t ks = (size_t)s->steps_k;
   s->rp_b = c.take<int>(n + 1);
   s->ci_b = c.take<int>(nnz);
-  s->kv_b = takev(nnz);
-  s->cost = c.take<double>(nnz);
+  s->kv_b = takev(ks * nnz);
+  s->cost = c.take<double>(ks * nnz);
   s->rp_f = c.take<int>(n + 1);
   s->ci_f = c.take<int>(nnz);
-  s->kv_f = takev(nnz);
+  s->kv_f = takev(ks * nnz);
   s->cnt = c.take<int>(n);
   s->cursor = c.take<int>(n);
   s->srcpos = c.take<int>(nnz);
@@ -258,7 +245,7 @@ void carve(mmot_solver* s, Carver& c) {
   s->exc_cnt = c.take<int>(n);
   s->exc = c.take<double>(1);
   s->flags = c.take<int>(4);
-  const size_t ell = dense ? 1 : n * kEllMax;
+  const size_t ell = (dense || s->steps_k > 1) ? 1 : n * kEllMax;   // time-varying networks use CSR
   s->ell_ci_b = c.take<int>(ell);
   s->ell_ci_f = c.take<int>(ell);
   s->ell_kv_b = takev(ell);
@@ -270,6 +257,9 @@ void carve(mmot_solver* s, Carver& c) {
     s->Kb = s->has_bf16 ? static_cast<void*>(c.take<uint16_t>(nn)) : nullptr;
     s->Ktb = s->has_bf16 ? static_cast<void*>(c.take<uint16_t>(nn)) : nullptr;
     s->part_s = c.take<float>((size_t)s->ntn * n);
+    s->n8 = (int)((n + 63) / 64 * 64);
+    for (int i = 0; i < 2; ++i)
+      s->Bbuf[i] = s->has_bf16 ? c.take<uint16_t>((size_t)s->n8 * Lp) : nullptr;
   }
   s->deg_b = c.take<int>(n);
   s->deg_f = c.take<int>(n);
@@ -281,7 +271,9 @@ mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
   if (p->n < 1 || p->L < 1 || p->T < 1) return MMOT_EINVAL;
   if (!(p->eps > 0) || !std::isfinite(p->eps)) return MMOT_EINVAL;
   if (p->kind != MMOT_CSR && p->kind != MMOT_DENSE) return MMOT_EINVAL;
+  if (p->cost_per_step != 0 && p->cost_per_step != 1) return MMOT_EINVAL;
   if (p->kind == MMOT_DENSE) {
+    if (p->cost_per_step) return MMOT_EUNSUPPORTED;   // per-step dense costs: not built
     // dense products run on MFMA in the scaled domain, FP32 or BF16 (+ FP32 polish)
     if (o->precision != MMOT_FP32 && o->precision != MMOT_BF16) return MMOT_EUNSUPPORTED;
     if (o->domain == MMOT_DOMAIN_LOG) return MMOT_EUNSUPPORTED;
@@ -327,17 +319,26 @@ struct Impl {
   static GemmArgs gemm_base(mmot_solver* s, bool forward_op) {
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
-    g.n = s->n; g.Lp = s->Lp; g.L = s->L; g.lda = s->lda;
+    g.n = s->n; g.Lp = s->Lp; g.L = s->L; g.lda = s->lda; g.n8 = s->n8;
     if (s->dense_bf16) g.A = forward_op ? s->Ktb : s->Kb;
     else g.A = forward_op ? static_cast<const void*>(s->Ktd) : static_cast<const void*>(s->Kd);
     g.nslot = s->nslot;
     return g;
   }
   // dense backward product t+1 -> t
+  // BF16 products read the operand diag(u) (panel) in BF16 as prepared by the
+  // producer of the panel (the previous backward product's epilogue; the forward
+  // capacity update), except the first product of a sweep, whose operand (U0T,
+  // U01) is staged from FP32
+  static uint16_t* bbuf(mmot_solver* s, int t) { return s->Bbuf[t & 1]; }
   static void dense_bwd(mmot_solver* s, int t, bool calib, hipStream_t st) {
     GemmArgs g = gemm_base(s, false);
     g.B = reinterpret_cast<const float*>((t + 1 == s->T) ? s->U0T : static_cast<void*>(psi(s, t + 1)));
     g.u = reinterpret_cast<const float*>(uat(s, t + 1));
+    if (s->dense_bf16) {
+      if (t + 1 < s->T) g.Bb = bbuf(s, t + 1);
+      if (t >= 1) { g.bout = bbuf(s, t); g.uo = reinterpret_cast<const float*>(uat(s, t)); }
+    }
     g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
     g.out = reinterpret_cast<float*>(psi(s, t));
     g.kl = (s->has_kl && t >= 1) ? static_cast<const float*>(s->KL) : nullptr;
@@ -352,6 +353,7 @@ struct Impl {
     GemmArgs g = gemm_base(s, true);
     g.B = reinterpret_cast<const float*>((t == 0) ? s->U01 : static_cast<void*>(zh(s, t)));
     g.u = reinterpret_cast<const float*>(uat(s, t));
+    if (s->dense_bf16 && t >= 1) g.Bb = bbuf(s, t);
     g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facf) + (size_t)to * Lp);
     g.out = reinterpret_cast<float*>(zh(s, to));
     g.slot_stride = (size_t)(T + 1) * Lp;
@@ -370,7 +372,9 @@ struct Impl {
       launch_dense_rows(s->n, s->ntn, s->part_s, reinterpret_cast<const float*>(static_cast<V*>(s->cap) + (size_t)(to - 1) * s->n),
                         reinterpret_cast<float*>(uat(s, to)), mode == 0 ? 1 : 0,
                         mode == 1 ? s->part + (size_t)to * pstride : nullptr,
-                        (mode == 1 && occ) ? occ + (size_t)to * s->n : nullptr, s->nblk, st);
+                        (mode == 1 && occ) ? occ + (size_t)to * s->n : nullptr,
+                        reinterpret_cast<const float*>(zh(s, to)), s->dense_bf16 ? bbuf(s, to) : nullptr, s->Lp,
+                        s->nblk, st);
     } else {
       launch_gemm(g, s->dense_bf16, st);   // hatPsi_T into the rolling buffer
       launch_dense_sink(s->n, s->Lp, s->L, g.out, reinterpret_cast<const float*>(s->R0T),
@@ -383,10 +387,14 @@ struct Impl {
     }
   }
 
+  // operator values of the move t -> t+1 (one set unless the network is time-varying)
+  static const V* kvat(mmot_solver* s, void* base, int t) {
+    return static_cast<const V*>(base) + (s->steps_k > 1 ? (size_t)t * s->nnz : 0);
+  }
   static StepArgs<V> bwd_args(mmot_solver* s, int t, bool calib) {
     const int T = s->T;
     StepArgs<V> a = base_args(s);
-    a.rp = s->rp_b; a.ci = s->ci_b; a.kv = static_cast<const V*>(s->kv_b);
+    a.rp = s->rp_b; a.ci = s->ci_b; a.kv = kvat(s, s->kv_b, t);
     if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_b; a.kv = static_cast<const V*>(s->ell_kv_b); a.deg = s->deg_b; }
     a.xin = (t + 1 == T) ? static_cast<const V*>(s->U0T) : psi(s, t + 1);
     a.uin = uat(s, t + 1);
@@ -422,7 +430,7 @@ struct Impl {
     const int T = s->T;
     const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
     StepArgs<V> a = base_args(s);
-    a.rp = s->rp_f; a.ci = s->ci_f; a.kv = static_cast<const V*>(s->kv_f);
+    a.rp = s->rp_f; a.ci = s->ci_f; a.kv = kvat(s, s->kv_f, t);
     if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_f; a.kv = static_cast<const V*>(s->ell_kv_f); a.deg = s->deg_f; }
     a.xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
     a.uin = uat(s, t);
@@ -514,6 +522,7 @@ struct Impl {
         GemmArgs g = gemm_base(s, fwd != 0);
         g.B = reinterpret_cast<const float*>(psi(s, t + 1));
         g.u = reinterpret_cast<const float*>(uat(s, t + 1));
+        if (s->dense_bf16) g.Bb = bbuf(s, t + 1);   // the operand form of the sweep's products
         g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
         g.out = reinterpret_cast<float*>(zh(s, t & 1));
         if (fwd) {   // forward product with the capacity partial sums, as in the sweep
@@ -551,8 +560,8 @@ struct Impl {
     for (int t = 0; t < T; ++t) {
       const V* xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
       const int tb = t + 1;
-      launch_flows<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, s->rp_b, s->ci_b, static_cast<const V*>(s->kv_b),
-                           s->cost, xin, uat(s, t), (tb == T) ? static_cast<const V*>(s->U0T) : psi(s, tb),
+      launch_flows<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, s->rp_b, s->ci_b, kvat(s, s->kv_b, t),
+                           s->cost + (s->steps_k > 1 ? (size_t)t * s->nnz : 0), xin, uat(s, t), (tb == T) ? static_cast<const V*>(s->U0T) : psi(s, tb),
                            uat(s, tb), s->sigf + (size_t)t * Lp, s->sigb + (size_t)tb * Lp,
                            flow + (size_t)t * s->nnz, s->part_flow + (size_t)t * pstride, s->nblk, st);
       if (tb < T) launch_step<V, LOG>(fwd_args(s, t, 1, false, nullptr, nullptr), 2, s->nblk, st);
@@ -569,7 +578,7 @@ struct Impl {
     launch_validate_vals(p->dst, n * L, 0, 0, 0, s->flags, st);
     launch_validate_vals(p->cap, p->cap_per_step ? Tm1 * n : n, 1, 1, 0, s->flags, st);
     const bool dense = s->kind == MMOT_DENSE;
-    if (!dense) launch_validate_vals(p->cost, nnz, 0, 0, 1, s->flags, st);
+    if (!dense) launch_validate_vals(p->cost, (size_t)s->steps_k * nnz, s->steps_k > 1 ? 1 : 0, 0, 1, s->flags, st);
     else launch_validate_vals(p->cost_dense, n * n, 1, 0, 1, s->flags, st);
     if (p->state_cost) launch_validate_vals(p->state_cost, n * L, 0, 0, 1, s->flags, st);
     if (!dense) launch_validate_csr(p->rowptr, p->colidx, s->n, s->nnz, s->flags, st);
@@ -587,10 +596,13 @@ struct Impl {
       // operators: backward = rows of K (input order), forward = rows of K^T
       HIPCK(hipMemcpyAsync(s->rp_b, p->rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, st));
       HIPCK(hipMemcpyAsync(s->ci_b, p->colidx, nnz * sizeof(int), hipMemcpyDeviceToDevice, st));
-      HIPCK(hipMemcpyAsync(s->cost, p->cost, nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
-      launch_gibbs<V, LOG>(s->cost, nnz, s->eps, static_cast<V*>(s->kv_b), st);
+      const size_t ks = (size_t)s->steps_k;
+      HIPCK(hipMemcpyAsync(s->cost, p->cost, ks * nnz * sizeof(double), hipMemcpyDeviceToDevice, st));
+      launch_gibbs<V, LOG>(s->cost, ks * nnz, s->eps, static_cast<V*>(s->kv_b), st);
       launch_transpose_pattern(s->rp_b, s->ci_b, s->n, s->nnz, s->cnt, s->rp_f, s->cursor, s->ci_f, s->srcpos, st);
-      launch_gather_vals<V>(static_cast<const V*>(s->kv_b), s->srcpos, s->nnz, static_cast<V*>(s->kv_f), st);
+      for (size_t k = 0; k < ks; ++k)
+        launch_gather_vals<V>(static_cast<const V*>(s->kv_b) + k * nnz, s->srcpos, s->nnz,
+                              static_cast<V*>(s->kv_f) + k * nnz, st);
       launch_fill<int>(s->maxdeg, 2, 0, st);
       launch_max_degree(s->rp_b, s->n, s->maxdeg, st);
       launch_max_degree(s->rp_f, s->n, s->maxdeg + 1, st);
@@ -600,7 +612,7 @@ struct Impl {
         const int D = std::max(s->host_flags[0], s->host_flags[1]);
         // rows of at most 8 entries (grids) gather in batches of 8, wider ones in 16s
         const int Dp = D <= 8 ? 8 : (D + 15) / 16 * 16;
-        s->ellD = (D >= 1 && Dp <= kEllMax) ? Dp : 0;
+        s->ellD = (D >= 1 && Dp <= kEllMax && s->steps_k == 1) ? Dp : 0;   // time-varying: CSR
       }
       if (s->ellD) {
         const V pad = LOG ? -static_cast<V>(INFINITY) : V(0);
@@ -609,8 +621,10 @@ struct Impl {
         launch_build_ell<V>(s->rp_f, s->ci_f, static_cast<const V*>(s->kv_f), s->n, s->ellD, pad, s->ell_ci_f,
                             static_cast<V*>(s->ell_kv_f), s->deg_f, st);
       }
-      launch_rowsum_max<V, LOG>(s->rp_b, static_cast<const V*>(s->kv_b), s->n, 0.0, s->rho, st);
-      launch_rowsum_max<V, LOG>(s->rp_f, static_cast<const V*>(s->kv_f), s->n, 0.0, s->rho + 1, st);
+      for (size_t k = 0; k < ks; ++k) {
+        launch_rowsum_max<V, LOG>(s->rp_b, static_cast<const V*>(s->kv_b) + k * nnz, s->n, 0.0, s->rho, st);
+        launch_rowsum_max<V, LOG>(s->rp_f, static_cast<const V*>(s->kv_f) + k * nnz, s->n, 0.0, s->rho + 1, st);
+      }
     }
     // panels
     const V zero = LOG ? -static_cast<V>(INFINITY) : V(0);
@@ -627,6 +641,8 @@ struct Impl {
     launch_fill<V>(static_cast<V*>(s->U01), n * Lp, zero, st);
     launch_fill<V>(static_cast<V*>(s->psi), T * n * Lp, zero, st);
     launch_fill<V>(static_cast<V*>(s->zh), 2 * n * Lp, zero, st);
+    for (int i = 0; i < 2; ++i)   // BF16 operand buffers: padding rows must stay zero
+      if (s->Bbuf[i]) launch_fill<uint32_t>(reinterpret_cast<uint32_t*>(s->Bbuf[i]), (size_t)s->n8 * Lp / 2, 0u, st);
     launch_fill<uint32_t>(s->slots_b, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
     launch_fill<uint32_t>(s->slots_f, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
     launch_fill<uint32_t>(s->slotsE, (size_t)s->nslot * Lp, 0u, st);
@@ -767,6 +783,7 @@ mmot_status mmot_query_workspace(const mmot_problem* p, const mmot_options* o, s
   if (st != MMOT_OK) return st;
   mmot_solver tmp;
   tmp.n = p->n; tmp.L = p->L; tmp.T = p->T; tmp.nnz = p->nnz; tmp.kind = p->kind;
+  tmp.steps_k = p->cost_per_step ? p->T : 1;
   tmp.has_kl = p->state_cost != nullptr;
   tmp.prec = (o->precision == MMOT_FP64) ? MMOT_FP64 : MMOT_FP32;
   tmp.has_bf16 = o->precision == MMOT_BF16;
@@ -793,6 +810,7 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
   mmot_solver* s = new (std::nothrow) mmot_solver();
   if (!s) return MMOT_ENOMEM;
   s->n = p->n; s->L = p->L; s->T = p->T; s->nnz = p->nnz; s->kind = p->kind; s->eps = p->eps;
+  s->steps_k = p->cost_per_step ? p->T : 1;
   s->has_kl = p->state_cost != nullptr;
   s->opt = *o;
   if (s->opt.check_every < 1) s->opt.check_every = 10;

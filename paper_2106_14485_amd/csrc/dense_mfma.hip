@@ -27,32 +27,129 @@
 namespace mmot {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GBM = 128, GBN = 128, GBK = 64;
 constexpr int kPadB16 = 8;   // LDS row padding (elements) for bf16 tiles
 constexpr int kPadF32 = 4;
 
-struct GemmArgs {
-  int n, Lp, L, lda;
-  const void* A;        // [n][lda] (bf16 or f32)
-  const float* B;       // panel [n][Lp]
-  const float* u;       // [n] scaling of the B rows, nullptr = 1
-  const float* fac;     // [Lp] output column factor
-  float* out;           // [n][Lp]
-  const float* kl;      // [n][Lp] K_L multiplied into the stored output, nullptr = none
-  int cap;              // 1: capacity partial sums (interior forward time)
-  const float* wpan;    // Psi_{t} panel at the output time
-  const float* wgt;     // [Lp]
-  float* part_s;        // [nTN][n] partial column sums
-  const float* ucur;    // check pass: u at the output time (per-commodity output)
-  double* pcomm;        // check pass: [L][n] per-commodity marginal, nullptr = none
-  uint32_t* slots;      // column levels of the stored output, nullptr = off
-  int nslot;
-  size_t slot_stride;
-};
+// Epilogue shared by the product kernels: range factor, K_L, store, the next
+// product's BF16 operand, capacity partial sums, column levels.
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2][2], int row0, int col0, int bn,
+                                              int logical) {
+  __shared__ float red[2][2][64];   // capacity partial sums across the two column waves
+  __shared__ float cmx[2][GBN];     // column maxima across the two row waves
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int lr = lane & 31, lh = lane >> 5;
+  (void)lane;
+  float colmax[2] = {-INFINITY, -INFINITY};
+  float rsum[2][16];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) rsum[i][r] = 0.f;
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int gc = col0 + wn * 64 + j * 32 + lr;
+    const bool cok = gc < a.Lp;
+    const int gcc = cok ? gc : 0;
+    const float f = cok ? a.fac[gcc] : 0.f;
+    const bool capc = a.cap && gc < a.L;
+    const float g = capc ? a.wgt[gcc] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      // operands of the epilogue, loaded unconditionally (clamped) before use
+      float klv[16], wv[16], uov[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int gr = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        const int grc = gr < a.n ? gr : a.n - 1;
+        const size_t off = (size_t)grc * a.Lp + gcc;
+        klv[r] = a.kl ? a.kl[off] : 1.f;
+        wv[r] = a.cap ? a.wpan[off] : 0.f;
+        uov[r] = a.bout ? a.uo[grc] : 0.f;
+      }
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int gr = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+        const bool ok = cok && gr < a.n;
+        const size_t off = (size_t)gr * a.Lp + gc;
+        const float o = acc[i][j][r] * f;
+        const float z = a.kl ? o * klv[r] : o;
+        if (ok) a.out[off] = z;
+        if (ok && z > 0.f) colmax[j] = fmaxf(colmax[j], z);
+        if (ok && capc) rsum[i][r] = fmaf(o * wv[r], g, rsum[i][r]);
+        if (a.pcomm && ok && capc) {
+          const double P = (double)o * (double)wv[r] * (double)g * (double)a.ucur[gr];
+          a.pcomm[(size_t)gc * a.n + gr] = P;
+        }
+      }
+      if (a.bout && cok) {
+        // next product's operand: bf16(u (.) stored value), k-blocked; the four rows
+        // r = 4q..4q+3 of this lane are consecutive within one block of 8
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int g0 = row0 + wm * 64 + i * 32 + 8 * q;          // multiple of 8
+          if (g0 >= a.n) continue;
+          bf16x4 p;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = 4 * q + e;
+            const int gr = g0 + 4 * lh + e;
+            const float o = acc[i][j][r] * f;
+            const float z = a.kl ? o * klv[r] : o;
+            p[e] = (__bf16)(gr < a.n ? z * uov[r] : 0.f);
+          }
+          *reinterpret_cast<bf16x4*>(a.bout + ((size_t)(g0 >> 3) * a.Lp + gc) * 8 + 4 * lh) = p;
+        }
+      }
+    }
+  }
+  if (a.cap) {
+    // reduce over the 32 lanes that share rows (same lane half), then over the two column waves
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        float v = rsum[i][r];
+        for (int m = 16; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+        rsum[i][r] = v;
+      }
+    if (lr == 0) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[wm][wn][i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)] = rsum[i][r];
+    }
+    __syncthreads();
+    if (tid < 128) {
+      const int wmr = tid >> 6, rr = tid & 63;
+      const int gr = row0 + wmr * 64 + rr;
+      if (gr < a.n) a.part_s[(size_t)bn * a.n + gr] = red[wmr][0][rr] + red[wmr][1][rr];
+    }
+  }
+  if (a.slots) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      float m = colmax[j];
+      m = fmaxf(m, __shfl_xor(m, 32, 64));
+      if (lh == 0) cmx[wm][wn * 64 + j * 32 + lr] = m;
+    }
+    __syncthreads();
+    if (tid < GBN) {
+      const float m = fmaxf(cmx[0][tid], cmx[1][tid]);
+      const int gc = col0 + tid;
+      if (gc < a.Lp && m > 0.f)
+        atomicMax(a.slots + (size_t)(logical % a.nslot) * a.slot_stride + gc, enc_f32(log2f(m)));
+    }
+  }
+}
 
-template <bool BF16>
+// BB (BF16 only): the B operand comes pre-scaled and k-blocked in BF16 (a.Bb),
+// staged by 16-byte copies like A; otherwise FP32 B is scaled by u and converted.
+template <bool BF16, bool BB>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   using TA = typename std::conditional<BF16, __bf16, float>::type;
   constexpr int PAD = BF16 ? kPadB16 : kPadF32;
@@ -60,8 +157,6 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   constexpr int AV = BF16 ? 4 : 8;          // 16-byte A chunks per thread per stage
   __shared__ TA As[2][GBM * LDK];
   __shared__ TA Bs[2][GBN * LDK];
-  __shared__ float red[2][2][64];   // capacity partial sums across the two column waves
-  __shared__ float cmx[2][GBN];     // column maxima across the two row waves
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -92,8 +187,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   // back and the wave waits once per stage, not once per load.
   uint4 ra[AV];
   uint32_t aok = 0;   // bit v: chunk v of A lies inside the matrix (applied at the LDS write)
-  float4 rb[8];
-  float ru[8];
+  float4 rb[BB ? 1 : 8];
+  float ru[BB ? 1 : 8];
+  uint4 rbb[BB ? 4 : 1];
   uint32_t bok = 0;   // bit e: k row e of the B chunk lies inside the matrix
   // B: thread owns 4 consecutive columns (16-byte loads along the panel row)
   // and 8 consecutive k of the stage
@@ -116,16 +212,30 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
       if (v == 0) aok = 0;
       aok |= (gr < a.n && gk < a.lda) ? (1u << v) : 0u;
     }
+    if constexpr (BB) {
+      // 8 k-blocks x 128 columns of 16 bytes; consecutive lanes take consecutive columns
+      bok = 0;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int gk = k0 + kg * 8 + e;
-      const int gkc = gk < a.n ? gk : a.n - 1;
-      rb[e] = *reinterpret_cast<const float4*>(a.B + (size_t)gkc * a.Lp + gcb_c);
-      ru[e] = has_u ? a.u[gkc] : 1.f;
+      for (int v = 0; v < 4; ++v) {
+        const int c = tid + v * 256;
+        const int kb = c >> 7, cl = c & 127;
+        const int gkb = (k0 >> 3) + kb, gc = col0 + cl;
+        const bool ok = gkb < (a.n8 >> 3) && gc < a.Lp;
+        rbb[v] = *reinterpret_cast<const uint4*>(a.Bb + ((size_t)(ok ? gkb : 0) * a.Lp + (ok ? gc : 0)) * 8);
+        bok |= ok ? (1u << v) : 0u;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int gk = k0 + kg * 8 + e;
+        const int gkc = gk < a.n ? gk : a.n - 1;
+        rb[e] = *reinterpret_cast<const float4*>(a.B + (size_t)gkc * a.Lp + gcb_c);
+        ru[e] = has_u ? a.u[gkc] : 1.f;
+      }
+      bok = 0;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) bok |= (k0 + kg * 8 + e < a.n && bcol_ok) ? (1u << e) : 0u;
     }
-    bok = 0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) bok |= (k0 + kg * 8 + e < a.n && bcol_ok) ? (1u << e) : 0u;
   };
   auto swrite = [&](int buf) {
     TA* as = As[buf];
@@ -146,24 +256,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
             make_float2(__uint_as_float(ra[v].y), __uint_as_float(ra[v].w));
       }
     }
-    // scale by u (zero outside the matrix) and store column-major: Bs[col][k]
+    if constexpr (BB) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float x[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float b = (q == 0) ? rb[e].x : (q == 1) ? rb[e].y : (q == 2) ? rb[e].z : rb[e].w;
-        x[e] = ((bok >> e) & 1u) ? b * ru[e] : 0.f;
+      for (int v = 0; v < 4; ++v) {
+        const int c = tid + v * 256;
+        const int kb = c >> 7, cl = c & 127;
+        const uint4 x = ((bok >> v) & 1u) ? rbb[v] : make_uint4(0, 0, 0, 0);
+        *reinterpret_cast<uint4*>(&bs[cl * LDK + kb * 8]) = x;
       }
-      if (BF16) {
-        bf16x8 p;
+    } else {
+      // scale by u (zero outside the matrix) and store column-major: Bs[col][k]
 #pragma unroll
-        for (int e = 0; e < 8; ++e) p[e] = (__bf16)x[e];
-        *reinterpret_cast<bf16x8*>(&bs[(cq * 4 + q) * LDK + kg * 8]) = p;
-      } else {
-        float* dst = reinterpret_cast<float*>(&bs[(cq * 4 + q) * LDK]);
-        *reinterpret_cast<float4*>(&dst[kg * 4]) = make_float4(x[0], x[2], x[4], x[6]);
-        *reinterpret_cast<float4*>(&dst[32 + kg * 4]) = make_float4(x[1], x[3], x[5], x[7]);
+      for (int q = 0; q < 4; ++q) {
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float b = (q == 0) ? rb[e].x : (q == 1) ? rb[e].y : (q == 2) ? rb[e].z : rb[e].w;
+          x[e] = ((bok >> e) & 1u) ? b * ru[e] : 0.f;
+        }
+        if (BF16) {
+          bf16x8 p;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) p[e] = (__bf16)x[e];
+          *reinterpret_cast<bf16x8*>(&bs[(cq * 4 + q) * LDK + kg * 8]) = p;
+        } else {
+          float* dst = reinterpret_cast<float*>(&bs[(cq * 4 + q) * LDK]);
+          *reinterpret_cast<float4*>(&dst[kg * 4]) = make_float4(x[0], x[2], x[4], x[6]);
+          *reinterpret_cast<float4*>(&dst[32 + kg * 4]) = make_float4(x[1], x[3], x[5], x[7]);
+        }
       }
     }
   };
@@ -237,87 +357,124 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
     __syncthreads();
   }
 
-  // ---- epilogue ----
-  float colmax[2] = {-INFINITY, -INFINITY};
-  float rsum[2][16];
+  gemm_epilogue(a, acc, row0, col0, bn, logical);
+}
+
+// ---------------------------------------------------------------------------
+// BF16 product with both operands in BF16 (A = K or K^T, B = the pre-scaled
+// k-blocked operand): a four-stage ring of LDS buffers filled by direct
+// global->LDS 16-byte loads (no registers in between), so three K-stages are
+// in flight while one is on the matrix cores.  Tile 128 x 128, K-depth 64 per
+// stage, four waves 2 x 2 as in k_gemm.  Rows of a stage are 8 chunks of 16
+// bytes; chunk c of row r sits at slot 8r + (c ^ ((r >> 1) & 7)), which keeps
+// the MFMA operand reads of 16 consecutive rows on distinct LDS banks.  The K
+// extent is padded with zeros to a multiple of 64 in both operands (lda and
+// the operand's row count), so every stage loads inside the buffers; rows and
+// columns past the matrix read clamped addresses and only feed outputs that
+// the epilogue discards.
+// ---------------------------------------------------------------------------
+constexpr int kStages = 4;
+constexpr int kSlots = GBM * GBK / 8;   // 16-byte slots per operand per stage
+
+__device__ __forceinline__ int swz_slot(int r, int c) { return r * 8 + (c ^ ((r >> 1) & 7)); }
+
+// One direct global->LDS copy of 16 bytes per lane: lane l writes LDS bytes
+// [lds_byte + 16 l, lds_byte + 16 l + 16).  Written as asm so that the compiler
+// does not make every later LDS read wait for all copies in flight (it cannot
+// tell the ring slots apart); the kernel orders them with explicit waits.  The
+// instruction writes LDS only, no registers.
+__device__ __forceinline__ void lds_copy16(const void* g, uint32_t lds_byte) {
+  asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds_byte) : "memory", "m0");
+}
+__device__ __forceinline__ uint32_t lds_addr(const void* p) {
+  return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void*)p;
+}
+
+// s_waitcnt immediate: wait until at most n vector-memory operations are outstanding
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+__global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
+  __shared__ uint4 lds[kStages][2][kSlots];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int nbm = gridDim.x, nbn = gridDim.y;
+  const int hw = blockIdx.y * nbm + blockIdx.x;
+  const int tot = nbm * nbn;
+  int logical = hw;
+  if ((tot & 7) == 0) logical = (hw & 7) * (tot >> 3) + (hw >> 3);
+  const int bn = logical % nbn, bm = logical / nbn;
+  const int row0 = bm * GBM, col0 = bn * GBN;
+  const uint16_t* A = static_cast<const uint16_t*>(a.A);
+
+  // this lane's four slots per operand and stage (wave instruction q covers 64 slots)
+  size_t aoff[4], boff[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int slot = (wave * 4 + q) * 64 + lane;
+    const int r = slot >> 3, c = (slot & 7) ^ ((r >> 1) & 7);
+    const int gr = min(row0 + r, a.n - 1), gc = min(col0 + r, a.Lp - 1);
+    aoff[q] = (size_t)gr * a.lda + c * 8;            // + k0
+    boff[q] = ((size_t)c * a.Lp + gc) * 8;           // + (k0 / 8) * Lp * 8
+  }
+  auto issue = [&](int st, int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      lds_copy16(A + aoff[q] + k0, lds_addr(&lds[st][0][(wave * 4 + q) * 64]));
+      lds_copy16(a.Bb + boff[q] + (size_t)(k0 >> 3) * a.Lp * 8, lds_addr(&lds[st][1][(wave * 4 + q) * 64]));
+    }
+  };
+
+  f32x16 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) rsum[i][r] = 0.f;
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int gc = col0 + wn * 64 + j * 32 + lr;
-    const bool cok = gc < a.Lp;
-    const int gcc = cok ? gc : 0;
-    const float f = cok ? a.fac[gcc] : 0.f;
-    const bool capc = a.cap && gc < a.L;
-    const float g = capc ? a.wgt[gcc] : 0.f;
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+
+  const int nk = (a.n + GBK - 1) / GBK;
+  for (int st = 0; st < kStages - 1 && st < nk; ++st) issue(st, st * GBK);
+  const int lr = lane & 31, lh = lane >> 5;
+  for (int kt = 0; kt < nk; ++kt) {
+    // this thread's loads of stage kt have landed once at most the later
+    // stages' loads (8 per stage) are outstanding; the barrier extends that to
+    // the whole block and frees the ring slot read in the previous stage
+    const int later = min(kStages - 2, nk - 1 - kt);
+    if (later >= 2) wait_vm<16>();
+    else if (later == 1) wait_vm<8>();
+    else wait_vm<0>();
+    // a bare barrier: the waits above already made this thread's ring writes
+    // complete; a fenced barrier would also wait for the stages still in flight
+    asm volatile("s_barrier" ::: "memory");
+    if (kt + kStages - 1 < nk) issue((kt + kStages - 1) % kStages, (kt + kStages - 1) * GBK);
+    const uint4* as = lds[kt % kStages][0];
+    const uint4* bs = lds[kt % kStages][1];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      // operands of the epilogue, loaded unconditionally (clamped) before use
-      float klv[16], wv[16];
+    for (int ks = 0; ks < GBK / 16; ++ks) {
+      bf16x8 af[2], bf[2];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int gr = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-        const size_t off = (size_t)(gr < a.n ? gr : a.n - 1) * a.Lp + gcc;
-        klv[r] = a.kl ? a.kl[off] : 1.f;
-        wv[r] = a.cap ? a.wpan[off] : 0.f;
+      for (int i = 0; i < 2; ++i) {
+        const uint4 v = as[swz_slot(wm * 64 + i * 32 + lr, ks * 2 + lh)];
+        af[i] = __builtin_bit_cast(bf16x8, v);
       }
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int gr = row0 + wm * 64 + i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
-        const bool ok = cok && gr < a.n;
-        const size_t off = (size_t)gr * a.Lp + gc;
-        const float o = acc[i][j][r] * f;
-        const float z = a.kl ? o * klv[r] : o;
-        if (ok) a.out[off] = z;
-        if (ok && z > 0.f) colmax[j] = fmaxf(colmax[j], z);
-        if (ok && capc) rsum[i][r] = fmaf(o * wv[r], g, rsum[i][r]);
-        if (a.pcomm && ok && capc) {
-          const double P = (double)o * (double)wv[r] * (double)g * (double)a.ucur[gr];
-          a.pcomm[(size_t)gc * a.n + gr] = P;
-        }
+      for (int j = 0; j < 2; ++j) {
+        const uint4 v = bs[swz_slot(wn * 64 + j * 32 + lr, ks * 2 + lh)];
+        bf[j] = __builtin_bit_cast(bf16x8, v);
       }
-    }
-  }
-  if (a.cap) {
-    // reduce over the 32 lanes that share rows (same lane half), then over the two column waves
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        float v = rsum[i][r];
-        for (int m = 16; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
-        rsum[i][r] = v;
-      }
-    if (lr == 0) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) red[wm][wn][i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)] = rsum[i][r];
-    }
-    __syncthreads();
-    if (tid < 128) {
-      const int wmr = tid >> 6, rr = tid & 63;
-      const int gr = row0 + wmr * 64 + rr;
-      if (gr < a.n) a.part_s[(size_t)bn * a.n + gr] = red[wmr][0][rr] + red[wmr][1][rr];
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
     }
   }
-  if (a.slots) {
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      float m = colmax[j];
-      m = fmaxf(m, __shfl_xor(m, 32, 64));
-      if (lh == 0) cmx[wm][wn * 64 + j * 32 + lr] = m;
-    }
-    __syncthreads();
-    if (tid < GBN) {
-      const float m = fmaxf(cmx[0][tid], cmx[1][tid]);
-      const int gc = col0 + tid;
-      if (gc < a.Lp && m > 0.f)
-        atomicMax(a.slots + (size_t)(logical % a.nslot) * a.slot_stride + gc, enc_f32(log2f(m)));
-    }
-  }
+  __syncthreads();
+  gemm_epilogue(a, acc, row0, col0, bn, logical);
 }
 
 // ---------------------------------------------------------------------------
@@ -327,7 +484,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
 // sums: s_j = sum_p part_s[p][j]; update: u_j = 1 if s_j <= d_j else d_j / s_j;
 // check: occupancy u_j s_j and the capacity / dual / gap statistics.
 __global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, const float* __restrict__ cap,
-                             float* __restrict__ u, int update, double* part, double* occ) {
+                             float* __restrict__ u, int update, double* part, double* occ, const float* __restrict__ x,
+                             uint16_t* __restrict__ bout, int Lp) {
   double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int per = (n + gridDim.x - 1) / gridDim.x;
   const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
@@ -347,6 +505,26 @@ __global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, c
       }
       if (!isfinite(occv)) st[ST_NONFINITE] += 1.0;
       if (occ) occ[j] = occv;
+    }
+  }
+  if (bout) {
+    // the next product's operand: bf16(u_j x_j) for this block's rows, k-blocked
+    // (element (j, c) at ((j/8) Lp + c) 8 + j%8); u of these rows is final here
+    __syncthreads();
+    __bf16* bo = reinterpret_cast<__bf16*>(bout);
+    const bool quad = ((r0 | (r1 - r0)) & 3) == 0;
+    for (int c = threadIdx.x; c < Lp; c += blockDim.x) {
+      if (quad) {
+        for (int j = r0; j < r1; j += 4) {
+          bf16x4 p;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) p[e] = (__bf16)(u[j + e] * x[(size_t)(j + e) * Lp + c]);
+          *reinterpret_cast<bf16x4*>(bo + ((size_t)(j >> 3) * Lp + c) * 8 + (j & 7)) = p;
+        }
+      } else {
+        for (int j = r0; j < r1; ++j)
+          bo[((size_t)(j >> 3) * Lp + c) * 8 + (j & 7)] = (__bf16)(u[j] * x[(size_t)j * Lp + c]);
+      }
     }
   }
   if (part) {
@@ -479,13 +657,15 @@ __global__ void k_dense_rowsum_max(const float* __restrict__ K, int n, int lda, 
 // launchers
 void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
   dim3 grid((a.n + GBM - 1) / GBM, (a.Lp + GBN - 1) / GBN);
-  if (bf16) hipLaunchKernelGGL(k_gemm<true>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_gemm<false>, grid, dim3(256), 0, s, a);
+  if (bf16 && a.Bb) hipLaunchKernelGGL(k_gemm_lds, grid, dim3(256), 0, s, a);
+  else if (bf16) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, a);
 }
 int gemm_col_tiles(int Lp) { return (Lp + GBN - 1) / GBN; }
 void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, float* u, int update, double* part,
-                       double* occ, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_rows, dim3(nblk), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ);
+                       double* occ, const float* x, uint16_t* bout, int Lp, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_rows, dim3(nblk), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ, x, bout,
+                     Lp);
 }
 void launch_dense_sink(int n, int Lp, int L, const float* hat, const float* rdst, float* u0t, int update,
                        const double* sigT, const double* sighT, uint32_t* slotsE, int nslot, uint32_t* slots_o,
@@ -496,7 +676,8 @@ void launch_dense_sink(int n, int Lp, int L, const float* hat, const float* rdst
 }
 void launch_dense_gibbs(const double* C, int n, int lda, double eps, float* K, float* Kt, void* Kb, void* Ktb,
                         hipStream_t s) {
-  dim3 grid((lda + 31) / 32, (n + 31) / 32);
+  // both grid dimensions cover lda, so the zero padding columns of K^T are written too
+  dim3 grid((lda + 31) / 32, (lda + 31) / 32);
   hipLaunchKernelGGL(k_dense_gibbs, grid, dim3(256), 0, s, C, n, lda, eps, K, Kt, static_cast<__bf16*>(Kb),
                      static_cast<__bf16*>(Ktb));
 }

@@ -162,6 +162,34 @@ struct Reduce2Args {
   double* out;
 };
 
+// Dense product OUT[n x Lp] = A[n x n] diag(u) B[n x Lp] on MFMA (see dense_mfma.hip).
+struct GemmArgs {
+  int n, Lp, L, lda;
+  const void* A;        // [n][lda] (bf16 or f32), lda a multiple of 64, zero beyond n
+  const float* B;       // panel [n][Lp] (FP32 operand), scaled by u while staged
+  const float* u;       // [n] scaling of the B rows, nullptr = 1
+  // BF16 operand already scaled by u, k-blocked: element (k, c) at ((k/8)*Lp + c)*8 + k%8,
+  // rows padded to a multiple of 64 with zeros; when set, B and u are not read
+  const uint16_t* Bb;
+  int n8;               // rows of Bb (n rounded up to 64, zero padding)
+  const float* fac;     // [Lp] output column factor
+  float* out;           // [n][Lp]
+  const float* kl;      // [n][Lp] K_L multiplied into the stored output, nullptr = none
+  // epilogue: also store bf16(uo[row] * stored value) k-blocked into bout (the
+  // next product's operand); nullptr = off
+  uint16_t* bout;
+  const float* uo;
+  int cap;              // 1: capacity partial sums (interior forward time)
+  const float* wpan;    // Psi_{t} panel at the output time
+  const float* wgt;     // [Lp]
+  float* part_s;        // [nTN][n] partial column sums
+  const float* ucur;    // check pass: u at the output time (per-commodity output)
+  double* pcomm;        // check pass: [L][n] per-commodity marginal, nullptr = none
+  uint32_t* slots;      // column levels of the stored output, nullptr = off
+  int nslot;
+  size_t slot_stride;
+};
+
 // Work items of the serving pool: one recorded kernel launch of one solve.
 // A pool tick runs the next item of every active solve in one launch.
 enum ItemKind {

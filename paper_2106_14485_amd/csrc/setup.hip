@@ -12,7 +12,7 @@ __global__ void k_validate_vals(const double* __restrict__ x, size_t cnt, int al
                                 int allow_neg, int* flags) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < cnt; i += (size_t)gridDim.x * blockDim.x) {
     const double v = x[i];
-    bool bad = isnan(v);
+    bool bad = isnan(v) || (isinf(v) && v < 0);   // -inf is never a valid cost, mass or capacity
     if (!allow_inf && isinf(v)) bad = true;
     if (!allow_neg && v < 0) bad = true;
     if (strictly_pos && !(v > 0)) bad = true;
@@ -289,7 +289,9 @@ __global__ void k_excess_rows(const int* __restrict__ rp, const int* __restrict_
   double wait = 0.0;
   for (int e = rp[i]; e < rp[i + 1]; ++e) if (ci[e] == i) wait = cost[e];
   double s = 0.0; int c = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) if (ci[e] != i) { s += fmax(cost[e] - wait, 0.0); ++c; }
+  // (moves closed at this step, +inf, carry no range)
+  for (int e = rp[i]; e < rp[i + 1]; ++e)
+    if (ci[e] != i && isfinite(cost[e])) { s += fmax(cost[e] - wait, 0.0); ++c; }
   rowsum[i] = s; rowcnt[i] = c;
 }
 __global__ void k_excess_total(const double* __restrict__ rowsum, const int* __restrict__ rowcnt, int n,

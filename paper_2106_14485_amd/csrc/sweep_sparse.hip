@@ -722,7 +722,7 @@ __global__ __launch_bounds__(kBlock) void k_flows(int n, int Lp, int L, int G, i
       }
       if (gl == 0) {
         flow[e] = F;
-        st[0] += cost[e] * F;
+        if (F > 0.0) st[0] += cost[e] * F;   // a move closed at this step (+inf cost) carries nothing
       }
     }
   }

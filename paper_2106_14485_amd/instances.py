@@ -40,6 +40,8 @@ __all__ = [
     "edge_state_instance",
     "sparse_grid_edge_instance",
     "dense_random_edge_instance",
+    "time_varying_instance",
+    "staggered_instance",
 ]
 
 
@@ -55,7 +57,9 @@ class Instance:
     cap: (n,) applied at every interior time 1..T-1, or (T-1, n); +inf means
     uncapacitated.  src / dst: (L, n) nonnegative, equal row sums (the
     commodity masses).  state_cost: optional (L, n) per-commodity state cost
-    charged at interior times (None means zero).
+    charged at interior times (None means zero).  A time-varying network
+    (Section 3.3) has cost of shape (T, nnz): row tau prices the moves from
+    time tau to tau+1 (same pattern; +inf closes a move at that step).
     """
 
     name: str
@@ -86,9 +90,13 @@ class Instance:
             return np.broadcast_to(self.cap, (max(self.T - 1, 0), self.n)).copy()
         return self.cap.copy()
 
-    def cost_csr(self) -> sp.csr_matrix:
-        """The transition cost matrix as scipy CSR (finite entries only)."""
+    def cost_csr(self):
+        """The transition cost matrix as scipy CSR (the allowed moves); for a
+        time-varying network (cost of shape (T, nnz)) the list of the T
+        per-step matrices, +inf marking a move closed at that step."""
         if self.kind == "csr":
+            if np.ndim(self.cost) == 2:
+                return [sp.csr_matrix((c, self.colidx, self.rowptr), shape=(self.n, self.n)) for c in self.cost]
             return sp.csr_matrix((self.cost, self.colidx, self.rowptr), shape=(self.n, self.n))
         r, c = np.nonzero(np.isfinite(self.cost_dense))
         return sp.csr_matrix((self.cost_dense[r, c], (r, c)), shape=(self.n, self.n))
@@ -504,6 +512,100 @@ def dense_random_edge_instance(nv: int = 40, p: float = 0.5, L: int = 100, T: in
     return edge_state_instance(nv, edges, L, T, eps, cost, src_vertex=s, dst_vertex=z, mass=np.ones(L),
                                cap_edge=1.0, terminals="storage", cap_vertex=float(L),
                                name=f"denseedges{nv}")
+
+
+def time_varying_instance(base: Instance, seed: int = 0, peak: float = 1.5, closed_frac: float = 0.03,
+                          closed_span: float = 0.3) -> Instance:
+    """A time-varying version of a CSR instance (Section 3.3: C_tau per move).
+
+    Moves between distinct states cost base * (1 + peak * rush(tau)) with a
+    smooth rush-hour profile rush(tau) = sin^2(pi tau / T) (waiting keeps its
+    cost); a seeded closed_frac of the state pairs have both directions closed
+    (+inf) during one window of closed_span * T consecutive steps at a seeded
+    start.  The source/sink draws of the base instance are kept."""
+    assert base.kind == "csr"
+    rng = np.random.default_rng(seed)
+    T = base.T
+    rows = np.repeat(np.arange(base.n), np.diff(base.rowptr))
+    move = rows != base.colidx
+    tau = np.arange(T)
+    rush = np.sin(np.pi * tau / max(T, 1)) ** 2
+    cost = np.tile(base.cost, (T, 1))
+    cost[:, move] *= (1.0 + peak * rush)[:, None]
+    a = np.minimum(rows, base.colidx).astype(np.int64)
+    b = np.maximum(rows, base.colidx).astype(np.int64)
+    pair_id = a * base.n + b
+    pairs = np.unique(pair_id[move])
+    shut = rng.choice(pairs, size=int(round(closed_frac * len(pairs))), replace=False)
+    span = max(1, int(round(closed_span * T)))
+    for pid in shut:
+        t0 = int(rng.integers(0, max(1, T - span + 1)))
+        cost[t0:t0 + span, pair_id == pid] = np.inf
+    return dataclasses.replace(base, name=base.name + "-tv", cost=cost, meta={**base.meta, "closed_pairs": shut})
+
+
+def staggered_instance(base: Instance, enter: np.ndarray, leave: np.ndarray) -> Instance:
+    """Commodities that enter and leave the network at their own times (Remark 8
+    and Section 3.3), in the one-tensor form of the solver.
+
+    base: a CSR instance with one source and one sink state per commodity
+    (fixed or time-varying costs).  Commodity l is at its source s_l at time
+    enter[l] and at its sink z_l at time leave[l] (0 <= enter < leave <= T) and
+    counts against the capacities only in between.  Encoding, with a
+    time-varying network: a holding state per distinct (enter > 0, s) where
+    the commodity waits outside the network; it leads only to s, by the move
+    enter-1 -> enter; an exit state per distinct (leave < T, z), reached from
+    z only by the move leave -> leave+1 and kept afterwards.  Holding and exit
+    states are uncapacitated and cost nothing; the source marginal sits on the
+    holding state (or on s when enter = 0), the sink marginal on the exit state
+    (or on z when leave = T)."""
+    assert base.kind == "csr"
+    L, n, T = base.L, base.n, base.T
+    enter = np.asarray(enter, dtype=np.int64); leave = np.asarray(leave, dtype=np.int64)
+    assert np.all(0 <= enter) and np.all(enter < leave) and np.all(leave <= T)
+    assert np.all((base.src > 0).sum(axis=1) == 1) and np.all((base.dst > 0).sum(axis=1) == 1)
+    s_of = base.src.argmax(axis=1); z_of = base.dst.argmax(axis=1); mass = base.src.sum(axis=1)
+    hold = {}; exit_ = {}
+    for l in range(L):
+        if enter[l] > 0:
+            hold.setdefault((int(enter[l]), int(s_of[l])), n + len(hold))
+    for l in range(L):
+        if leave[l] < T:
+            exit_.setdefault((int(leave[l]), int(z_of[l])), n + len(hold) + len(exit_))
+    n2 = n + len(hold) + len(exit_)
+    base_cost = base.cost if np.ndim(base.cost) == 2 else np.tile(base.cost, (T, 1))
+    rows = list(np.repeat(np.arange(n), np.diff(base.rowptr))); cols = list(base.colidx)
+    steps = [list(base_cost[:, e]) for e in range(base.nnz)]
+    inf = np.inf
+
+    def add(i, j, open_at):
+        rows.append(i); cols.append(j)
+        steps.append([0.0 if open_at(tau) else inf for tau in range(T)])
+
+    for (a, sn), h in hold.items():
+        add(h, h, lambda tau, a=a: tau < a - 1)          # wait outside the network
+        add(h, sn, lambda tau, a=a: tau == a - 1)        # enter at time a
+    for (b, zn), x in exit_.items():
+        add(zn, x, lambda tau, b=b: tau == b)            # leave right after time b
+        add(x, x, lambda tau, b=b: tau > b)              # and stay out
+    order = np.lexsort((np.array(cols), np.array(rows)))
+    rows = np.array(rows)[order]; cols = np.array(cols)[order]
+    cost = np.array(steps, dtype=np.float64)[order].T.copy()           # (T, nnz2)
+    rowptr = np.zeros(n2 + 1, dtype=np.int32)
+    np.add.at(rowptr, rows + 1, 1)
+    rowptr = np.cumsum(rowptr).astype(np.int32)
+    src = np.zeros((L, n2)); dst = np.zeros((L, n2))
+    for l in range(L):
+        src[l, hold[(int(enter[l]), int(s_of[l]))] if enter[l] > 0 else s_of[l]] = mass[l]
+        dst[l, exit_[(int(leave[l]), int(z_of[l]))] if leave[l] < T else z_of[l]] = mass[l]
+    cap = base.cap_full()
+    cap = np.concatenate([cap, np.full((cap.shape[0], n2 - n), np.inf)], axis=1)
+    sc = None
+    if base.state_cost is not None:
+        sc = np.concatenate([base.state_cost, np.zeros((L, n2 - n))], axis=1)
+    return Instance(name=base.name + "-staggered", n=n2, L=L, T=T, eps=base.eps, kind="csr", src=src, dst=dst,
+                    cap=cap, rowptr=rowptr, colidx=cols.astype(np.int32), cost=cost, state_cost=sc,
+                    meta={**base.meta, "enter": enter, "leave": leave, "n_network": n, "s_of": s_of, "z_of": z_of})
 
 
 # ----------------------------------------------------------------------------

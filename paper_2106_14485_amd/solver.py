@@ -52,6 +52,7 @@ def device_problem(inst, device="cuda"):
         keep += [rp, ci, c]
         p.rowptr, p.colidx, p.cost = _ptr(rp), _ptr(ci), _ptr(c)
         p.nnz = int(inst.rowptr[-1])
+        p.cost_per_step = 1 if np.ndim(inst.cost) == 2 else 0     # (T, nnz): time-varying network
     else:
         p.kind = _lib.MMOT_DENSE
         cd = dt(inst.cost_dense, torch.float64)

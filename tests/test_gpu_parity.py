@@ -38,9 +38,8 @@ def oracle_outputs(inst, n_iter, log=False):
         with np.errstate(divide="ignore"):
             duals = (np.log(st.U01), np.log(st.U0T), np.log(st.u))
         g = st.g
-    C = inst.cost_csr()
-    rows = np.repeat(np.arange(inst.n), np.diff(C.indptr))
-    flows = np.stack([np.asarray(f.tocsr()[rows, C.indices]).ravel() for f in out["flows"]])
+    rows = np.repeat(np.arange(inst.n), np.diff(inst.rowptr))
+    flows = np.stack([np.asarray(f.tocsr()[rows, inst.colidx]).ravel() for f in out["flows"]])
     return dict(Pt=out["Pt"], P0t=out["P0t"], flows=flows, cost=out["cost"], duals=duals, g=g, floor=floor)
 
 
@@ -369,4 +368,30 @@ def test_edge_lift_dense_random_network():
     assert g["stats"]["domain"] == 2
     compare(g, o, max(1e-5, o["floor"]))
     g64 = gpu_outputs(inst, 10, "fp64", "log")
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# time-varying networks: one cost matrix per move (rush hour, closures)
+# ---------------------------------------------------------------------------
+
+def test_time_varying_rgg_scaled_domain():
+    base = instances.rgg_instance(n=400, L=24, T=12, seed=21, cap_lo=0.5, cap_hi=1.5)
+    inst = instances.time_varying_instance(base, seed=4, peak=1.0, closed_frac=0.05)
+    assert np.isinf(inst.cost).any()
+    o = oracle_outputs(inst, 15)
+    g = gpu_outputs(inst, 15, "fp32", "scaled")
+    compare(g, o, 1e-5)
+    g64 = gpu_outputs(inst, 15, "fp64", "scaled")
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+
+
+def test_time_varying_road_grid_log_domain():
+    base = instances.road_grid_instance(side=10, L=20, T=24, eps=0.1, seed=3)
+    inst = instances.time_varying_instance(base, seed=2)
+    o = oracle_outputs(inst, 15, log=True)
+    g = gpu_outputs(inst, 15, "fp32", "auto")
+    assert g["stats"]["domain"] == 2
+    compare(g, o, max(1e-5, o["floor"]))
+    g64 = gpu_outputs(inst, 15, "fp64", "log")
     compare(g64, o, 1e-12, duals_tol=1e-8)
