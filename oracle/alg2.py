@@ -36,9 +36,20 @@ Readings where the paper is silent or inconsistent:
   * Zero marginals (Theorem 4): U = 0 where R = 0; a positive R facing a zero
     message is infeasible (error).  min(d/s, 1) is evaluated as 1 when s <= d
     (no division; covers s = 0 and d = +inf).
+  * Commodity-dependent capacities (the extension closing Section 3:
+    P_{0,tau} <= D_tau, (T-1) x L x n, +inf = none) get one more dual
+    scaling w_tau (L x n, in (0, 1]) per interior time, multiplying K_L at
+    that time in every message and projection.  In the forward sweep, at
+    time tau, w_tau is projected first with the current u_tau,
+        w_tau = min(D_tau ./ (hatPsi (.) Psi (.) KL (.) u_tau), 1),
+    then u_tau with the new w_tau (both are exact Bregman projections, so
+    any fixed order is a valid block-coordinate ascent step).  Where
+    D_tau = 0 the scaling is 0 (the state is closed to that commodity;
+    where it already carries no mass any value would do, 0 is chosen).
   * Dual objective (Theorem 3, with u = exp(-lambda/eps)):
-      g = eps * (<log U01, R01> + <log U0T, R0T> + sum_tau <log u_tau, d_tau>)
-          - eps * <K, U>,     with 0 log 0 = 0 and d = +inf contributing 0.
+      g = eps * (<log U01, R01> + <log U0T, R0T> + sum_tau <log u_tau, d_tau>
+                 + sum_tau <log w_tau, D_tau>) - eps * <K, U>,
+      with 0 log 0 = 0 and d, D = +inf contributing 0.
 """
 from __future__ import annotations
 
@@ -70,6 +81,7 @@ class Problem:
     dst: np.ndarray           # R^(0,TT), (L, n)
     cap: np.ndarray           # (T-1, n), +inf = uncapacitated
     state_cost: Optional[np.ndarray] = None   # C_L, (L, n)
+    cap_comm: Optional[np.ndarray] = None     # D, (T-1, L, n), +inf = none; None = no such constraints
 
     @property
     def L(self):
@@ -80,7 +92,7 @@ class Problem:
         return self.src.shape[1]
 
 
-def make_problem(C, eps, T, src, dst, cap, state_cost=None) -> Problem:
+def make_problem(C, eps, T, src, dst, cap, state_cost=None, cap_comm=None) -> Problem:
     src = np.asarray(src, dtype=np.float64)
     n = src.shape[1]
     cap = np.asarray(cap, dtype=np.float64)
@@ -94,8 +106,14 @@ def make_problem(C, eps, T, src, dst, cap, state_cost=None) -> Problem:
     else:
         C = one(C)
     sc = None if state_cost is None else np.asarray(state_cost, dtype=np.float64)
+    cc = None
+    if cap_comm is not None:
+        cc = np.asarray(cap_comm, dtype=np.float64)
+        if cc.ndim == 2:
+            cc = np.broadcast_to(cc, (max(T - 1, 0),) + cc.shape).copy()
+        assert cc.shape == (max(T - 1, 0),) + src.shape
     return Problem(C=C, eps=float(eps), T=int(T), src=src,
-                   dst=np.asarray(dst, dtype=np.float64), cap=cap, state_cost=sc)
+                   dst=np.asarray(dst, dtype=np.float64), cap=cap, state_cost=sc, cap_comm=cc)
 
 
 def _gibbs_one(C, eps):
@@ -148,11 +166,18 @@ class State:
     u: np.ndarray             # (T-1, n): u[tau-1] is the scaling at interior time tau
     psi: np.ndarray           # (T, L, n): psi[tau] = Psi_{tau+1}
     g: list
+    w: Optional[np.ndarray] = None   # (T-1, L, n) commodity-capacity scalings (None: no such constraints)
 
 
 def initial_state(p: Problem) -> State:
+    w = None if p.cap_comm is None else np.ones((max(p.T - 1, 0), p.L, p.n))
     return State(U01=np.zeros((p.L, p.n)), U0T=(p.dst > 0).astype(np.float64),
-                 u=np.ones((max(p.T - 1, 0), p.n)), psi=np.zeros((p.T, p.L, p.n)), g=[])
+                 u=np.ones((max(p.T - 1, 0), p.n)), psi=np.zeros((p.T, p.L, p.n)), g=[], w=w)
+
+
+def _klw(KL, w, tau):
+    """K_L at interior time tau, times the commodity-capacity scaling w_tau."""
+    return KL if w is None else KL * w[tau - 1]
 
 
 def backward_sweep(p: Problem, st: State, K=None, KL=None) -> None:
@@ -161,7 +186,7 @@ def backward_sweep(p: Problem, st: State, K=None, KL=None) -> None:
     KL = gibbs_state(p) if KL is None else KL
     st.psi[p.T - 1] = _right_t(st.U0T, _kat(K, p.T - 1))
     for tau in range(p.T - 1, 0, -1):
-        st.psi[tau - 1] = _right_t(st.psi[tau] * KL * st.u[tau - 1][None, :], _kat(K, tau - 1))
+        st.psi[tau - 1] = _right_t(st.psi[tau] * _klw(KL, st.w, tau) * st.u[tau - 1][None, :], _kat(K, tau - 1))
 
 
 def _divide_support(R, msg, what):
@@ -194,16 +219,29 @@ def forward_sweep(p: Problem, st: State, K=None, KL=None, update: bool = True,
     kept = [None, ph] if keep else None
     for tau in range(1, p.T):
         if update:
-            s = (ph * st.psi[tau] * KL).sum(axis=0)
+            q = ph * st.psi[tau] * KL                  # P_{0,tau} without u_tau and w_tau
+            if st.w is not None:
+                st.w[tau - 1] = _comm_update(q * st.u[tau - 1][None, :], p.cap_comm[tau - 1])
+                q = q * st.w[tau - 1]
+            s = q.sum(axis=0)
             d = p.cap[tau - 1]
             u = np.ones(p.n)
             over = s > d
             u[over] = d[over] / s[over]
             st.u[tau - 1] = u
-        ph = _right(ph * KL * st.u[tau - 1][None, :], _kat(K, tau))
+        ph = _right(ph * _klw(KL, st.w, tau) * st.u[tau - 1][None, :], _kat(K, tau))
         if keep:
             kept.append(ph)
     return (ph, kept) if keep else ph
+
+
+def _comm_update(q, D):
+    """w = min(D ./ q, 1), evaluated as 1 where q <= D and as 0 where D = 0."""
+    w = np.ones_like(q)
+    over = q > D
+    w[over] = D[over] / q[over]
+    w[D == 0] = 0.0
+    return w
 
 
 def sink_update(p: Problem, st: State, ph) -> None:
@@ -224,6 +262,9 @@ def dual_objective(p: Problem, st: State, mass: float) -> float:
     fin = np.isfinite(p.cap)
     if p.T > 1:
         val += (p.cap[fin] * np.log(st.u[fin])).sum()
+    if st.w is not None:
+        m = np.isfinite(p.cap_comm) & (p.cap_comm > 0)
+        val += (p.cap_comm[m] * np.log(st.w[m])).sum()
     return p.eps * val - p.eps * mass
 
 
@@ -255,23 +296,25 @@ def projections(p: Problem, st: State):
             moving i -> j between tau and tau+1:
             K_ij * sum_l A_tau[l, i] B_{tau+1}[l, j], with A_0 = U01,
             A_tau = hatPsi_tau (.) KL (.) u_tau, B_T = U0T,
-            B_tau = Psi_tau (.) KL (.) u_tau.
+            B_tau = Psi_tau (.) KL (.) u_tau (KL times w_tau with
+            commodity capacities).
       cost  transport cost <C, M> = sum_tau <C, flows[tau]> + sum_interior <C_L, P0t>
       mass  (T+1, L) per-commodity mass at every time (all equal)
     """
     K = gibbs(p)
     KL = gibbs_state(p)
-    tmp = State(U01=st.U01.copy(), U0T=st.U0T.copy(), u=st.u.copy(), psi=np.zeros_like(st.psi), g=[])
+    tmp = State(U01=st.U01.copy(), U0T=st.U0T.copy(), u=st.u.copy(), psi=np.zeros_like(st.psi), g=[],
+                w=None if st.w is None else st.w.copy())
     backward_sweep(p, tmp, K, KL)
     ph_T, hats = forward_sweep(p, tmp, K, KL, update=False, keep=True)
     T, L, n = p.T, p.L, p.n
     P0t = np.zeros((T + 1, L, n))
     P0t[0] = tmp.U01 * tmp.psi[0]
     for tau in range(1, T):
-        P0t[tau] = hats[tau] * tmp.psi[tau] * KL * tmp.u[tau - 1][None, :]
+        P0t[tau] = hats[tau] * tmp.psi[tau] * _klw(KL, tmp.w, tau) * tmp.u[tau - 1][None, :]
     P0t[T] = tmp.U0T * ph_T
-    A = [tmp.U01] + [hats[tau] * KL * tmp.u[tau - 1][None, :] for tau in range(1, T)]
-    B = [None] + [tmp.psi[tau] * KL * tmp.u[tau - 1][None, :] for tau in range(1, T)] + [tmp.U0T]
+    A = [tmp.U01] + [hats[tau] * _klw(KL, tmp.w, tau) * tmp.u[tau - 1][None, :] for tau in range(1, T)]
+    B = [None] + [tmp.psi[tau] * _klw(KL, tmp.w, tau) * tmp.u[tau - 1][None, :] for tau in range(1, T)] + [tmp.U0T]
     flows = []
     for tau in range(T):
         Kt = _kat(K, tau)
@@ -359,13 +402,19 @@ class LogState:
     lu: np.ndarray
     lpsi: np.ndarray
     g: list
+    lw: Optional[np.ndarray] = None
 
 
 def initial_log_state(p: Problem) -> LogState:
+    lw = None if p.cap_comm is None else np.zeros((max(p.T - 1, 0), p.L, p.n))
     return LogState(lU01=np.full((p.L, p.n), -np.inf),
                     lU0T=np.where(p.dst > 0, 0.0, -np.inf),
                     lu=np.zeros((max(p.T - 1, 0), p.n)),
-                    lpsi=np.full((p.T, p.L, p.n), -np.inf), g=[])
+                    lpsi=np.full((p.T, p.L, p.n), -np.inf), g=[], lw=lw)
+
+
+def _lklw(lKL, lw, tau):
+    return lKL if lw is None else lKL + lw[tau - 1]
 
 
 def _log_divide_support(R, lmsg, what):
@@ -394,16 +443,27 @@ def iterate_log(p: Problem, st: LogState, n_iter: int) -> LogState:
     kb = _log_kernel_csc(p, transpose=True)
     lKL = np.zeros((p.L, p.n)) if p.state_cost is None else -p.state_cost / p.eps
     lcap = _log_cap(p)
+    with np.errstate(divide="ignore"):
+        lD = None if p.cap_comm is None else np.log(p.cap_comm)
     for _ in range(n_iter):
         st.lpsi[p.T - 1] = lse_matmul(st.lU0T, _kat(kb, p.T - 1))
         for tau in range(p.T - 1, 0, -1):
-            st.lpsi[tau - 1] = lse_matmul(st.lpsi[tau] + lKL + st.lu[tau - 1][None, :], _kat(kb, tau - 1))
+            st.lpsi[tau - 1] = lse_matmul(st.lpsi[tau] + _lklw(lKL, st.lw, tau) + st.lu[tau - 1][None, :],
+                                          _kat(kb, tau - 1))
         st.lU01 = _log_divide_support(p.src, st.lpsi[0], "source")
         lph = lse_matmul(st.lU01, _kat(kf, 0))
         for tau in range(1, p.T):
-            ls = _lse_rows(lph + st.lpsi[tau] + lKL)
+            lq = lph + st.lpsi[tau] + lKL
+            if st.lw is not None:
+                with np.errstate(invalid="ignore"):
+                    lw = np.minimum(lD[tau - 1] - (lq + st.lu[tau - 1][None, :]), 0.0)
+                lw[~np.isfinite(lq)] = 0.0
+                lw[p.cap_comm[tau - 1] == 0] = -np.inf
+                st.lw[tau - 1] = lw
+                lq = lq + lw
+            ls = _lse_rows(lq)
             st.lu[tau - 1] = np.minimum(lcap[tau - 1] - ls, 0.0)
-            lph = lse_matmul(lph + lKL + st.lu[tau - 1][None, :], _kat(kf, tau))
+            lph = lse_matmul(lph + _lklw(lKL, st.lw, tau) + st.lu[tau - 1][None, :], _kat(kf, tau))
         st.lU0T = _log_divide_support(p.dst, lph, "sink")
         mass = float(np.exp(_lse_rows((st.lU0T + lph).reshape(-1, 1))[0]))
         st.g.append(_dual_log(p, st, mass))
@@ -419,6 +479,9 @@ def _dual_log(p, st, mass):
     if p.T > 1:
         fin = np.isfinite(p.cap)
         val += (p.cap[fin] * st.lu[fin]).sum()
+    if st.lw is not None:
+        m = np.isfinite(p.cap_comm) & (p.cap_comm > 0)
+        val += (p.cap_comm[m] * st.lw[m]).sum()
     return p.eps * val - p.eps * mass
 
 
@@ -431,19 +494,19 @@ def projections_log(p: Problem, st: LogState, want_flows: bool = True):
     lpsi = np.full((T, L, n), -np.inf)
     lpsi[T - 1] = lse_matmul(st.lU0T, _kat(kb, T - 1))
     for tau in range(T - 1, 0, -1):
-        lpsi[tau - 1] = lse_matmul(lpsi[tau] + lKL + st.lu[tau - 1][None, :], _kat(kb, tau - 1))
+        lpsi[tau - 1] = lse_matmul(lpsi[tau] + _lklw(lKL, st.lw, tau) + st.lu[tau - 1][None, :], _kat(kb, tau - 1))
     lhats = [None, lse_matmul(st.lU01, _kat(kf, 0))]
     for tau in range(1, T):
-        lhats.append(lse_matmul(lhats[tau] + lKL + st.lu[tau - 1][None, :], _kat(kf, tau)))
+        lhats.append(lse_matmul(lhats[tau] + _lklw(lKL, st.lw, tau) + st.lu[tau - 1][None, :], _kat(kf, tau)))
     P0t = np.zeros((T + 1, L, n))
     P0t[0] = np.exp(st.lU01 + lpsi[0])
     for tau in range(1, T):
-        P0t[tau] = np.exp(lhats[tau] + lpsi[tau] + lKL + st.lu[tau - 1][None, :])
+        P0t[tau] = np.exp(lhats[tau] + lpsi[tau] + _lklw(lKL, st.lw, tau) + st.lu[tau - 1][None, :])
     P0t[T] = np.exp(st.lU0T + lhats[T])
     out = dict(P0t=P0t, Pt=P0t.sum(axis=1), mass=P0t.sum(axis=2), lpsi=lpsi, lpsihat=lhats)
     if want_flows:
-        lA = [st.lU01] + [lhats[tau] + lKL + st.lu[tau - 1][None, :] for tau in range(1, T)]
-        lB = [None] + [lpsi[tau] + lKL + st.lu[tau - 1][None, :] for tau in range(1, T)] + [st.lU0T]
+        lA = [st.lU01] + [lhats[tau] + _lklw(lKL, st.lw, tau) + st.lu[tau - 1][None, :] for tau in range(1, T)]
+        lB = [None] + [lpsi[tau] + _lklw(lKL, st.lw, tau) + st.lu[tau - 1][None, :] for tau in range(1, T)] + [st.lU0T]
         flows = []
         cost = 0.0
         for tau in range(T):

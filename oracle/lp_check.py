@@ -23,10 +23,12 @@ from scipy.optimize import linprog
 __all__ = ["lp_optimum", "walk_counts"]
 
 
-def lp_optimum(C, T, src, dst, cap, state_cost=None):
+def lp_optimum(C, T, src, dst, cap, state_cost=None, cap_comm=None):
     """Optimal value of the unregularised problem; C scipy sparse (allowed moves),
     or a list of T of them with one sparsity pattern (costs of the move tau ->
-    tau+1; +inf closes a move at that step)."""
+    tau+1; +inf closes a move at that step).  cap_comm: optional commodity
+    capacities D (T-1, L, n) or (L, n): commodity l's occupancy of state i at
+    interior time tau is at most D[tau-1, l, i] (+inf = none)."""
     steps = C if isinstance(C, (list, tuple)) else [C] * T
     Cc = sp.coo_matrix(steps[0])
     ei, ej = Cc.row, Cc.col
@@ -81,6 +83,18 @@ def lp_optimum(C, T, src, dst, cap, state_cost=None):
             for l in range(L):
                 R += [r] * len(a); Cl += list(l * T * E + (tau - 1) * E + a); V += [1.0] * len(a)
             b.append(cap[tau - 1, i]); r += 1
+    if cap_comm is not None:
+        D = np.asarray(cap_comm, dtype=np.float64)
+        if D.ndim == 2:
+            D = np.broadcast_to(D, (max(T - 1, 0),) + D.shape)
+        for tau in range(1, T):
+            for l in range(L):
+                for i in range(n):
+                    if not np.isfinite(D[tau - 1, l, i]):
+                        continue
+                    a = into[i]
+                    R += [r] * len(a); Cl += list(l * T * E + (tau - 1) * E + a); V += [1.0] * len(a)
+                    b.append(D[tau - 1, l, i]); r += 1
     Aub = sp.csr_matrix((V, (R, Cl)), shape=(r, nv)) if r else None
     bub = np.array(b) if r else None
     bounds = [(0, 0) if c else (0, None) for c in closed]     # a closed move carries no flow

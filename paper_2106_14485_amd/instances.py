@@ -60,6 +60,9 @@ class Instance:
     charged at interior times (None means zero).  A time-varying network
     (Section 3.3) has cost of shape (T, nnz): row tau prices the moves from
     time tau to tau+1 (same pattern; +inf closes a move at that step).
+    cap_comm: optional commodity-dependent capacities D (the extension at the
+    end of Section 3), (L, n) at every interior time or (T-1, L, n):
+    commodity l occupies state i by at most D (+inf = no such bound).
     """
 
     name: str
@@ -76,6 +79,7 @@ class Instance:
     cost: Optional[np.ndarray] = None
     cost_dense: Optional[np.ndarray] = None
     state_cost: Optional[np.ndarray] = None
+    cap_comm: Optional[np.ndarray] = None
     meta: dict = dataclasses.field(default_factory=dict)
 
     @property
@@ -603,8 +607,12 @@ def staggered_instance(base: Instance, enter: np.ndarray, leave: np.ndarray) -> 
     sc = None
     if base.state_cost is not None:
         sc = np.concatenate([base.state_cost, np.zeros((L, n2 - n))], axis=1)
+    cc = None
+    if base.cap_comm is not None:
+        pad = np.full(base.cap_comm.shape[:-1] + (n2 - n,), np.inf)
+        cc = np.concatenate([base.cap_comm, pad], axis=-1)
     return Instance(name=base.name + "-staggered", n=n2, L=L, T=T, eps=base.eps, kind="csr", src=src, dst=dst,
-                    cap=cap, rowptr=rowptr, colidx=cols.astype(np.int32), cost=cost, state_cost=sc,
+                    cap=cap, rowptr=rowptr, colidx=cols.astype(np.int32), cost=cost, state_cost=sc, cap_comm=cc,
                     meta={**base.meta, "enter": enter, "leave": leave, "n_network": n, "s_of": s_of, "z_of": z_of})
 
 

@@ -8,7 +8,7 @@ from paper_2106_14485_amd.instances import Instance
 
 def to_oracle(inst: Instance) -> alg2.Problem:
     C = inst.cost_csr() if inst.kind == "csr" else inst.cost_dense
-    return alg2.make_problem(C, inst.eps, inst.T, inst.src, inst.dst, inst.cap, inst.state_cost)
+    return alg2.make_problem(C, inst.eps, inst.T, inst.src, inst.dst, inst.cap, inst.state_cost, inst.cap_comm)
 
 
 def random_tiny(n=4, T=4, L=2, seed=0, density=0.6, state_cost=True, cap_scale=0.6,
