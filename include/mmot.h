@@ -84,6 +84,15 @@ typedef struct mmot_problem {
    * to close that move at that step.  CSR only (EUNSUPPORTED for dense).
    * 0: cost holds nnz values used at every step (finite). */
   int32_t cost_per_step;
+  /* Commodity-dependent capacities (the extension at the end of Section 3):
+   * P_{0,t}[l, i] <= D_t[l, i] at the interior times, D >= 0, +INF = no bound,
+   * 0 closes state i to commodity l.  L x n values used at every interior
+   * time (cap_comm_per_step = 0) or (T-1) x L x n (index ((t-1)*L + l)*n + i,
+   * cap_comm_per_step = 1).  NULL = none.  CSR only (EUNSUPPORTED for dense).
+   * Each adds one dual scaling w_t (L x n, in [0, 1]) per interior time; see
+   * mmot_get_comm_duals. */
+  const double* cap_comm;
+  int32_t cap_comm_per_step;
 } mmot_problem;
 
 typedef struct mmot_options {
@@ -98,8 +107,10 @@ typedef struct mmot_options {
 
 /* Convergence / dual statistics of the current iterate (FP64 reductions).
  * dual_obj: dual objective of Theorem 3 at the current scalings,
- *   eps*(<log U01,R01> + <log U0T,R0T> + sum_t <log u_t,d_t>) - eps*<K,U>.
- * src_resid: sum|P_{0,1} - R01| / sum R01; cap_viol: max_t,i (P_t - d)_+ / d;
+ *   eps*(<log U01,R01> + <log U0T,R0T> + sum_t <log u_t,d_t> + sum_t <log w_t,D_t>)
+ *   - eps*<K,U> (the w_t term only with commodity capacities).
+ * src_resid: sum|P_{0,1} - R01| / sum R01; cap_viol: max_t,i (P_t - d)_+ / d,
+ *   and max_t,l,i (P_{0,t} - D_t)_+ / D_t with commodity capacities;
  * mass_drift: max over times of |mass(t) - mass(T)| / mass(T) (Corollary 1
  * makes it zero in exact arithmetic); dual_gap: eps*(<log U,P - R> terms). */
 typedef struct mmot_stats {
@@ -174,6 +185,16 @@ mmot_status mmot_get_log_duals(mmot_solver* s, double* log_src, double* log_dst,
  * its first source update).  Asynchronous. */
 mmot_status mmot_set_log_duals(mmot_solver* s, const double* log_src, const double* log_dst,
                                const double* log_cap);
+
+/* Commodity-capacity duals (problems with cap_comm): natural logs of the
+ * scalings w_t, (T-1) x L x n (index ((t-1)*L + l)*n + i), <= 0, -INF where
+ * D_t = 0.  In the forward sweep, at each interior time, w_t is projected
+ * first (w_t = min(D_t ./ P_{0,t} without w_t, 1) with the current u_t), then
+ * u_t.  EINVAL for a solver without commodity capacities.  get: asynchronous
+ * device output.  set (warm start / resume, same layout, values clamped at 0):
+ * asynchronous; the next iteration recomputes the messages. */
+mmot_status mmot_get_comm_duals(mmot_solver* s, double* log_w);
+mmot_status mmot_set_comm_duals(mmot_solver* s, const double* log_w);
 
 /* Release host-side resources (the workspace stays the caller's). */
 void mmot_destroy(mmot_solver* s);

@@ -25,6 +25,7 @@ class Problem(ctypes.Structure):
         ("cost_dense", ctypes.c_void_p), ("state_cost", ctypes.c_void_p), ("cap", ctypes.c_void_p),
         ("src", ctypes.c_void_p), ("dst", ctypes.c_void_p),
         ("cost_per_step", ctypes.c_int32),
+        ("cap_comm", ctypes.c_void_p), ("cap_comm_per_step", ctypes.c_int32),
     ]
 
 
@@ -70,6 +71,8 @@ _SIGS = {
     "mmot_edge_flows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
     "mmot_get_log_duals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "mmot_set_log_duals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "mmot_get_comm_duals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "mmot_set_comm_duals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "mmot_destroy": (None, [ctypes.c_void_p]),
     "mmot_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "mmot_iterations": (ctypes.c_int64, [ctypes.c_void_p]),

@@ -31,6 +31,8 @@ void launch_log_duals(const V*, const double*, const V*, const double*, const V*
 template <typename V, bool LOG>
 void launch_set_duals(const double*, const double*, const double*, int, int, int, int, V*, V*, V*, double*, double*,
                       hipStream_t);
+template <typename V, bool LOG>
+void launch_comm_duals(const V*, int, int, int, int, double*, int, const double*, V*, hipStream_t);
 void launch_excess(const int*, const int*, const double*, int, double*, int*, double*, hipStream_t);
 void launch_max_degree(const int*, int, int*, hipStream_t);
 template <typename V> void launch_build_ell(const int*, const int*, const V*, int, int, V, int*, V*, int*, hipStream_t);
@@ -111,6 +113,8 @@ struct mmot_solver {
   long long nnz = 0;
   double eps = 0;
   bool has_kl = false;
+  bool has_comm = false;          // commodity-dependent capacities D_t
+  int comm_steps = 1;             // D value sets: T-1 (per step) or 1
   mmot_options opt{};
   int prec = MMOT_FP32;   // FP32 or FP64 (element type V)
   int dom = MMOT_DOMAIN_SCALED;
@@ -125,6 +129,7 @@ struct mmot_solver {
   double* cost = nullptr;
   void *KL = nullptr, *cap = nullptr, *R01 = nullptr, *R0T = nullptr, *U01 = nullptr, *U0T = nullptr;
   void *psi = nullptr, *zh = nullptr, *u = nullptr;
+  void *dcomm = nullptr, *wcomm = nullptr;   // D_t and w_t panels [n][Lp] per interior time
   double *cb = nullptr, *cf = nullptr, *sigb = nullptr, *sigf = nullptr, *gauge0 = nullptr, *gaugeT = nullptr;
   void *facb = nullptr, *facf = nullptr, *wgt = nullptr;
   uint32_t *slots_b = nullptr, *slots_f = nullptr, *slotsE = nullptr, *slotsS = nullptr, *rho = nullptr;
@@ -205,6 +210,8 @@ void carve(mmot_solver* s, Carver& c) {
   s->cursor = c.take<int>(n);
   s->srcpos = c.take<int>(nnz);
   s->KL = s->has_kl ? takev(n * Lp) : nullptr;
+  s->dcomm = s->has_comm ? takev((size_t)s->comm_steps * n * Lp) : nullptr;
+  s->wcomm = s->has_comm ? takev(Tm1 * n * Lp) : nullptr;
   s->cap = takev(Tm1 * n);
   s->R01 = takev(n * Lp);
   s->R0T = takev(n * Lp);
@@ -272,6 +279,8 @@ mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
   if (!(p->eps > 0) || !std::isfinite(p->eps)) return MMOT_EINVAL;
   if (p->kind != MMOT_CSR && p->kind != MMOT_DENSE) return MMOT_EINVAL;
   if (p->cost_per_step != 0 && p->cost_per_step != 1) return MMOT_EINVAL;
+  if (p->cap_comm_per_step != 0 && p->cap_comm_per_step != 1) return MMOT_EINVAL;
+  if (p->cap_comm && p->kind == MMOT_DENSE) return MMOT_EUNSUPPORTED;   // commodity capacities: sparse path
   if (p->kind == MMOT_DENSE) {
     if (p->cost_per_step) return MMOT_EUNSUPPORTED;   // per-step dense costs: not built
     // dense products run on MFMA in the scaled domain, FP32 or BF16 (+ FP32 polish)
@@ -297,11 +306,20 @@ mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
 // ---------------------------------------------------------------------------
 template <typename V, bool LOG>
 struct Impl {
+  using value_type = V;
+  static constexpr bool kLog = LOG;
   static V* pan(mmot_solver* s, void* base, size_t k) { return static_cast<V*>(base) + k * s->panel_elems(); }
   static V* psi(mmot_solver* s, int t) { return pan(s, s->psi, t); }
   static V* zh(mmot_solver* s, int k) { return pan(s, s->zh, k & 1); }
   static V* uat(mmot_solver* s, int tau) {  // u at interior time tau (1..T-1)
     return (tau >= 1 && tau <= s->T - 1) ? static_cast<V*>(s->u) + (size_t)(tau - 1) * s->n : nullptr;
+  }
+  // commodity capacities at interior time tau: scaling w_tau and bound D_tau (panels)
+  static V* wat(mmot_solver* s, int tau) {
+    return (s->has_comm && tau >= 1 && tau <= s->T - 1) ? pan(s, s->wcomm, tau - 1) : nullptr;
+  }
+  static const V* dat(mmot_solver* s, int tau) {
+    return s->has_comm ? pan(s, s->dcomm, s->comm_steps > 1 ? tau - 1 : 0) : nullptr;
   }
   static StepArgs<V> base_args(mmot_solver* s) {
     StepArgs<V> a;
@@ -401,6 +419,7 @@ struct Impl {
     a.fac = static_cast<const V*>(s->facb) + (size_t)t * s->Lp;
     a.out = psi(s, t);
     a.kl = (s->has_kl && t >= 1) ? static_cast<const V*>(s->KL) : nullptr;
+    a.cw = wat(s, t);
     a.epi = 0;
     // log domain: the backward panels are calibrated on their values at the plan
     // peak, recorded by the forward sweep (and the source update for t = 0)
@@ -446,6 +465,9 @@ struct Impl {
       a.epi = 1;
       a.out = zh(s, to);
       a.kl = s->has_kl ? static_cast<const V*>(s->KL) : nullptr;
+      a.cw = wat(s, to);
+      a.cwo = (mode == 0) ? wat(s, to) : nullptr;
+      a.dc = dat(s, to);
       a.wpan = psi(s, to);
       a.wgt = static_cast<const V*>(s->wgt) + (size_t)to * Lp;
       a.cap = static_cast<const V*>(s->cap) + (size_t)(to - 1) * s->n;
@@ -534,7 +556,7 @@ struct Impl {
         launch_gemm(g, s->dense_bf16, s->stream);
       } else {
         StepArgs<V> a = fwd ? fwd_args(s, t, 0, false, nullptr, nullptr) : bwd_args(s, t, false);
-        if (fwd && a.epi == 1) a.uout = reinterpret_cast<V*>(s->exc_row);
+        if (fwd && a.epi == 1) { a.uout = reinterpret_cast<V*>(s->exc_row); a.cwo = nullptr; }
         launch_step<V, LOG>(a, fwd, s->nblk, s->stream);
       }
     };
@@ -581,6 +603,7 @@ struct Impl {
     if (!dense) launch_validate_vals(p->cost, (size_t)s->steps_k * nnz, s->steps_k > 1 ? 1 : 0, 0, 1, s->flags, st);
     else launch_validate_vals(p->cost_dense, n * n, 1, 0, 1, s->flags, st);
     if (p->state_cost) launch_validate_vals(p->state_cost, n * L, 0, 0, 1, s->flags, st);
+    if (p->cap_comm) launch_validate_vals(p->cap_comm, (size_t)s->comm_steps * L * n, 1, 0, 0, s->flags, st);
     if (!dense) launch_validate_csr(p->rowptr, p->colidx, s->n, s->nnz, s->flags, st);
     launch_validate_mass(p->src, p->dst, s->L, s->n, s->flags, s->masses, st);
     HIPCK(hipMemcpyAsync(s->host_flags, s->flags, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -635,6 +658,13 @@ struct Impl {
       launch_to_panel<V>(p->state_cost, s->L, s->n, s->Lp, LOG ? 3 : 2, s->eps, LOG ? V(0) : V(1),
                          static_cast<V*>(s->KL), st);
     launch_cap<V, LOG>(p->cap, p->cap_per_step, s->n, (int)Tm1, static_cast<V*>(s->cap), st);
+    if (s->has_comm) {
+      // D_t as panels (log2 in the log domain; padding columns unconstrained), w_t = 1
+      for (int k = 0; k < s->comm_steps; ++k)
+        launch_to_panel<V>(p->cap_comm + (size_t)k * L * n, s->L, s->n, s->Lp, LOG ? 1 : 0, s->eps,
+                           static_cast<V>(INFINITY), pan(s, s->dcomm, k), st);
+      launch_fill<V>(static_cast<V*>(s->wcomm), Tm1 * n * Lp, LOG ? V(0) : V(1), st);
+    }
     // initial scalings: u = 1, U0T = 1 on supp(R0T)
     launch_fill<V>(static_cast<V*>(s->u), Tm1 * n, LOG ? V(0) : V(1), st);
     launch_init_u0t<V, LOG>(static_cast<const V*>(s->R0T), n * Lp, static_cast<V*>(s->U0T), st);
@@ -785,6 +815,8 @@ mmot_status mmot_query_workspace(const mmot_problem* p, const mmot_options* o, s
   tmp.n = p->n; tmp.L = p->L; tmp.T = p->T; tmp.nnz = p->nnz; tmp.kind = p->kind;
   tmp.steps_k = p->cost_per_step ? p->T : 1;
   tmp.has_kl = p->state_cost != nullptr;
+  tmp.has_comm = p->cap_comm != nullptr && p->T > 1;
+  tmp.comm_steps = p->cap_comm_per_step ? std::max(p->T - 1, 1) : 1;
   tmp.prec = (o->precision == MMOT_FP64) ? MMOT_FP64 : MMOT_FP32;
   tmp.has_bf16 = o->precision == MMOT_BF16;
   set_geometry(&tmp);
@@ -812,6 +844,8 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
   s->n = p->n; s->L = p->L; s->T = p->T; s->nnz = p->nnz; s->kind = p->kind; s->eps = p->eps;
   s->steps_k = p->cost_per_step ? p->T : 1;
   s->has_kl = p->state_cost != nullptr;
+  s->has_comm = p->cap_comm != nullptr && p->T > 1;
+  s->comm_steps = p->cap_comm_per_step ? std::max(p->T - 1, 1) : 1;
   s->opt = *o;
   if (s->opt.check_every < 1) s->opt.check_every = 10;
   if (!(s->opt.tol > 0)) s->opt.tol = 1e-6;
@@ -959,6 +993,31 @@ mmot_status mmot_get_log_duals(mmot_solver* s, double* ls, double* ld, double* l
       launch_log_duals<float, false>(static_cast<float*>(s->U01), s->gauge0, static_cast<float*>(s->U0T), s->gaugeT,
                                      static_cast<float*>(s->u), s->n, s->L, s->Lp, s->T - 1, ls, ld, lc, s->stream);
   }
+  return hipGetLastError() == hipSuccess ? MMOT_OK : MMOT_EHIP;
+}
+
+mmot_status mmot_get_comm_duals(mmot_solver* s, double* log_w) {
+  if (!s || !log_w || !s->has_comm) return MMOT_EINVAL;
+  dispatch(s, [&](auto impl) {
+    using I = decltype(impl);
+    using V = typename I::value_type;
+    launch_comm_duals<V, I::kLog>(static_cast<const V*>(s->wcomm), s->n, s->L, s->Lp, s->T - 1, log_w, 0, nullptr,
+                                  nullptr, s->stream);
+    return 0;
+  });
+  return hipGetLastError() == hipSuccess ? MMOT_OK : MMOT_EHIP;
+}
+
+mmot_status mmot_set_comm_duals(mmot_solver* s, const double* log_w) {
+  if (!s || !log_w || !s->has_comm) return MMOT_EINVAL;
+  dispatch(s, [&](auto impl) {
+    using I = decltype(impl);
+    using V = typename I::value_type;
+    launch_comm_duals<V, I::kLog>(nullptr, s->n, s->L, s->Lp, s->T - 1, nullptr, 1, log_w,
+                                  static_cast<V*>(s->wcomm), s->stream);
+    return 0;
+  });
+  s->psi_fresh = false;
   return hipGetLastError() == hipSuccess ? MMOT_OK : MMOT_EHIP;
 }
 

@@ -147,9 +147,9 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2
   }
 }
 
-// BB (BF16 only): the B operand comes pre-scaled and k-blocked in BF16 (a.Bb),
-// staged by 16-byte copies like A; otherwise FP32 B is scaled by u and converted.
-template <bool BF16, bool BB>
+// Register-staged GEMM (FP32 products, and the first BF16 product of a sweep):
+// FP32 B is scaled by u and converted while it is written to LDS.
+template <bool BF16>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   using TA = typename std::conditional<BF16, __bf16, float>::type;
   constexpr int PAD = BF16 ? kPadB16 : kPadF32;
@@ -187,9 +187,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
   // back and the wave waits once per stage, not once per load.
   uint4 ra[AV];
   uint32_t aok = 0;   // bit v: chunk v of A lies inside the matrix (applied at the LDS write)
-  float4 rb[BB ? 1 : 8];
-  float ru[BB ? 1 : 8];
-  uint4 rbb[BB ? 4 : 1];
+  float4 rb[8];
+  float ru[8];
   uint32_t bok = 0;   // bit e: k row e of the B chunk lies inside the matrix
   // B: thread owns 4 consecutive columns (16-byte loads along the panel row)
   // and 8 consecutive k of the stage
@@ -212,30 +211,16 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
       if (v == 0) aok = 0;
       aok |= (gr < a.n && gk < a.lda) ? (1u << v) : 0u;
     }
-    if constexpr (BB) {
-      // 8 k-blocks x 128 columns of 16 bytes; consecutive lanes take consecutive columns
-      bok = 0;
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = tid + v * 256;
-        const int kb = c >> 7, cl = c & 127;
-        const int gkb = (k0 >> 3) + kb, gc = col0 + cl;
-        const bool ok = gkb < (a.n8 >> 3) && gc < a.Lp;
-        rbb[v] = *reinterpret_cast<const uint4*>(a.Bb + ((size_t)(ok ? gkb : 0) * a.Lp + (ok ? gc : 0)) * 8);
-        bok |= ok ? (1u << v) : 0u;
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int gk = k0 + kg * 8 + e;
-        const int gkc = gk < a.n ? gk : a.n - 1;
-        rb[e] = *reinterpret_cast<const float4*>(a.B + (size_t)gkc * a.Lp + gcb_c);
-        ru[e] = has_u ? a.u[gkc] : 1.f;
-      }
-      bok = 0;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) bok |= (k0 + kg * 8 + e < a.n && bcol_ok) ? (1u << e) : 0u;
+    for (int e = 0; e < 8; ++e) {
+      const int gk = k0 + kg * 8 + e;
+      const int gkc = gk < a.n ? gk : a.n - 1;
+      rb[e] = *reinterpret_cast<const float4*>(a.B + (size_t)gkc * a.Lp + gcb_c);
+      ru[e] = has_u ? a.u[gkc] : 1.f;
     }
+    bok = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) bok |= (k0 + kg * 8 + e < a.n && bcol_ok) ? (1u << e) : 0u;
   };
   auto swrite = [&](int buf) {
     TA* as = As[buf];
@@ -256,34 +241,24 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
             make_float2(__uint_as_float(ra[v].y), __uint_as_float(ra[v].w));
       }
     }
-    if constexpr (BB) {
+    // scale by u (zero outside the matrix) and store column-major: Bs[col][k]
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = tid + v * 256;
-        const int kb = c >> 7, cl = c & 127;
-        const uint4 x = ((bok >> v) & 1u) ? rbb[v] : make_uint4(0, 0, 0, 0);
-        *reinterpret_cast<uint4*>(&bs[cl * LDK + kb * 8]) = x;
+    for (int q = 0; q < 4; ++q) {
+      float x[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const float b = (q == 0) ? rb[e].x : (q == 1) ? rb[e].y : (q == 2) ? rb[e].z : rb[e].w;
+        x[e] = ((bok >> e) & 1u) ? b * ru[e] : 0.f;
       }
-    } else {
-      // scale by u (zero outside the matrix) and store column-major: Bs[col][k]
+      if (BF16) {
+        bf16x8 p;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float x[8];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float b = (q == 0) ? rb[e].x : (q == 1) ? rb[e].y : (q == 2) ? rb[e].z : rb[e].w;
-          x[e] = ((bok >> e) & 1u) ? b * ru[e] : 0.f;
-        }
-        if (BF16) {
-          bf16x8 p;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) p[e] = (__bf16)x[e];
-          *reinterpret_cast<bf16x8*>(&bs[(cq * 4 + q) * LDK + kg * 8]) = p;
-        } else {
-          float* dst = reinterpret_cast<float*>(&bs[(cq * 4 + q) * LDK]);
-          *reinterpret_cast<float4*>(&dst[kg * 4]) = make_float4(x[0], x[2], x[4], x[6]);
-          *reinterpret_cast<float4*>(&dst[32 + kg * 4]) = make_float4(x[1], x[3], x[5], x[7]);
-        }
+        for (int e = 0; e < 8; ++e) p[e] = (__bf16)x[e];
+        *reinterpret_cast<bf16x8*>(&bs[(cq * 4 + q) * LDK + kg * 8]) = p;
+      } else {
+        float* dst = reinterpret_cast<float*>(&bs[(cq * 4 + q) * LDK]);
+        *reinterpret_cast<float4*>(&dst[kg * 4]) = make_float4(x[0], x[2], x[4], x[6]);
+        *reinterpret_cast<float4*>(&dst[32 + kg * 4]) = make_float4(x[1], x[3], x[5], x[7]);
       }
     }
   };
@@ -658,8 +633,8 @@ __global__ void k_dense_rowsum_max(const float* __restrict__ K, int n, int lda, 
 void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
   dim3 grid((a.n + GBM - 1) / GBM, (a.Lp + GBN - 1) / GBN);
   if (bf16 && a.Bb) hipLaunchKernelGGL(k_gemm_lds, grid, dim3(256), 0, s, a);
-  else if (bf16) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, s, a);
+  else if (bf16) hipLaunchKernelGGL((k_gemm<true>), grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((k_gemm<false>), grid, dim3(256), 0, s, a);
 }
 int gemm_col_tiles(int Lp) { return (Lp + GBN - 1) / GBN; }
 void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, float* u, int update, double* part,

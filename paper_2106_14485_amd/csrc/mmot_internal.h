@@ -50,6 +50,13 @@ struct StepArgs {
   const V* fac;         // [Lp] per-column output factor 2^-c (scaled) or -c (log)
   V* out;               // output panel (nullptr = do not store)
   const V* kl;          // [n][Lp] K_L multiplied into the stored output (interior times), nullptr = none
+  // commodity-dependent capacities P_{0,t} <= D_t (interior output times), nullptr = none:
+  // cw = w_t [n][Lp] multiplied into the stored output with K_L; a forward update
+  // projects w_t first (with the current u_t), writes it to cwo (nullptr = do not
+  // store) and multiplies the new value in; dc = D_t [n][Lp] (log2 in the log domain)
+  const V* cw;
+  V* cwo;
+  const V* dc;
   // forward epilogue: capacity update at an interior output time
   int epi;              // 0 plain store, 1 capacity (u-update / check), 2 sink (E update / check)
   int update;           // 1: Sinkhorn update, 0: update-free (check / output pass)

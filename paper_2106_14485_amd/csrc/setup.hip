@@ -241,9 +241,10 @@ __global__ void k_log_duals_panel(const V* __restrict__ pan, const double* __res
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < tot; k += (size_t)gridDim.x * blockDim.x) {
     const int l = (int)(k / n), i = (int)(k % n);
     const V x = pan[(size_t)i * Lp + l];
+    const double sg = sig ? sig[l] : 0.0;
     double r;
-    if (LOG) r = (x == -static_cast<V>(INFINITY)) ? -INFINITY : ((double)x + sig[l]) * M_LN2;
-    else r = (x > V(0)) ? (log2((double)x) + sig[l]) * M_LN2 : -INFINITY;
+    if (LOG) r = (x == -static_cast<V>(INFINITY)) ? -INFINITY : ((double)x + sg) * M_LN2;
+    else r = (x > V(0)) ? (log2((double)x) + sg) * M_LN2 : -INFINITY;
     out[k] = r;
   }
 }
@@ -278,6 +279,17 @@ template <typename V, bool LOG>
 __global__ void k_set_u(const double* __restrict__ in, size_t cnt, V* __restrict__ u) {
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < cnt; k += (size_t)gridDim.x * blockDim.x)
     u[k] = LOG ? static_cast<V>(fmin(in[k], 0.0) * M_LOG2E) : static_cast<V>(exp(fmin(in[k], 0.0)));
+}
+
+// commodity-capacity scalings w_t in (0, 1] from natural logs (clamped at 0)
+template <typename V, bool LOG>
+__global__ void k_set_wpanel(const double* __restrict__ in, int n, int L, int Lp, V* __restrict__ pan) {
+  const size_t tot = (size_t)L * n;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < tot; k += (size_t)gridDim.x * blockDim.x) {
+    const int l = (int)(k / n), i = (int)(k % n);
+    const double x = fmin(in[k], 0.0);
+    pan[(size_t)i * Lp + l] = LOG ? static_cast<V>(x * M_LOG2E) : static_cast<V>(exp(x));
+  }
 }
 
 // range estimate for the domain choice: per row, sum over off-diagonal moves
@@ -387,6 +399,19 @@ void launch_set_duals(const double* ls, const double* ld, const double* lc, int 
   if (lc && Tm1 > 0)
     hipLaunchKernelGGL((k_set_u<V, LOG>), dim3(gs((size_t)Tm1 * n)), dim3(256), 0, s, lc, (size_t)Tm1 * n, u);
 }
+template <typename V, bool LOG>
+void launch_comm_duals(const V* w, int n, int L, int Lp, int Tm1, double* out, int set, const double* in,
+                       V* wout, hipStream_t s) {
+  const size_t tot = (size_t)L * n;
+  for (int t = 0; t < Tm1; ++t) {
+    if (set)
+      hipLaunchKernelGGL((k_set_wpanel<V, LOG>), dim3(gs(tot)), dim3(256), 0, s, in + (size_t)t * tot, n, L, Lp,
+                         wout + (size_t)t * n * Lp);
+    else
+      hipLaunchKernelGGL((k_log_duals_panel<V, LOG>), dim3(gs(tot)), dim3(256), 0, s, w + (size_t)t * n * Lp,
+                         nullptr, n, L, Lp, out + (size_t)t * tot);
+  }
+}
 void launch_excess(const int* rp, const int* ci, const double* cost, int n, double* rowsum, int* rowcnt, double* out,
                    hipStream_t s) {
   hipLaunchKernelGGL(k_excess_rows, dim3((n + 255) / 256), dim3(256), 0, s, rp, ci, cost, n, rowsum, rowcnt);
@@ -401,7 +426,9 @@ void launch_excess(const int* rp, const int* ci, const double* cost, int n, doub
   template void launch_log_duals<V, LOG>(const V*, const double*, const V*, const double*, const V*, int, int,   \
                                          int, int, double*, double*, double*, hipStream_t);                      \
   template void launch_set_duals<V, LOG>(const double*, const double*, const double*, int, int, int, int, V*,    \
-                                         V*, V*, double*, double*, hipStream_t);
+                                         V*, V*, double*, double*, hipStream_t);                                 \
+  template void launch_comm_duals<V, LOG>(const V*, int, int, int, int, double*, int, const double*, V*,         \
+                                          hipStream_t);
 MMOT_SETUP_INST(float, false)
 MMOT_SETUP_INST(float, true)
 MMOT_SETUP_INST(double, false)

@@ -207,6 +207,10 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   V lm = ninf<V>(), ls = 0;         // log: running LSE of the column sum
   double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
   double occ_row = 0.0;             // sink / output: occupancy of this row
+  // commodity capacities: w_t, projected before u_t with the u_t of the last sweep
+  const bool comm = a.cw != nullptr;
+  V ucur = LOG ? V(0) : V(1);
+  if (FWD && a.epi == 1 && (CHK || comm)) ucur = a.uout[rowc];
 
   for (int ch = 0; ch < a.nchunk; ++ch) {
     const int col = (ch * G + gl) * NV;
@@ -221,6 +225,11 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     if (FWD && a.epi == 1) {
       vld(a.wpan + rowc * Lp + colc, w);
       vld(a.wgt + colc, g);
+    }
+    V cwv[NV], dcv[NV];
+    if (comm) {
+      vld(a.cw + rowc * Lp + colc, cwv);
+      if (FWD && a.epi == 1) vld(a.dc + rowc * Lp + colc, dcv);
     }
     vld(a.fac + colc, f);
     // ---------------- product ----------------
@@ -395,8 +404,35 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
         for (int v = 0; v < NV; ++v) z[v] = LOG ? ninf<V>() : V(0);
       }
     } else {
+      V cwn[NV];   // w_t multiplied into the stored output (the new one after an update)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) cwn[v] = comm ? cwv[v] : (LOG ? V(0) : V(1));
       if (capepi) {
-        if (!LOG) {
+        if (comm && !CHK && a.update) {
+          // w_t = min(D_t ./ (P_{0,t} without w_t, times u_t), 1), 0 where D_t = 0; in the
+          // multiplicative form w_old D / (P_{0,t} u_t), P_{0,t} taken with w_old (which is
+          // folded into the stored backward panel), then P_{0,t} re-weighted to the new w_t
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            if (!LOG) {
+              const V q = o[v] * w[v] * g[v];
+              const V qu = q * ucur, lim = cwv[v] * dcv[v];
+              const V wn = (dcv[v] == V(0)) ? V(0) : ((qu <= lim) ? V(1) : lim / qu);
+              ssum += (cwv[v] > V(0)) ? q * (wn / cwv[v]) : V(0);
+              cwn[v] = wn;
+            } else {
+              const V q = o[v] + w[v] + g[v];
+              const V wn = (dcv[v] == ninf<V>()) ? ninf<V>()
+                           : ((q == ninf<V>()) ? V(0) : fmin(V(0), cwv[v] + dcv[v] - q - ucur));
+              const V y = (cwv[v] == ninf<V>() || wn == ninf<V>()) ? ninf<V>() : q - cwv[v] + wn;
+              const V nm = fmax(lm, y);
+              const V b = (nm == ninf<V>()) ? V(0) : nm;
+              ls = ls * xexp2(lm - b) + xexp2(y - b);
+              lm = nm;
+              cwn[v] = wn;
+            }
+          }
+        } else if (!LOG) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) ssum = fma(o[v] * w[v], g[v], ssum);
         } else {
@@ -409,10 +445,11 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             lm = nm;
           }
         }
-        if (CHK && (a.pcomm || a.kl)) {
-          // update-free pass: u is final, P_{0,t} = hatPsi (.) Psi (.) K_L u_t (eq. proj_0t);
-          // with state costs also accumulate <C_L, P_{0,t}> (cost tensor, eq. cost_multicommodity)
-          const V ur = a.uout[row];
+        if (CHK && (a.pcomm || a.kl || comm)) {
+          // update-free pass: u is final, P_{0,t} = hatPsi (.) Psi (.) K_L w_t u_t (eq. proj_0t);
+          // with state costs also accumulate <C_L, P_{0,t}> (cost tensor, eq. cost_multicommodity);
+          // with commodity capacities their violation, dual term and gap term
+          const V ur = ucur;
           V k[NV];
           if (a.kl) vld(a.kl + row * Lp + col, k);
 #pragma unroll
@@ -427,6 +464,15 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
               const double cl = LOG ? -(double)k[v] * a.eps * M_LN2 : -a.eps * log((double)k[v]);
               st[ST_SCOST] += P * cl;
             }
+            if (comm) {
+              const double D = LOG ? exp2((double)dcv[v]) : (double)dcv[v];
+              if (isfinite(D) && D > 0.0) {
+                const double lnw = LOG ? (double)cwv[v] * M_LN2 : log((double)cwv[v]);
+                st[ST_CAP_VIOL] = fmax(st[ST_CAP_VIOL], fmax(P - D, 0.0) / D);
+                st[ST_DUAL] += D * lnw;
+                st[ST_GAP] += lnw * (P - D);
+              }
+            }
           }
         }
       }
@@ -438,6 +484,11 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) z[v] = o[v];
+      }
+      if (comm) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) z[v] = LOG ? z[v] + cwn[v] : z[v] * cwn[v];
+        if (FWD && !CHK && a.update && capepi && a.cwo) vst(a.cwo + row * Lp + col, cwn);
       }
       if (cv && a.out) vst(a.out + row * Lp + col, z);
       if (!cv) {

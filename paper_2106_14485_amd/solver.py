@@ -65,6 +65,12 @@ def device_problem(inst, device="cuda"):
     sc = dt(inst.state_cost, torch.float64)
     keep += [cap, src, dst, sc]
     p.cap, p.src, p.dst, p.state_cost = _ptr(cap), _ptr(src), _ptr(dst), _ptr(sc)
+    cc = getattr(inst, "cap_comm", None)
+    if cc is not None:
+        ccd = dt(cc, torch.float64)
+        keep.append(ccd)
+        p.cap_comm = _ptr(ccd)
+        p.cap_comm_per_step = 1 if np.ndim(cc) == 3 else 0     # (T-1, L, n) or (L, n)
     return p, keep
 
 
@@ -135,6 +141,17 @@ class Solver:
         ld = ld.to(self.device, torch.float64).contiguous()
         lc = lc.to(self.device, torch.float64).contiguous()
         check(_lib.lib().mmot_set_log_duals(self._h, _ptr(ls), _ptr(ld), _ptr(lc)), "mmot_set_log_duals")
+        self.stream.synchronize()
+
+    def comm_duals(self):
+        """log w_t of the commodity capacities, (T-1, L, n)."""
+        lw = torch.empty((max(self.T - 1, 1), self.L, self.n), dtype=torch.float64, device=self.device)
+        check(_lib.lib().mmot_get_comm_duals(self._h, _ptr(lw)), "mmot_get_comm_duals")
+        return lw[: self.T - 1]
+
+    def set_comm_duals(self, lw):
+        lw = lw.to(self.device, torch.float64).contiguous()
+        check(_lib.lib().mmot_set_comm_duals(self._h, _ptr(lw)), "mmot_set_comm_duals")
         self.stream.synchronize()
 
     def set_precision(self, precision: str):

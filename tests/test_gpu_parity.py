@@ -395,3 +395,128 @@ def test_time_varying_road_grid_log_domain():
     compare(g, o, max(1e-5, o["floor"]))
     g64 = gpu_outputs(inst, 15, "fp64", "log")
     compare(g64, o, 1e-12, duals_tol=1e-8)
+
+
+# ---------------------------------------------------------------------------
+# staggered entry and exit times (commodities present over their own windows)
+# ---------------------------------------------------------------------------
+
+def test_staggered_windows_rgg():
+    from oracle import lp_check
+    base = instances.time_varying_instance(
+        instances.rgg_instance(n=300, L=20, T=16, seed=5, cap_lo=0.5, cap_hi=1.5), seed=6, closed_frac=0.03)
+    rng = np.random.default_rng(7)
+    hop = instances._hop_dist(base.rowptr, base.colidx, base.n, base.src.argmax(axis=1))
+    hop = hop[np.arange(base.L), base.dst.argmax(axis=1)].astype(np.int64)
+    enter = rng.integers(0, 5, base.L)
+    leave = np.minimum(base.T, np.maximum(enter + hop + 2, rng.integers(base.T - 4, base.T + 1, base.L)))
+    enter = np.minimum(enter, leave - hop - 1).clip(0)
+    inst = instances.staggered_instance(base, enter, leave)
+    walks = lp_check.walk_counts(inst.cost_csr(), inst.T, inst.src.argmax(axis=1), inst.dst.argmax(axis=1))
+    assert min(walks) > 0
+    o = oracle_outputs(inst, 12)
+    g = gpu_outputs(inst, 12, "fp32", "scaled")
+    compare(g, o, 1e-5)
+    g64 = gpu_outputs(inst, 12, "fp64", "scaled")
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+    # outside its window a commodity is on no network state
+    occ = g64["P0t"][:, :, :base.n].sum(axis=2)
+    for l in range(base.L):
+        out = [t for t in range(inst.T + 1) if not enter[l] <= t <= leave[l]]
+        assert np.all(occ[out, l] <= 1e-12 * inst.src[l].sum())
+
+
+# ---------------------------------------------------------------------------
+# commodity-dependent capacities P_{0,t} <= D_t
+# ---------------------------------------------------------------------------
+
+def _with_comm_caps(inst, seed, frac=0.3, ratio=0.6, zero_frac=0.01, per_step=True, log=False):
+    """Bounds that bind: on a seeded fraction of the (time, commodity, state)
+    entries that carry between 5% and 50% of the commodity in the plan after
+    20 oracle iterations without them (so the commodity has somewhere else to
+    go), D = ratio times that mass; and a few zero bounds that close a lightly
+    used state to one commodity (never its own source or sink).  per_step=False
+    keeps the bounds drawn for the middle time, as one (L, n) bound for all times."""
+    import dataclasses
+    rng = np.random.default_rng(seed)
+    p = to_oracle(inst)
+    if log:
+        free = alg2.projections_log(p, alg2.iterate_log(p, alg2.initial_log_state(p), 20), want_flows=False)["P0t"]
+    else:
+        free = alg2.projections(p, alg2.iterate(p, alg2.initial_state(p), 20))["P0t"]
+    free = free[1:-1]
+    m = inst.src.sum(axis=1)[None, :, None]
+    mid = (free > 0.05 * m) & (free < 0.5 * m)
+    D = np.full(free.shape, np.inf)
+    pick = mid & (rng.random(free.shape) < frac)
+    D[pick] = ratio * free[pick]
+    ends = (inst.src > 0) | (inst.dst > 0)
+    z = (rng.random(free.shape) < zero_frac) & ~ends[None] & ~(free > 0.05 * m)
+    D[z] = 0.0
+    if not per_step:
+        D = D[(inst.T - 1) // 2]
+    return dataclasses.replace(inst, cap_comm=D)
+
+
+def _comm_duals_gpu(inst, n_iter, precision, domain):
+    S = _solver()(inst, precision=precision, domain=domain)
+    S.iterate(n_iter)
+    lw = S.comm_duals().cpu().numpy()
+    S.close()
+    return lw
+
+
+@pytest.mark.parametrize("per_step", [True, False])
+def test_comm_caps_rgg_scaled(per_step):
+    base = instances.rgg_instance(n=400, L=24, T=12, seed=31, cap_lo=0.5, cap_hi=1.5)
+    inst = _with_comm_caps(base, 8, per_step=per_step)
+    p = to_oracle(inst)
+    st = alg2.iterate(p, alg2.initial_state(p), 15)
+    assert np.sum((st.w < 1.0) & (st.w > 0.0)) > 50 and np.any(st.w == 0.0)
+    o = oracle_outputs(inst, 15)
+    g = gpu_outputs(inst, 15, "fp32", "scaled")
+    compare(g, o, 1e-5)
+    g64 = gpu_outputs(inst, 15, "fp64", "scaled")
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+    with np.errstate(divide="ignore"):
+        lw_o = np.log(st.w)
+    lw = _comm_duals_gpu(inst, 15, "fp64", "scaled")
+    assert np.array_equal(np.isfinite(lw), np.isfinite(lw_o))
+    fin = np.isfinite(lw_o)
+    assert np.abs(lw[fin] - lw_o[fin]).max() <= 1e-8
+
+
+def test_comm_caps_road_grid_log_domain():
+    base = instances.road_grid_instance(side=10, L=20, T=24, eps=0.1, seed=3)
+    inst = _with_comm_caps(base, 9, log=True)
+    o = oracle_outputs(inst, 15, log=True)
+    g = gpu_outputs(inst, 15, "fp32", "auto")
+    assert g["stats"]["domain"] == 2
+    compare(g, o, max(1e-5, o["floor"]))
+    g64 = gpu_outputs(inst, 15, "fp64", "log")
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+
+
+def test_comm_caps_converge_with_slackness():
+    base = instances.rgg_instance(n=300, L=16, T=10, seed=32, cap_lo=0.8, cap_hi=2.0, eps=0.1)
+    inst = _with_comm_caps(base, 10, ratio=0.7, zero_frac=0.0)
+    S = _solver()(inst, precision="fp64", domain="scaled", tol=1e-10)
+    st = S.solve(1000)
+    assert st["converged"] == 1, st
+    occ, pc = S.occupancy(per_commodity=True)
+    P = pc.cpu().numpy()[1:-1]
+    lw = S.comm_duals().cpu().numpy()
+    D = inst.cap_comm
+    fin = np.isfinite(D)
+    assert np.all(P[fin] <= D[fin] * (1 + 1e-6) + 1e-12)
+    active = lw < -1e-6
+    assert active.any()
+    assert np.allclose(P[active], D[active], rtol=1e-5)
+    # the dual objective of the oracle at the GPU's scalings equals the GPU's
+    ls, ld, lc = (d.cpu().numpy() for d in S.log_duals())
+    p = to_oracle(inst)
+    ost = alg2.initial_state(p)
+    ost.U01, ost.U0T, ost.u, ost.w = np.exp(ls), np.exp(ld), np.exp(lc), np.exp(lw)
+    mass = alg2.projections(p, ost)["mass"][-1].sum()
+    assert abs(alg2.dual_objective(p, ost, mass) - st["dual_obj"]) <= 1e-8 * abs(st["dual_obj"])
+    S.close()
