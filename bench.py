@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "4334a6c07c829487143da52e784febbe8c1e2315890d14e35f46b273a162e88e",
-                "fetch_kib": 2428.403, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "1d06b68ce15a90fe11e4f5a266d0712b3067c8bcc79e8dd713acc86a0e30e73d",
+                "fetch_kib": 2438.448, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 

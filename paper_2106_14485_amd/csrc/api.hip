@@ -130,6 +130,7 @@ struct mmot_solver {
   void *KL = nullptr, *cap = nullptr, *R01 = nullptr, *R0T = nullptr, *U01 = nullptr, *U0T = nullptr;
   void *psi = nullptr, *zh = nullptr, *u = nullptr;
   void *dcomm = nullptr, *wcomm = nullptr;   // D_t and w_t panels [n][Lp] per interior time
+  void* ones = nullptr;                      // [n] u of an input time without capacity (1, log: 0)
   double *cb = nullptr, *cf = nullptr, *sigb = nullptr, *sigf = nullptr, *gauge0 = nullptr, *gaugeT = nullptr;
   void *facb = nullptr, *facf = nullptr, *wgt = nullptr;
   uint32_t *slots_b = nullptr, *slots_f = nullptr, *slotsE = nullptr, *slotsS = nullptr, *rho = nullptr;
@@ -220,6 +221,7 @@ void carve(mmot_solver* s, Carver& c) {
   s->psi = takev(T * n * Lp);
   s->zh = takev(2 * n * Lp);
   s->u = takev(Tm1 * n);
+  s->ones = takev(n);
   s->cb = c.take<double>((T + 1) * Lp);
   s->cf = c.take<double>((T + 1) * Lp);
   s->sigb = c.take<double>((T + 1) * Lp);
@@ -313,6 +315,11 @@ struct Impl {
   static V* zh(mmot_solver* s, int k) { return pan(s, s->zh, k & 1); }
   static V* uat(mmot_solver* s, int tau) {  // u at interior time tau (1..T-1)
     return (tau >= 1 && tau <= s->T - 1) ? static_cast<V*>(s->u) + (size_t)(tau - 1) * s->n : nullptr;
+  }
+  // u as a sparse step reads it: the vector of ones at the end times
+  static const V* uin_at(mmot_solver* s, int tau) {
+    V* p = uat(s, tau);
+    return p ? p : static_cast<const V*>(s->ones);
   }
   // commodity capacities at interior time tau: scaling w_tau and bound D_tau (panels)
   static V* wat(mmot_solver* s, int tau) {
@@ -415,7 +422,7 @@ struct Impl {
     a.rp = s->rp_b; a.ci = s->ci_b; a.kv = kvat(s, s->kv_b, t);
     if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_b; a.kv = static_cast<const V*>(s->ell_kv_b); a.deg = s->deg_b; }
     a.xin = (t + 1 == T) ? static_cast<const V*>(s->U0T) : psi(s, t + 1);
-    a.uin = uat(s, t + 1);
+    a.uin = uin_at(s, t + 1);
     a.fac = static_cast<const V*>(s->facb) + (size_t)t * s->Lp;
     a.out = psi(s, t);
     a.kl = (s->has_kl && t >= 1) ? static_cast<const V*>(s->KL) : nullptr;
@@ -452,7 +459,7 @@ struct Impl {
     a.rp = s->rp_f; a.ci = s->ci_f; a.kv = kvat(s, s->kv_f, t);
     if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_f; a.kv = static_cast<const V*>(s->ell_kv_f); a.deg = s->deg_f; }
     a.xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
-    a.uin = uat(s, t);
+    a.uin = uin_at(s, t);
     const int to = t + 1;
     a.fac = static_cast<const V*>(s->facf) + (size_t)to * Lp;
     a.update = (mode == 0);
@@ -635,7 +642,8 @@ struct Impl {
         const int D = std::max(s->host_flags[0], s->host_flags[1]);
         // rows of at most 8 entries (grids) gather in batches of 8, wider ones in 16s
         const int Dp = D <= 8 ? 8 : (D + 15) / 16 * 16;
-        s->ellD = (D >= 1 && Dp <= kEllMax && s->steps_k == 1) ? Dp : 0;   // time-varying: CSR
+        // time-varying networks and commodity capacities run on the CSR operators
+        s->ellD = (D >= 1 && Dp <= kEllMax && s->steps_k == 1 && !s->has_comm) ? Dp : 0;
       }
       if (s->ellD) {
         const V pad = LOG ? -static_cast<V>(INFINITY) : V(0);
@@ -667,6 +675,7 @@ struct Impl {
     }
     // initial scalings: u = 1, U0T = 1 on supp(R0T)
     launch_fill<V>(static_cast<V*>(s->u), Tm1 * n, LOG ? V(0) : V(1), st);
+    launch_fill<V>(static_cast<V*>(s->ones), n, LOG ? V(0) : V(1), st);
     launch_init_u0t<V, LOG>(static_cast<const V*>(s->R0T), n * Lp, static_cast<V*>(s->U0T), st);
     launch_fill<V>(static_cast<V*>(s->U01), n * Lp, zero, st);
     launch_fill<V>(static_cast<V*>(s->psi), T * n * Lp, zero, st);

@@ -428,24 +428,29 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
     if (kt + kStages - 1 < nk) issue((kt + kStages - 1) % kStages, (kt + kStages - 1) * GBK);
     const uint4* as = lds[kt % kStages][0];
     const uint4* bs = lds[kt % kStages][1];
+    // operand fragments in two register sets: the reads of k-step ks+1 are in
+    // flight while the MFMAs of k-step ks run
+    bf16x8 af[2][2], bf[2][2];
+    auto frag = [&](int ks, int set) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        af[set][i] = __builtin_bit_cast(bf16x8, as[swz_slot(wm * 64 + i * 32 + lr, ks * 2 + lh)]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        bf[set][j] = __builtin_bit_cast(bf16x8, bs[swz_slot(wn * 64 + j * 32 + lr, ks * 2 + lh)]);
+    };
+    frag(0, 0);
 #pragma unroll
     for (int ks = 0; ks < GBK / 16; ++ks) {
-      bf16x8 af[2], bf[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const uint4 v = as[swz_slot(wm * 64 + i * 32 + lr, ks * 2 + lh)];
-        af[i] = __builtin_bit_cast(bf16x8, v);
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const uint4 v = bs[swz_slot(wn * 64 + j * 32 + lr, ks * 2 + lh)];
-        bf[j] = __builtin_bit_cast(bf16x8, v);
-      }
+      if (ks + 1 < GBK / 16) frag(ks + 1, (ks + 1) & 1);
+      // keep the reads above the MFMAs (the scheduler would otherwise sink them
+      // below and reuse one register set, exposing the LDS latency every k-step)
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks & 1][i], bf[ks & 1][j], acc[i][j], 0, 0, 0);
     }
   }
   __syncthreads();

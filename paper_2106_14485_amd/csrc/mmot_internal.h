@@ -46,7 +46,7 @@ struct StepArgs {
   int ellD;             // > 0: ELL layout with this (padded) row width, deg[] = true row lengths
   const int* deg;
   const V* xin;         // input panel (already multiplied by K_L at its time)
-  const V* uin;         // u at the input time, nullptr = 1
+  const V* uin;         // [n] u at the input time (a vector of ones -- zeros in the log domain -- where none)
   const V* fac;         // [Lp] per-column output factor 2^-c (scaled) or -c (log)
   V* out;               // output panel (nullptr = do not store)
   const V* kl;          // [n][Lp] K_L multiplied into the stored output (interior times), nullptr = none

@@ -14,6 +14,8 @@
 // the commodity reduction is a shuffle reduction inside the group.  Four
 // wavefronts per block, blocks ordered XCD-contiguously.
 #include "mmot_internal.h"
+
+#include <type_traits>
 #include <math.h>
 
 namespace mmot {
@@ -168,8 +170,9 @@ __device__ void corr_chunk(const V (&pl)[VT<V>::N], const V (&val)[VT<V>::N], in
 // ---------------------------------------------------------------------------
 // the sweep step
 // ---------------------------------------------------------------------------
-// KB: neighbours gathered per batch (ELL rows are padded to a multiple of it)
-template <typename V, bool LOG, bool FWD, bool CHK, bool ELL, int KB>
+// KB: neighbours gathered per batch (ELL rows are padded to a multiple of it);
+// CM: commodity capacities at the output time (a.cw set; CSR operators only)
+template <typename V, bool LOG, bool FWD, bool CHK, bool ELL, int KB, bool CM>
 __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nblk) {
 
   constexpr int NV = VT<V>::N;
@@ -198,7 +201,9 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   auto ell_len = [&]() -> int {
     const int* dp = a.deg + rowc;
     asm volatile("" : "+v"(dp));
-    return *dp;
+    // (a global load again: through the asm the pointer lost its address space,
+    // and a flat load would make every later wait a full one)
+    return *(const __attribute__((address_space(1))) int*)dp;
   };
   auto row_end = [&]() -> int { return !valid ? e0 : endv; };
   const size_t Lp = (size_t)a.Lp;
@@ -208,7 +213,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
   double occ_row = 0.0;             // sink / output: occupancy of this row
   // commodity capacities: w_t, projected before u_t with the u_t of the last sweep
-  const bool comm = a.cw != nullptr;
+  constexpr bool comm = CM;
   V ucur = LOG ? V(0) : V(1);
   if (FWD && a.epi == 1 && (CHK || comm)) ucur = a.uout[rowc];
 
@@ -216,65 +221,80 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     const int col = (ch * G + gl) * NV;
     const bool cv = valid && col < a.Lp;
     V o[NV];
-    // operands of the epilogue that do not depend on the product: issue first
-    // (unconditional loads at clamped addresses: a wave waits for them only
-    // where they are used)
+    // operands of the epilogue that do not depend on the product (unconditional
+    // loads at clamped addresses).  The backward panel row W is read from HBM:
+    // it is requested after the first batch's gathers, so that it is in flight
+    // with them while the waits for the (cached) operator entries and for the
+    // gathered rows, which count loads in issue order, do not include it
     V w[NV], g[NV], f[NV];
     const bool capepi = FWD && a.epi == 1 && cv;
     const int colc = cv ? col : 0;
-    if (FWD && a.epi == 1) {
-      vld(a.wpan + rowc * Lp + colc, w);
-      vld(a.wgt + colc, g);
-    }
-    V cwv[NV], dcv[NV];
-    if (comm) {
-      vld(a.cw + rowc * Lp + colc, cwv);
-      if (FWD && a.epi == 1) vld(a.dc + rowc * Lp + colc, dcv);
-    }
+    // (branch-free: the sink step, which has no W, re-reads the factor row instead)
+    auto epi_loads = [&]() {
+      if (FWD) {
+        vld(a.epi == 1 ? a.wpan + rowc * Lp + colc : a.fac + colc, w);
+        vld(a.epi == 1 ? a.wgt + colc : a.fac + colc, g);
+      }
+    };
     vld(a.fac + colc, f);
     // ---------------- product ----------------
     // neighbours in batches of KB: all indices, then all u values and rows are
-    // requested before any of them is used, so one batch costs ~one latency
+    // requested before any of them is used, so one batch costs two memory
+    // latencies (entries, then rows and u).  All loads of a batch are
+    // unconditional, so the wave keeps them all in flight: entries past the row
+    // end re-read the batch's first entry (CSR) or the padding (ELL rows are
+    // padded to a multiple of KB with the own index and a zero coefficient), and
+    // their coefficient is masked.  u at the input time is always given (a
+    // vector of ones, or zeros in the log domain, where the input has none).
+    struct Batch {
+      int idx[KB];
+      V cf[KB], uu[KB];
+      V x[KB][NV];
+      int cnt, len;
+    };
+    auto load_batch = [&](Batch& b, int e, auto first) {
+      b.cnt = ell ? KB : min(KB, row_end() - e);
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const int ek = (ell || k < b.cnt) ? e + k : e;
+        b.idx[k] = a.ci[ek];
+        b.cf[k] = a.kv[ek];
+      }
+      b.len = ELL ? ell_len() : 0;
+#pragma unroll
+      for (int k = 0; k < KB; ++k) b.uu[k] = a.uin[b.idx[k]];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) vld(a.xin + b.idx[k] * Lp + col, b.x[k]);
+      if constexpr (decltype(first)::value) epi_loads();
+    };
+    auto more = [&](const Batch& b, int e) { return e + KB < (ELL ? e0 + b.len : row_end()); };
+    const bool nonempty = cv && (ell || row_end() > e0);
     if (!LOG) {
       V acc[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) acc[v] = 0;
-      if (cv && (ell || row_end() > e0)) {
-        for (int e = e0;; e += KB) {
-          const int cnt = ell ? KB : min(KB, row_end() - e);
-          // All loads of a batch are unconditional, so the wave keeps them all in
-          // flight and a batch costs two memory latencies (entries, then rows and
-          // u).  Entries past the row end re-read the batch's first entry (CSR)
-          // or the padding (ELL rows are padded to a multiple of KB with the own
-          // index and a zero coefficient); their coefficient is masked to zero.
-          int idx[KB];
-          V cf[KB], uu[KB];
-          V x[KB][NV];
+      auto fold = [&](const Batch& b) {
 #pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            const int ek = (ell || k < cnt) ? e + k : e;
-            idx[k] = a.ci[ek];
-            cf[k] = a.kv[ek];
-          }
-          const int len = ELL ? ell_len() : 0;
+        for (int k = 0; k < KB; ++k) {
+          const V c = ((ell || k < b.cnt) ? b.cf[k] : V(0)) * b.uu[k];
 #pragma unroll
-          for (int k = 0; k < KB; ++k) vld(a.xin + idx[k] * Lp + col, x[k]);
-          if (a.uin) {
-#pragma unroll
-            for (int k = 0; k < KB; ++k) uu[k] = a.uin[idx[k]];
-          }
-#pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            const V ck = (ell || k < cnt) ? cf[k] : V(0);
-            const V c = a.uin ? ck * uu[k] : ck;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) acc[v] = fma(c, x[k][v], acc[v]);
-          }
-          if (e + KB >= (ELL ? e0 + len : row_end())) break;
+          for (int v = 0; v < NV; ++v) acc[v] = fma(c, b.x[k][v], acc[v]);
+        }
+      };
+      if (nonempty) {
+        Batch b;
+        int e = e0;
+        load_batch(b, e, std::true_type{});
+        fold(b);
+        while (more(b, e)) {
+          e += KB;
+          load_batch(b, e, std::false_type{});
+          fold(b);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = acc[v] * f[v];
       } else {
+        epi_loads();
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = 0;
       }
@@ -282,65 +302,60 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       V m[NV], sm[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) { m[v] = ninf<V>(); sm[v] = 0; }
-      if (cv && (ell || row_end() > e0)) {
-        int batch = 0;
-        for (int e = e0;; e += KB) {
-          const int cnt = ell ? KB : min(KB, row_end() - e);
-          // batch loads as in the linear domain (masked coefficient: -inf)
-          int idx[KB];
-          V cf[KB], uu[KB];
-          V x[KB][NV];
+      int batch = 0;
+      auto fold = [&](Batch& b) {
 #pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            const int ek = (ell || k < cnt) ? e + k : e;
-            idx[k] = a.ci[ek];
-            cf[k] = a.kv[ek];
-          }
-          const int len = ELL ? ell_len() : 0;
+        for (int k = 0; k < KB; ++k) b.cf[k] = ((ell || k < b.cnt) ? b.cf[k] : ninf<V>()) + b.uu[k];
+        // terms that are exactly zero are not evaluated: the ELL padding of a row
+        // that the whole wave works on (exp2(-inf)), and the rescaled running sum
+        // in a row's first batch (it is empty)
+        int live = KB;
+        if (ELL && G == 64) live = __builtin_amdgcn_readfirstlane(min(KB, b.len - batch * KB));
 #pragma unroll
-          for (int k = 0; k < KB; ++k) vld(a.xin + idx[k] * Lp + col, x[k]);
-          if (a.uin) {
+        for (int v = 0; v < NV; ++v) {
+          V y[KB];
+          V bm = ninf<V>();
 #pragma unroll
-            for (int k = 0; k < KB; ++k) uu[k] = a.uin[idx[k]];
-          }
+          for (int k = 0; k < KB; ++k) { y[k] = b.cf[k] + b.x[k][v]; bm = fmax(bm, y[k]); }
+          const V nm = fmax(m[v], bm);
+          const V bb = (nm == ninf<V>()) ? V(0) : nm;
+          V acc = V(0);
+          if (batch > 0) acc = sm[v] * xexp2(m[v] - bb);
 #pragma unroll
-          for (int k = 0; k < KB; ++k) {
-            cf[k] = (ell || k < cnt) ? cf[k] : ninf<V>();
-            if (a.uin) cf[k] += uu[k];
-          }
-          // terms that are exactly zero are not evaluated: the ELL padding of a row
-          // that the whole wave works on (exp2(-inf)), and the rescaled running sum
-          // in a row's first batch (it is empty)
-          int live = KB;
-          if (ELL && G == 64) live = __builtin_amdgcn_readfirstlane(min(KB, len - batch * KB));
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            V y[KB];
-            V bm = ninf<V>();
-#pragma unroll
-            for (int k = 0; k < KB; ++k) { y[k] = cf[k] + x[k][v]; bm = fmax(bm, y[k]); }
-            const V nm = fmax(m[v], bm);
-            const V b = (nm == ninf<V>()) ? V(0) : nm;
-            V acc = V(0);
-            if (batch > 0) acc = sm[v] * xexp2(m[v] - b);
-#pragma unroll
-            for (int k = 0; k < KB; ++k)
-              if (k < live) acc += xexp2(y[k] - b);
-            sm[v] = acc;
-            m[v] = nm;
-          }
-          ++batch;
-          if (e + KB >= (ELL ? e0 + len : row_end())) break;
+          for (int k = 0; k < KB; ++k)
+            if (k < live) acc += xexp2(y[k] - bb);
+          sm[v] = acc;
+          m[v] = nm;
+        }
+        ++batch;
+      };
+      if (nonempty) {
+        Batch b;
+        int e = e0;
+        load_batch(b, e, std::true_type{});
+        fold(b);
+        while (more(b, e)) {
+          e += KB;
+          load_batch(b, e, std::false_type{});
+          fold(b);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = (sm[v] > V(0)) ? m[v] + xlog2(sm[v]) + f[v] : ninf<V>();
       } else {
+        epi_loads();
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = ninf<V>();
       }
     }
 
     // ---------------- epilogue ----------------
+    // commodity capacities (loaded here, not with the operands above, so that
+    // solves without them keep the product loop's register budget)
+    V cwv[NV], dcv[NV];
+    if (comm) {
+      vld(a.cw + rowc * Lp + colc, cwv);
+      if (FWD && a.epi == 1) vld(a.dc + rowc * Lp + colc, dcv);
+    }
     V z[NV];   // value stored into the output panel (and calibrated on)
     V plT[NV];  // log domain sink: plan level at time T (= R0T after the update)
 #pragma unroll
@@ -558,9 +573,9 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   }
   if (CHK && a.part) block_stats(st, a.part, bid);
 }
-template <typename V, bool LOG, bool FWD, bool CHK, bool ELL, int KB>
+template <typename V, bool LOG, bool FWD, bool CHK, bool ELL, int KB, bool CM>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
-  step_body<V, LOG, FWD, CHK, ELL, KB>(a, blockIdx.x, gridDim.x);
+  step_body<V, LOG, FWD, CHK, ELL, KB, CM>(a, blockIdx.x, gridDim.x);
 }
 
 
@@ -1080,15 +1095,17 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
   if (record_item(fwd == 0 ? IK_STEP_BWD : (fwd == 1 ? IK_STEP_FWD : IK_STEP_CHK), LOG, nblk, &a, sizeof(a))) return;
   // ELL rows padded to a multiple of 16 gather 16 neighbours per batch, to a
   // multiple of 8 (low-degree graphs such as road grids) 8; CSR batches are 16
-#define MMOT_STEP_LAUNCH(E, K)                                                                               \
+  // commodity capacities run on CSR operators (the solver builds no ELL copy for them)
+#define MMOT_STEP_LAUNCH(E, K, C)                                                                            \
   do {                                                                                                      \
-    if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false, E, K>), dim3(nblk), dim3(kBlock), 0, s, a); \
-    else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, E, K>), dim3(nblk), dim3(kBlock), 0, s, a); \
-    else hipLaunchKernelGGL((k_step<V, LOG, false, false, E, K>), dim3(nblk), dim3(kBlock), 0, s, a);       \
+    if (fwd == 1) hipLaunchKernelGGL((k_step<V, LOG, true, false, E, K, C>), dim3(nblk), dim3(kBlock), 0, s, a); \
+    else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, E, K, C>), dim3(nblk), dim3(kBlock), 0, s, a); \
+    else hipLaunchKernelGGL((k_step<V, LOG, false, false, E, K, C>), dim3(nblk), dim3(kBlock), 0, s, a);       \
   } while (0)
-  if (a.ellD > 0 && a.ellD % 16 == 0) MMOT_STEP_LAUNCH(true, 16);
-  else if (a.ellD > 0) MMOT_STEP_LAUNCH(true, 8);
-  else MMOT_STEP_LAUNCH(false, 16);
+  if (a.cw) MMOT_STEP_LAUNCH(false, 16, true);
+  else if (a.ellD > 0 && a.ellD % 16 == 0) MMOT_STEP_LAUNCH(true, 16, false);
+  else if (a.ellD > 0) MMOT_STEP_LAUNCH(true, 8, false);
+  else MMOT_STEP_LAUNCH(false, 16, false);
 #undef MMOT_STEP_LAUNCH
 }
 template <typename V, bool LOG>
@@ -1182,12 +1199,13 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
     case IK_STEP_FWD:
     case IK_STEP_CHK: {
       const StepArgs<float>& sa = *static_cast<const StepArgs<float>*>(p);
-      const int e = sa.ellD <= 0 ? 0 : (sa.ellD % 16 == 0 ? 2 : 1);
+      const int e = sa.cw ? 3 : (sa.ellD <= 0 ? 0 : (sa.ellD % 16 == 0 ? 2 : 1));
 #define MMOT_STEP_ITEM(F, C)                                                                  \
       do {                                                                                    \
-        if (e == 2) step_body<float, LOG, F, C, true, 16>(sa, bid, it.nblk);                  \
-        else if (e == 1) step_body<float, LOG, F, C, true, 8>(sa, bid, it.nblk);              \
-        else step_body<float, LOG, F, C, false, 16>(sa, bid, it.nblk);                        \
+        if (e == 3) step_body<float, LOG, F, C, false, 16, true>(sa, bid, it.nblk);           \
+        else if (e == 2) step_body<float, LOG, F, C, true, 16, false>(sa, bid, it.nblk);      \
+        else if (e == 1) step_body<float, LOG, F, C, true, 8, false>(sa, bid, it.nblk);       \
+        else step_body<float, LOG, F, C, false, 16, false>(sa, bid, it.nblk);                 \
       } while (0)
       if (it.kind == IK_STEP_BWD) MMOT_STEP_ITEM(false, false);
       else if (it.kind == IK_STEP_FWD) MMOT_STEP_ITEM(true, false);
