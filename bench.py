@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "1d06b68ce15a90fe11e4f5a266d0712b3067c8bcc79e8dd713acc86a0e30e73d",
-                "fetch_kib": 2438.448, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "529ef9d8bfa72914d9b8f0f179004d2527cdce41c6f83420ed84da6064827156",
+                "fetch_kib": 2421.189, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
@@ -126,6 +126,30 @@ def copy_probe(mib, reps=20):
     return 0
 
 
+def library_gemm(shape, reps=50):
+    """Reference point for the dense products: the vendor library's plain GEMM
+    (torch.matmul -> hipBLASLt) of the same shape, no epilogue, BF16 and FP32."""
+    import torch
+    m, k, n = (int(x) for x in shape.split(","))
+    out = {"library_gemm": f"{m}x{k}x{n}", "reps": reps}
+    for name, dt in (("bf16", torch.bfloat16), ("fp32", torch.float32)):
+        g = torch.Generator(device="cuda").manual_seed(0)
+        a = torch.randn(m, k, device="cuda", dtype=dt, generator=g)
+        b = torch.randn(k, n, device="cuda", dtype=dt, generator=g)
+        for _ in range(5):
+            a @ b
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"us": round(ms * 1e3, 2), "tflops": round(2.0 * m * k * n / ms / 1e9, 1)}
+    print(json.dumps(out))
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +166,8 @@ def main():
     ap.add_argument("--serve-lmax", type=int, default=512)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="MiB: only run a plain device copy of this size (HBM counter calibration)")
+    ap.add_argument("--library-gemm", default="",
+                    help="M,K,N: only time the vendor library's plain GEMM of this shape (reference point)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU sharding is designed but not built "
@@ -152,6 +178,8 @@ def main():
         return serving(args)
     if args.copy_probe:
         return copy_probe(args.copy_probe)
+    if args.library_gemm:
+        return library_gemm(args.library_gemm)
 
     import torch
     from paper_2106_14485_amd.solver import Solver

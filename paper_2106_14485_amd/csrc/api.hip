@@ -173,7 +173,7 @@ struct mmot_solver {
 namespace {
 
 int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
-constexpr int kEllMax = 64;    // widest ELL row kept; wider graphs use CSR
+constexpr int kEllMax = 16;    // widest ELL row (one gather batch); wider graphs use CSR
 
 void set_geometry(mmot_solver* s) {
   s->vsize = (s->prec == MMOT_FP64) ? 8 : 4;
@@ -640,10 +640,11 @@ struct Impl {
       HIPCK(hipStreamSynchronize(st));
       {
         const int D = std::max(s->host_flags[0], s->host_flags[1]);
-        // rows of at most 8 entries (grids) gather in batches of 8, wider ones in 16s
-        const int Dp = D <= 8 ? 8 : (D + 15) / 16 * 16;
-        // time-varying networks and commodity capacities run on the CSR operators
-        s->ellD = (D >= 1 && Dp <= kEllMax && s->steps_k == 1 && !s->has_comm) ? Dp : 0;
+        // an ELL row is one gather batch: 8 entries for rows of at most 8 (grids), 16
+        // for at most 16; wider graphs, time-varying networks and commodity
+        // capacities run on the CSR operators
+        const int Dp = D <= 8 ? 8 : 16;
+        s->ellD = (D >= 1 && D <= 16 && s->steps_k == 1 && !s->has_comm) ? Dp : 0;
       }
       if (s->ellD) {
         const V pad = LOG ? -static_cast<V>(INFINITY) : V(0);

@@ -205,6 +205,22 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     // and a flat load would make every later wait a full one)
     return *(const __attribute__((address_space(1))) int*)dp;
   };
+  // ELL rows are exactly one batch of KB entries (padded with the own index and a
+  // zero coefficient), the same for every column chunk of the row: their entries
+  // and the u values at the neighbours are loaded once per row
+  int eidx[ELL ? KB : 1];
+  V ecf[ELL ? KB : 1], euu[ELL ? KB : 1];
+  int elen = KB;
+  if constexpr (ELL) {
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      eidx[k] = a.ci[e0 + k];
+      ecf[k] = a.kv[e0 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) euu[k] = a.uin[eidx[k]];
+    if (LOG && G == 64) elen = ell_len();
+  }
   auto row_end = [&]() -> int { return !valid ? e0 : endv; };
   const size_t Lp = (size_t)a.Lp;
 
@@ -240,34 +256,45 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     // ---------------- product ----------------
     // neighbours in batches of KB: all indices, then all u values and rows are
     // requested before any of them is used, so one batch costs two memory
-    // latencies (entries, then rows and u).  All loads of a batch are
-    // unconditional, so the wave keeps them all in flight: entries past the row
-    // end re-read the batch's first entry (CSR) or the padding (ELL rows are
-    // padded to a multiple of KB with the own index and a zero coefficient), and
-    // their coefficient is masked.  u at the input time is always given (a
-    // vector of ones, or zeros in the log domain, where the input has none).
+    // latencies (entries, then rows and u), an ELL chunk one (its entries are
+    // already loaded).  All loads of a batch are unconditional, so the wave keeps
+    // them all in flight: CSR entries past the row end re-read the batch's first
+    // entry, and their coefficient is masked.  u at the input time is always
+    // given (a vector of ones, or zeros in the log domain, where the input has none).
     struct Batch {
       int idx[KB];
       V cf[KB], uu[KB];
       V x[KB][NV];
       int cnt, len;
     };
-    auto load_batch = [&](Batch& b, int e, auto first) {
-      b.cnt = ell ? KB : min(KB, row_end() - e);
+    auto load_csr = [&](Batch& b, int e, auto first) {
+      b.cnt = min(KB, row_end() - e);
+      b.len = KB;
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
-        const int ek = (ell || k < b.cnt) ? e + k : e;
+        const int ek = (k < b.cnt) ? e + k : e;
         b.idx[k] = a.ci[ek];
         b.cf[k] = a.kv[ek];
       }
-      b.len = ELL ? ell_len() : 0;
 #pragma unroll
       for (int k = 0; k < KB; ++k) b.uu[k] = a.uin[b.idx[k]];
 #pragma unroll
       for (int k = 0; k < KB; ++k) vld(a.xin + b.idx[k] * Lp + col, b.x[k]);
       if constexpr (decltype(first)::value) epi_loads();
     };
-    auto more = [&](const Batch& b, int e) { return e + KB < (ELL ? e0 + b.len : row_end()); };
+    auto load_ell = [&](Batch& b) {
+      b.cnt = KB;
+      b.len = elen;
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        b.idx[k] = eidx[k];
+        b.cf[k] = ecf[k];
+        b.uu[k] = euu[k];
+      }
+#pragma unroll
+      for (int k = 0; k < KB; ++k) vld(a.xin + b.idx[k] * Lp + col, b.x[k]);
+      epi_loads();
+    };
     const bool nonempty = cv && (ell || row_end() > e0);
     if (!LOG) {
       V acc[NV];
@@ -281,15 +308,20 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
           for (int v = 0; v < NV; ++v) acc[v] = fma(c, b.x[k][v], acc[v]);
         }
       };
+      Batch b;
       if (nonempty) {
-        Batch b;
-        int e = e0;
-        load_batch(b, e, std::true_type{});
-        fold(b);
-        while (more(b, e)) {
-          e += KB;
-          load_batch(b, e, std::false_type{});
+        if (ELL) {
+          load_ell(b);
           fold(b);
+        } else {
+          int e = e0;
+          load_csr(b, e, std::true_type{});
+          fold(b);
+          while (e + KB < row_end()) {
+            e += KB;
+            load_csr(b, e, std::false_type{});
+            fold(b);
+          }
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = acc[v] * f[v];
@@ -329,15 +361,20 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
         }
         ++batch;
       };
+      Batch b;
       if (nonempty) {
-        Batch b;
-        int e = e0;
-        load_batch(b, e, std::true_type{});
-        fold(b);
-        while (more(b, e)) {
-          e += KB;
-          load_batch(b, e, std::false_type{});
+        if (ELL) {
+          load_ell(b);
           fold(b);
+        } else {
+          int e = e0;
+          load_csr(b, e, std::true_type{});
+          fold(b);
+          while (e + KB < row_end()) {
+            e += KB;
+            load_csr(b, e, std::false_type{});
+            fold(b);
+          }
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = (sm[v] > V(0)) ? m[v] + xlog2(sm[v]) + f[v] : ninf<V>();
@@ -573,8 +610,10 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   }
   if (CHK && a.part) block_stats(st, a.part, bid);
 }
+// (at least two waves per SIMD: the wide CSR variants would otherwise take the
+// whole register file for one)
 template <typename V, bool LOG, bool FWD, bool CHK, bool ELL, int KB, bool CM>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs<V> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_step(StepArgs<V> a) {
   step_body<V, LOG, FWD, CHK, ELL, KB, CM>(a, blockIdx.x, gridDim.x);
 }
 
@@ -1103,8 +1142,8 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
     else hipLaunchKernelGGL((k_step<V, LOG, false, false, E, K, C>), dim3(nblk), dim3(kBlock), 0, s, a);       \
   } while (0)
   if (a.cw) MMOT_STEP_LAUNCH(false, 16, true);
-  else if (a.ellD > 0 && a.ellD % 16 == 0) MMOT_STEP_LAUNCH(true, 16, false);
-  else if (a.ellD > 0) MMOT_STEP_LAUNCH(true, 8, false);
+  else if (a.ellD == 16) MMOT_STEP_LAUNCH(true, 16, false);
+  else if (a.ellD == 8) MMOT_STEP_LAUNCH(true, 8, false);
   else MMOT_STEP_LAUNCH(false, 16, false);
 #undef MMOT_STEP_LAUNCH
 }
@@ -1199,7 +1238,7 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
     case IK_STEP_FWD:
     case IK_STEP_CHK: {
       const StepArgs<float>& sa = *static_cast<const StepArgs<float>*>(p);
-      const int e = sa.cw ? 3 : (sa.ellD <= 0 ? 0 : (sa.ellD % 16 == 0 ? 2 : 1));
+      const int e = sa.cw ? 3 : (sa.ellD == 16 ? 2 : (sa.ellD == 8 ? 1 : 0));
 #define MMOT_STEP_ITEM(F, C)                                                                  \
       do {                                                                                    \
         if (e == 3) step_body<float, LOG, F, C, false, 16, true>(sa, bid, it.nblk);           \
