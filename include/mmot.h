@@ -132,7 +132,8 @@ typedef struct mmot_solver mmot_solver;
 void mmot_default_options(mmot_options* opt);
 
 /* Bytes of device workspace mmot_create needs for this problem and options.
- * Only sizes/kind/precision are read (no device data is touched).
+ * Only sizes, kinds and precision are read; the optional arrays (state_cost,
+ * cap_comm) are only tested for NULL (no device data is touched).
  * EINVAL on bad sizes; EUNSUPPORTED on an unsupported combination. */
 mmot_status mmot_query_workspace(const mmot_problem* prob, const mmot_options* opt, size_t* bytes_host);
 

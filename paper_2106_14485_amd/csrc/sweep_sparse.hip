@@ -44,6 +44,15 @@ __device__ __forceinline__ float xexp2(float x) { return exp2f(x); }
 __device__ __forceinline__ double xexp2(double x) { return exp2(x); }
 __device__ __forceinline__ float xlog2(float x) { return log2f(x); }
 __device__ __forceinline__ double xlog2(double x) { return log2(x); }
+// log-sum-exp terms: exp2 of an argument <= 0 (or -inf) added to a sum that holds
+// a unit term, and log2 of such a sum (>= 1).  In single precision these are the
+// bare v_exp_f32 / v_log_f32: the library versions differ only by the scaling that
+// makes results below 2^-126 denormal instead of 0 (and accepts denormal inputs),
+// which cannot change a sum of at least 1.
+__device__ __forceinline__ float lexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double lexp2(double x) { return exp2(x); }
+__device__ __forceinline__ float llog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double llog2(double x) { return log2(x); }
 
 template <typename V>
 __device__ __forceinline__ V shfl_xor(V v, int m) { return __shfl_xor(v, m, 64); }
@@ -61,7 +70,7 @@ __device__ __forceinline__ void group_lse(V& m, V& s, int G) {
     V om = shfl_xor(m, k), os = shfl_xor(s, k);
     V nm = fmax(m, om);
     V base = (nm == ninf<V>()) ? V(0) : nm;
-    s = s * xexp2(m - base) + os * xexp2(om - base);
+    s = s * lexp2(m - base) + os * lexp2(om - base);
     m = nm;
   }
 }
@@ -184,11 +193,8 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   const int row = (lb * kWaves + wave) * rpw + grp;
   const bool valid = row < a.n;
   constexpr bool ell = ELL;
-  // CSR batches need the row start at once (wave-uniform for whole-wave rows).
-  // ELL rows start at a fixed offset and padding makes every batch safe to load,
-  // so the row length is only read where a batch ends; it is loaded inside the
-  // batch, behind the entry loads (the empty asm on its address keeps the load
-  // from being hoisted to the kernel start, where the first wait would stall on it).
+  // CSR batches need the row start at once (wave-uniform for whole-wave rows);
+  // ELL rows start at a fixed offset and are exactly one (padded) batch.
   const int rowc = valid ? row : 0;
   int e0 = 0, endv = 0;
   if (ELL) {
@@ -198,19 +204,12 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     endv = a.rp[rowc + 1];
     if (G == 64) { e0 = __builtin_amdgcn_readfirstlane(e0); endv = __builtin_amdgcn_readfirstlane(endv); }
   }
-  auto ell_len = [&]() -> int {
-    const int* dp = a.deg + rowc;
-    asm volatile("" : "+v"(dp));
-    // (a global load again: through the asm the pointer lost its address space,
-    // and a flat load would make every later wait a full one)
-    return *(const __attribute__((address_space(1))) int*)dp;
-  };
+
   // ELL rows are exactly one batch of KB entries (padded with the own index and a
   // zero coefficient), the same for every column chunk of the row: their entries
   // and the u values at the neighbours are loaded once per row
   int eidx[ELL ? KB : 1];
   V ecf[ELL ? KB : 1], euu[ELL ? KB : 1];
-  int elen = KB;
   if constexpr (ELL) {
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
@@ -219,7 +218,6 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     }
 #pragma unroll
     for (int k = 0; k < KB; ++k) euu[k] = a.uin[eidx[k]];
-    if (LOG && G == 64) elen = ell_len();
   }
   auto row_end = [&]() -> int { return !valid ? e0 : endv; };
   const size_t Lp = (size_t)a.Lp;
@@ -265,11 +263,10 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       int idx[KB];
       V cf[KB], uu[KB];
       V x[KB][NV];
-      int cnt, len;
+      int cnt;
     };
     auto load_csr = [&](Batch& b, int e, auto first) {
       b.cnt = min(KB, row_end() - e);
-      b.len = KB;
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
         const int ek = (k < b.cnt) ? e + k : e;
@@ -284,7 +281,6 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     };
     auto load_ell = [&](Batch& b) {
       b.cnt = KB;
-      b.len = elen;
 #pragma unroll
       for (int k = 0; k < KB; ++k) {
         b.idx[k] = eidx[k];
@@ -338,11 +334,9 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       auto fold = [&](Batch& b) {
 #pragma unroll
         for (int k = 0; k < KB; ++k) b.cf[k] = ((ell || k < b.cnt) ? b.cf[k] : ninf<V>()) + b.uu[k];
-        // terms that are exactly zero are not evaluated: the ELL padding of a row
-        // that the whole wave works on (exp2(-inf)), and the rescaled running sum
-        // in a row's first batch (it is empty)
-        int live = KB;
-        if (ELL && G == 64) live = __builtin_amdgcn_readfirstlane(min(KB, b.len - batch * KB));
+        // (the ELL padding and masked CSR entries have coefficient -inf: their terms
+        // are exactly 0; the rescaled running sum of a row's first batch is empty
+        // and is not evaluated)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
           V y[KB];
@@ -352,10 +346,9 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
           const V nm = fmax(m[v], bm);
           const V bb = (nm == ninf<V>()) ? V(0) : nm;
           V acc = V(0);
-          if (batch > 0) acc = sm[v] * xexp2(m[v] - bb);
+          if (batch > 0) acc = sm[v] * lexp2(m[v] - bb);
 #pragma unroll
-          for (int k = 0; k < KB; ++k)
-            if (k < live) acc += xexp2(y[k] - bb);
+          for (int k = 0; k < KB; ++k) acc += lexp2(y[k] - bb);
           sm[v] = acc;
           m[v] = nm;
         }
@@ -377,7 +370,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
           }
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) o[v] = (sm[v] > V(0)) ? m[v] + xlog2(sm[v]) + f[v] : ninf<V>();
+        for (int v = 0; v < NV; ++v) o[v] = (sm[v] > V(0)) ? m[v] + llog2(sm[v]) + f[v] : ninf<V>();
       } else {
         epi_loads();
 #pragma unroll
@@ -479,7 +472,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
               const V y = (cwv[v] == ninf<V>() || wn == ninf<V>()) ? ninf<V>() : q - cwv[v] + wn;
               const V nm = fmax(lm, y);
               const V b = (nm == ninf<V>()) ? V(0) : nm;
-              ls = ls * xexp2(lm - b) + xexp2(y - b);
+              ls = ls * lexp2(lm - b) + lexp2(y - b);
               lm = nm;
               cwn[v] = wn;
             }
@@ -493,7 +486,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             const V y = o[v] + w[v] + g[v];
             const V nm = fmax(lm, y);
             const V b = (nm == ninf<V>()) ? V(0) : nm;
-            ls = ls * xexp2(lm - b) + xexp2(y - b);
+            ls = ls * lexp2(lm - b) + lexp2(y - b);
             lm = nm;
           }
         }
@@ -573,7 +566,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   if (FWD && a.epi == 1) {
     V sv;
     if (!LOG) sv = group_sum(ssum, G);
-    else { group_lse(lm, ls, G); sv = (ls > V(0)) ? lm + xlog2(ls) : ninf<V>(); }
+    else { group_lse(lm, ls, G); sv = (ls > V(0)) ? lm + llog2(ls) : ninf<V>(); }
     if (valid && gl == 0) {
       const V d = a.cap[row];
       V u;

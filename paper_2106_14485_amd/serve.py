@@ -96,12 +96,20 @@ class Pool:
 
 
 def _problem_sizes(inst):
+    """The problem struct as mmot_query_workspace reads it: sizes and kinds, and the
+    optional arrays only as present or absent (a host placeholder, never read)."""
     p = _lib.Problem()
     p.n, p.L, p.T, p.eps = inst.n, inst.L, inst.T, float(inst.eps)
     p.kind = _lib.MMOT_CSR if inst.kind == "csr" else _lib.MMOT_DENSE
     p.nnz = inst.nnz
     p.cost_per_step = 1 if inst.kind == "csr" and np.ndim(inst.cost) == 2 else 0
-    return p, None
+    marker = np.zeros(1)
+    if inst.state_cost is not None:
+        p.state_cost = marker.ctypes.data
+    if getattr(inst, "cap_comm", None) is not None:
+        p.cap_comm = marker.ctypes.data
+        p.cap_comm_per_step = 1 if np.ndim(inst.cap_comm) == 3 else 0
+    return p, marker
 
 
 def serve(instances, arrivals, budget_bytes, max_iter=500, ticks_per_round=32, check_every=10, tol=1e-6):

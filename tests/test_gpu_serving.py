@@ -89,3 +89,33 @@ def test_serve_loop_latency_report():
     s = latency_summary(res, total)
     assert s["n"] == len(insts) and s["p99_s"] >= s["p50_s"] > 0
     assert all(r["status"] == 0 for r in res)
+
+
+def _extensions():
+    """Requests using the extensions: a time-varying network, commodity-dependent
+    capacities (both on the CSR operators), staggered entry/exit windows and
+    per-commodity state costs."""
+    import dataclasses
+    tv = instances.time_varying_instance(instances.rgg_instance(n=300, L=12, T=10, seed=21, cap_lo=1.0, cap_hi=2.0),
+                                         seed=3, closed_frac=0.02)
+    base = instances.rgg_instance(n=350, L=20, T=12, seed=22, cap_lo=1.0, cap_hi=2.0)
+    rng = np.random.default_rng(5)
+    shape = (base.T - 1, base.L, base.n)
+    D = np.where(rng.random(shape) < 0.2, 0.3 * base.src.sum(axis=1)[None, :, None], np.inf)
+    comm = dataclasses.replace(base, cap_comm=D)
+    g = instances.grid_instance(side=5, T=12, L=3, eps=0.1, cap=2.0, seed=4, check_feasible=False)
+    stag = instances.staggered_instance(instances.time_varying_instance(g, seed=1, closed_frac=0.0),
+                                        np.array([0, 1, 2]), np.array([12, 11, 12]))
+    sc = dataclasses.replace(instances.rgg_instance(n=320, L=10, T=10, seed=23, cap_lo=1.0, cap_hi=2.0),
+                             state_cost=rng.uniform(0.0, 0.5, (10, 320)))
+    return [tv, comm, stag, sc]
+
+
+def test_extension_requests_same_in_pool_and_plain():
+    insts = _extensions() + [_mix()[0]]
+    mixed = _pooled(insts, 40)
+    for k, inst in enumerate(insts):
+        plain = _plain(inst, 40)
+        assert np.array_equal(mixed[k][1], plain[1]), f"request {k}: pool differs from plain solver"
+        assert mixed[k][0]["iters"] == plain[0]["iters"]
+        assert mixed[k][0]["dual_obj"] == plain[0]["dual_obj"]
