@@ -65,8 +65,10 @@ void launch_dense_rows(int, int, const float*, const float*, float*, int, double
 void launch_dense_sink(int, int, int, const float*, const float*, float*, int, const double*, const double*,
                        uint32_t*, int, uint32_t*, size_t, int*, double*, double*, double*, int, hipStream_t);
 void launch_dense_gibbs(const double*, int, int, double, float*, float*, void*, void*, hipStream_t);
+void launch_dense_operand(int, int, const float*, const float*, uint16_t*, hipStream_t);
 void launch_dense_rowsum_max(const float*, int, int, uint32_t*, hipStream_t);
-void launch_pool_tick(const TickArgs&, hipStream_t);
+void launch_pool_tick(const TickArgs&, bool, hipStream_t);
+bool pool_item_is_light(const PoolItem&);
 
 // ---- recording of kernel launches into serving-pool work items ----
 struct Recorder {
@@ -353,15 +355,15 @@ struct Impl {
   // dense backward product t+1 -> t
   // BF16 products read the operand diag(u) (panel) in BF16 as prepared by the
   // producer of the panel (the previous backward product's epilogue; the forward
-  // capacity update), except the first product of a sweep, whose operand (U0T,
-  // U01) is staged from FP32
+  // capacity update); the first product of a sweep reads U0T / U01, converted at
+  // the start of the sweep (k_dense_operand)
   static uint16_t* bbuf(mmot_solver* s, int t) { return s->Bbuf[t & 1]; }
   static void dense_bwd(mmot_solver* s, int t, bool calib, hipStream_t st) {
     GemmArgs g = gemm_base(s, false);
     g.B = reinterpret_cast<const float*>((t + 1 == s->T) ? s->U0T : static_cast<void*>(psi(s, t + 1)));
     g.u = reinterpret_cast<const float*>(uat(s, t + 1));
     if (s->dense_bf16) {
-      if (t + 1 < s->T) g.Bb = bbuf(s, t + 1);
+      g.Bb = bbuf(s, t + 1);
       if (t >= 1) { g.bout = bbuf(s, t); g.uo = reinterpret_cast<const float*>(uat(s, t)); }
     }
     g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
@@ -378,7 +380,7 @@ struct Impl {
     GemmArgs g = gemm_base(s, true);
     g.B = reinterpret_cast<const float*>((t == 0) ? s->U01 : static_cast<void*>(zh(s, t)));
     g.u = reinterpret_cast<const float*>(uat(s, t));
-    if (s->dense_bf16 && t >= 1) g.Bb = bbuf(s, t);
+    if (s->dense_bf16) g.Bb = bbuf(s, t);
     g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facf) + (size_t)to * Lp);
     g.out = reinterpret_cast<float*>(zh(s, to));
     g.slot_stride = (size_t)(T + 1) * Lp;
@@ -420,7 +422,7 @@ struct Impl {
     const int T = s->T;
     StepArgs<V> a = base_args(s);
     a.rp = s->rp_b; a.ci = s->ci_b; a.kv = kvat(s, s->kv_b, t);
-    if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_b; a.kv = static_cast<const V*>(s->ell_kv_b); a.deg = s->deg_b; }
+    if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_b; a.kv = static_cast<const V*>(s->ell_kv_b); }
     a.xin = (t + 1 == T) ? static_cast<const V*>(s->U0T) : psi(s, t + 1);
     a.uin = uin_at(s, t + 1);
     a.fac = static_cast<const V*>(s->facb) + (size_t)t * s->Lp;
@@ -445,6 +447,8 @@ struct Impl {
     }
     launch_prep_bwd<V, LOG>(T, s->Lp, s->cb, s->sigb, static_cast<V*>(s->facb), s->gaugeT, s->lvlT, s->slotsE,
                             s->nslot, st);
+    if (s->kind == MMOT_DENSE && s->dense_bf16)
+      launch_dense_operand(s->n, s->Lp, static_cast<const float*>(s->U0T), nullptr, bbuf(s, T), st);
     for (int t = T - 1; t >= 0; --t) {
       if (s->kind == MMOT_DENSE) dense_bwd(s, t, calib, st);
       else launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk, st);
@@ -457,7 +461,7 @@ struct Impl {
     const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
     StepArgs<V> a = base_args(s);
     a.rp = s->rp_f; a.ci = s->ci_f; a.kv = kvat(s, s->kv_f, t);
-    if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_f; a.kv = static_cast<const V*>(s->ell_kv_f); a.deg = s->deg_f; }
+    if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_f; a.kv = static_cast<const V*>(s->ell_kv_f); }
     a.xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
     a.uin = uin_at(s, t);
     const int to = t + 1;
@@ -530,6 +534,8 @@ struct Impl {
       launch_check0<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->U01),
                             static_cast<const V*>(s->R01), s->sigf, s->sigb, s->part, occ, pcomm, s->nblk, st);
     }
+    if (s->kind == MMOT_DENSE && s->dense_bf16)
+      launch_dense_operand(s->n, s->Lp, static_cast<const float*>(s->U01), nullptr, bbuf(s, 0), st);
     for (int t = 0; t < T; ++t) {
       if (s->kind == MMOT_DENSE) dense_fwd(s, t, mode, calib, occ, pcomm, st);
       else launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), mode == 0 ? 1 : 2, s->nblk, st);
@@ -1315,6 +1321,7 @@ mmot_status mmot_pool_run(mmot_pool* P, int32_t max_ticks, int32_t* n_running) {
     TickArgs ta;
     ta.nslot = 0;
     int total = 0;
+    bool lean = true;   // every item of the tick is light: the leaner tick kernel
     for (auto& kv : P->reqs) {
       mmot_pool::Req* r = kv.second;
       if (r->state != 0 || r->lane >= 0 || r->awaiting) continue;
@@ -1323,6 +1330,7 @@ mmot_status mmot_pool_run(mmot_pool* P, int32_t max_ticks, int32_t* n_running) {
       ta.prefix[ta.nslot] = total;
       ta.idx[ta.nslot] = (int)idx;
       ta.prog[ta.nslot] = r->d_prog;
+      lean = lean && pool_item_is_light(r->h_prog[idx]);
       total += r->maxblk;
       ++ta.nslot;
     }
@@ -1330,7 +1338,7 @@ mmot_status mmot_pool_run(mmot_pool* P, int32_t max_ticks, int32_t* n_running) {
     if (ta.nslot == 0) break;   // nothing batched to run now: let the caller admit and poll
     const int li = (int)(P->ticks % mmot_pool::kLead);
     if (P->ticks >= mmot_pool::kLead) (void)hipEventSynchronize(P->lead_ev[li]);
-    launch_pool_tick(ta, P->stream);
+    launch_pool_tick(ta, lean, P->stream);
     if (hipEventRecord(P->lead_ev[li], P->stream) != hipSuccess) return MMOT_EHIP;
     // requests whose chunk ended with this tick: fetch their statistics
     for (auto& kv : P->reqs) {

@@ -464,8 +464,7 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
 // sums: s_j = sum_p part_s[p][j]; update: u_j = 1 if s_j <= d_j else d_j / s_j;
 // check: occupancy u_j s_j and the capacity / dual / gap statistics.
 __global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, const float* __restrict__ cap,
-                             float* __restrict__ u, int update, double* part, double* occ, const float* __restrict__ x,
-                             uint16_t* __restrict__ bout, int Lp) {
+                             float* __restrict__ u, int update, double* part, double* occ) {
   double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int per = (n + gridDim.x - 1) / gridDim.x;
   const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
@@ -487,26 +486,6 @@ __global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, c
       if (occ) occ[j] = occv;
     }
   }
-  if (bout) {
-    // the next product's operand: bf16(u_j x_j) for this block's rows, k-blocked
-    // (element (j, c) at ((j/8) Lp + c) 8 + j%8); u of these rows is final here
-    __syncthreads();
-    __bf16* bo = reinterpret_cast<__bf16*>(bout);
-    const bool quad = ((r0 | (r1 - r0)) & 3) == 0;
-    for (int c = threadIdx.x; c < Lp; c += blockDim.x) {
-      if (quad) {
-        for (int j = r0; j < r1; j += 4) {
-          bf16x4 p;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) p[e] = (__bf16)(u[j + e] * x[(size_t)(j + e) * Lp + c]);
-          *reinterpret_cast<bf16x4*>(bo + ((size_t)(j >> 3) * Lp + c) * 8 + (j & 7)) = p;
-        }
-      } else {
-        for (int j = r0; j < r1; ++j)
-          bo[((size_t)(j >> 3) * Lp + c) * 8 + (j & 7)] = (__bf16)(u[j] * x[(size_t)j * Lp + c]);
-      }
-    }
-  }
   if (part) {
     __shared__ double red[256][kNSt];
 #pragma unroll
@@ -519,6 +498,25 @@ __global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, c
       part[(size_t)blockIdx.x * kNSt + k] = v;
     }
   }
+}
+
+// BF16 operand of the next product, bf16(u_j x_j) k-blocked (element (j, c) at
+// ((j/8) Lp + c) 8 + j%8), one 16-byte store per k-block and column; rows past n
+// (the zero padding of the last k-block) store 0.  u == nullptr: no scaling (the
+// first product of a sweep, which reads U0T or U01)
+__global__ void k_dense_operand(int n, int Lp, const float* __restrict__ x, const float* __restrict__ u,
+                                uint16_t* __restrict__ bout) {
+  const int kb = blockIdx.x, c = blockIdx.y * blockDim.x + threadIdx.x;
+  if (c >= Lp) return;
+  bf16x8 p;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int j = kb * 8 + e;
+    const int jc = j < n ? j : n - 1;
+    const float v = x[(size_t)jc * Lp + c] * (u ? u[jc] : 1.f);
+    p[e] = (j < n) ? (__bf16)v : (__bf16)0.f;
+  }
+  *reinterpret_cast<bf16x8*>(bout + ((size_t)kb * Lp + c) * 8) = p;
 }
 
 // sink update U0T = R0T ./ hatPsi_T (Algorithm 2) from the stored product
@@ -635,6 +633,7 @@ __global__ void k_dense_rowsum_max(const float* __restrict__ K, int n, int lda, 
 }
 
 // launchers
+void launch_dense_operand(int n, int Lp, const float* x, const float* u, uint16_t* bout, hipStream_t s);
 void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
   dim3 grid((a.n + GBM - 1) / GBM, (a.Lp + GBN - 1) / GBN);
   if (bf16 && a.Bb) hipLaunchKernelGGL(k_gemm_lds, grid, dim3(256), 0, s, a);
@@ -644,8 +643,15 @@ void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
 int gemm_col_tiles(int Lp) { return (Lp + GBN - 1) / GBN; }
 void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, float* u, int update, double* part,
                        double* occ, const float* x, uint16_t* bout, int Lp, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_rows, dim3(nblk), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ, x, bout,
-                     Lp);
+  // statistics come as one partial per block of the check pass's fixed grid; the
+  // update alone needs one thread per state
+  const int g = part ? nblk : (n + 255) / 256;
+  hipLaunchKernelGGL(k_dense_rows, dim3(g), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ);
+  // the next product's operand, bf16(u_j x_j), once u is final
+  if (bout) launch_dense_operand(n, Lp, x, u, bout, s);
+}
+void launch_dense_operand(int n, int Lp, const float* x, const float* u, uint16_t* bout, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_operand, dim3((n + 7) / 8, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout);
 }
 void launch_dense_sink(int n, int Lp, int L, const float* hat, const float* rdst, float* u0t, int update,
                        const double* sigT, const double* sighT, uint32_t* slotsE, int nslot, uint32_t* slots_o,

@@ -10,9 +10,10 @@
 //
 // Mapping: a "row group" of G lanes (G = 64 when Lp >= 256 floats) owns one
 // output state; each lane holds 16 bytes (4 floats / 2 doubles) of the row per
-// 64*16-byte chunk.  Neighbour rows are gathered with coalesced 16-byte loads;
-// the commodity reduction is a shuffle reduction inside the group.  Four
-// wavefronts per block, blocks ordered XCD-contiguously.
+// 64*16-byte chunk.  Neighbour rows are gathered with coalesced 16-byte loads in
+// batches (an ELL row is exactly one batch of 8 or 16, loaded once per row; CSR
+// rows take batches of 16); the commodity reduction is a shuffle reduction inside
+// the group.  Four wavefronts per block, blocks ordered XCD-contiguously.
 #include "mmot_internal.h"
 
 #include <type_traits>
@@ -40,8 +41,6 @@ __device__ __forceinline__ void vst(double* p, const double (&r)[2]) {
 }
 
 template <typename V> __device__ __forceinline__ V ninf() { return -static_cast<V>(INFINITY); }
-__device__ __forceinline__ float xexp2(float x) { return exp2f(x); }
-__device__ __forceinline__ double xexp2(double x) { return exp2(x); }
 __device__ __forceinline__ float xlog2(float x) { return log2f(x); }
 __device__ __forceinline__ double xlog2(double x) { return log2(x); }
 // log-sum-exp terms: exp2 of an argument <= 0 (or -inf) added to a sum that holds
@@ -1223,7 +1222,12 @@ void launch_reduce_cost(const double* pflow, const double* pstate, int nblk, int
 // ---------------------------------------------------------------------------
 static_assert(sizeof(StepArgs<float>) <= kItemArgBytes, "item argument area too small");
 
-template <bool LOG>
+// LEAN: a tick whose items are all light (no check-pass step, no CSR or
+// commodity-capacity step; pool_item_is_light decides on the host) runs a kernel
+// without the heavy step variants, so it keeps more waves per SIMD.  A heavy step
+// reaching a lean tick is a host error: it is reported through the request's
+// flags, never run half-done.
+template <bool LOG, bool LEAN>
 __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
   const void* p = it.args;
   switch (it.kind) {
@@ -1232,17 +1236,32 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
     case IK_STEP_CHK: {
       const StepArgs<float>& sa = *static_cast<const StepArgs<float>*>(p);
       const int e = sa.cw ? 3 : (sa.ellD == 16 ? 2 : (sa.ellD == 8 ? 1 : 0));
+      if constexpr (LEAN) {
+        if (it.kind == IK_STEP_CHK || e == 3 || e == 0) {
+          if (bid == 0 && threadIdx.x == 0) atomicOr(sa.flags, FLAG_NONFINITE);
+          break;
+        }
 #define MMOT_STEP_ITEM(F, C)                                                                  \
-      do {                                                                                    \
-        if (e == 3) step_body<float, LOG, F, C, false, 16, true>(sa, bid, it.nblk);           \
-        else if (e == 2) step_body<float, LOG, F, C, true, 16, false>(sa, bid, it.nblk);      \
-        else if (e == 1) step_body<float, LOG, F, C, true, 8, false>(sa, bid, it.nblk);       \
-        else step_body<float, LOG, F, C, false, 16, false>(sa, bid, it.nblk);                 \
-      } while (0)
-      if (it.kind == IK_STEP_BWD) MMOT_STEP_ITEM(false, false);
-      else if (it.kind == IK_STEP_FWD) MMOT_STEP_ITEM(true, false);
-      else MMOT_STEP_ITEM(true, true);
+        do {                                                                                  \
+          if (e == 2) step_body<float, LOG, F, C, true, 16, false>(sa, bid, it.nblk);         \
+          else step_body<float, LOG, F, C, true, 8, false>(sa, bid, it.nblk);                 \
+        } while (0)
+        if (it.kind == IK_STEP_BWD) MMOT_STEP_ITEM(false, false);
+        else MMOT_STEP_ITEM(true, false);
 #undef MMOT_STEP_ITEM
+      } else {
+#define MMOT_STEP_ITEM(F, C)                                                                  \
+        do {                                                                                  \
+          if (e == 3) step_body<float, LOG, F, C, false, 16, true>(sa, bid, it.nblk);         \
+          else if (e == 2) step_body<float, LOG, F, C, true, 16, false>(sa, bid, it.nblk);    \
+          else if (e == 1) step_body<float, LOG, F, C, true, 8, false>(sa, bid, it.nblk);     \
+          else step_body<float, LOG, F, C, false, 16, false>(sa, bid, it.nblk);               \
+        } while (0)
+        if (it.kind == IK_STEP_BWD) MMOT_STEP_ITEM(false, false);
+        else if (it.kind == IK_STEP_FWD) MMOT_STEP_ITEM(true, false);
+        else MMOT_STEP_ITEM(true, true);
+#undef MMOT_STEP_ITEM
+      }
       break;
     }
     case IK_SOURCE: source_body<float, LOG>(*static_cast<const SourceArgs<float>*>(p), bid, it.nblk); break;
@@ -1253,6 +1272,7 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
   }
 }
 
+template <bool LEAN>
 __global__ __launch_bounds__(kBlock) void k_pool_tick(const TickArgs ta) {
   int lo = 0, hi = ta.nslot - 1;
   const int b = blockIdx.x;
@@ -1271,13 +1291,22 @@ __global__ __launch_bounds__(kBlock) void k_pool_tick(const TickArgs ta) {
     case IK_REDUCE2: reduce2_body(*reinterpret_cast<const Reduce2Args*>(it.args), bid, it.nblk); return;
     default: break;
   }
-  if (it.log_domain) run_item<true>(it, bid);
-  else run_item<false>(it, bid);
+  if (it.log_domain) run_item<true, LEAN>(it, bid);
+  else run_item<false, LEAN>(it, bid);
 }
 
-void launch_pool_tick(const TickArgs& ta, hipStream_t s) {
-  if (ta.nslot > 0 && ta.prefix[ta.nslot] > 0)
-    hipLaunchKernelGGL(k_pool_tick, dim3(ta.prefix[ta.nslot]), dim3(kBlock), 0, s, ta);
+void launch_pool_tick(const TickArgs& ta, bool lean, hipStream_t s) {
+  if (ta.nslot > 0 && ta.prefix[ta.nslot] > 0) {
+    if (lean) hipLaunchKernelGGL(k_pool_tick<true>, dim3(ta.prefix[ta.nslot]), dim3(kBlock), 0, s, ta);
+    else hipLaunchKernelGGL(k_pool_tick<false>, dim3(ta.prefix[ta.nslot]), dim3(kBlock), 0, s, ta);
+  }
+}
+// a recorded item that the lean tick runs (see run_item)
+bool pool_item_is_light(const PoolItem& it) {
+  if (it.kind != IK_STEP_BWD && it.kind != IK_STEP_FWD && it.kind != IK_STEP_CHK) return true;
+  if (it.kind == IK_STEP_CHK) return false;
+  const StepArgs<float>& sa = *reinterpret_cast<const StepArgs<float>*>(it.args);
+  return !sa.cw && (sa.ellD == 16 || sa.ellD == 8);
 }
 
 #define MMOT_INST(V, LOG)                                                                                         \
