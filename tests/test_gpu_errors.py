@@ -1,0 +1,98 @@
+"""Error behaviour of the C ABI on the device (each case documented in mmot.h):
+bad problem data is rejected at creation (MMOT_EINVAL) without a usable solver,
+option combinations that are not built return MMOT_EUNSUPPORTED, a workspace below
+the queried size returns MMOT_ENOMEM, and a sink that no walk of T moves reaches is
+reported as MMOT_EINFEASIBLE by the first statistics call.  After every error the
+next, valid solve on the same GPU still agrees with the oracle."""
+import ctypes
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import alg2
+from paper_2106_14485_amd import _lib, instances
+from tests.helpers import rel_l1, to_oracle
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _solver(inst, **kw):
+    from paper_2106_14485_amd.solver import Solver
+    return Solver(inst, **kw)
+
+
+def _status(exc_info):
+    return exc_info.value.args[0] if exc_info.value.args else None
+
+
+def _base():
+    return instances.rgg_instance(n=120, L=5, T=6, seed=3, cap_lo=1.0, cap_hi=2.0)
+
+
+def _expect(inst, status, **kw):
+    with pytest.raises(_lib.MmotError) as e:
+        _solver(inst, **kw)
+    assert e.value.status == status, (e.value.status, status)
+
+
+def test_bad_data_is_rejected():
+    b = _base()
+    src = b.src.copy(); src[0, src[0].argmax()] *= -1.0
+    _expect(dataclasses.replace(b, src=src), _lib.MMOT_EINVAL)                       # negative mass
+    dst = b.dst.copy(); dst[1] *= 1.5
+    _expect(dataclasses.replace(b, dst=dst), _lib.MMOT_EINVAL)                       # unequal masses
+    cost = b.cost.copy(); cost[3] = np.nan
+    _expect(dataclasses.replace(b, cost=cost), _lib.MMOT_EINVAL)                     # NaN cost
+    cap = b.cap_full(); cap[0, 0] = 0.0
+    _expect(dataclasses.replace(b, cap=cap), _lib.MMOT_EINVAL)                       # capacity must be > 0
+    ci = b.colidx.copy(); r0, r1 = b.rowptr[0], b.rowptr[1]
+    ci[r0:r1] = ci[r0:r1][::-1]
+    _expect(dataclasses.replace(b, colidx=ci), _lib.MMOT_EINVAL)                     # unsorted CSR row
+    D = np.full((b.L, b.n), np.inf); D[0, 0] = -1.0
+    _expect(dataclasses.replace(b, cap_comm=D), _lib.MMOT_EINVAL)                    # negative commodity bound
+
+
+def test_unsupported_combinations():
+    d = instances.dense_blob_instance(n=64, L=8, T=4, seed=1)
+    _expect(d, _lib.MMOT_EUNSUPPORTED, precision="fp64")                             # dense products: FP32/BF16
+    _expect(d, _lib.MMOT_EUNSUPPORTED, domain="log")                                 # dense: scaled domain only
+    _expect(dataclasses.replace(d, cap_comm=np.full((d.L, d.n), np.inf)), _lib.MMOT_EUNSUPPORTED)
+
+
+def test_workspace_too_small():
+    from paper_2106_14485_amd.solver import default_options, device_problem
+    b = _base()
+    L = _lib.lib()
+    opts = default_options(precision="fp32", domain="auto")
+    p, keep = device_problem(b, "cuda")
+    nb = ctypes.c_size_t(0)
+    assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(opts), ctypes.byref(nb)) == _lib.MMOT_OK
+    ws = torch.empty(nb.value, dtype=torch.uint8, device="cuda")
+    h = ctypes.c_void_p(0)
+    st = L.mmot_create(ctypes.byref(p), ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()), nb.value - 4096,
+                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(h))
+    assert st == _lib.MMOT_ENOMEM and not h.value
+    del keep
+
+
+def test_unreachable_sink_is_infeasible_and_the_gpu_recovers():
+    b = instances.grid_instance(side=6, T=3, L=2, eps=0.1, cap=5.0, seed=2, check_feasible=False)
+    # a sink more than T grid moves from its source: no walk of T moves reaches it
+    src = np.zeros_like(b.src); dst = np.zeros_like(b.dst)
+    src[:, 0] = 1.0; dst[:, 35] = 1.0
+    bad = dataclasses.replace(b, src=src, dst=dst)
+    S = _solver(bad, precision="fp64", domain="scaled")
+    with pytest.raises(_lib.MmotError) as e:
+        S.iterate(2, stats=True)
+    assert e.value.status == _lib.MMOT_EINFEASIBLE
+    S.close()
+    good = _base()
+    S = _solver(good, precision="fp64", domain="scaled")
+    S.iterate(5)
+    occ = S.occupancy().cpu().numpy()
+    S.close()
+    p = to_oracle(good)
+    ref = alg2.projections(p, alg2.iterate(p, alg2.initial_state(p), 5))["Pt"]
+    assert rel_l1(occ, ref) < 1e-12
