@@ -646,10 +646,11 @@ struct Impl {
       HIPCK(hipStreamSynchronize(st));
       {
         const int D = std::max(s->host_flags[0], s->host_flags[1]);
-        // an ELL row is one gather batch: 8 entries for rows of at most 8 (grids), 16
-        // for at most 16; wider graphs, time-varying networks and commodity
+        // an ELL row is one gather batch of 4, 5, 8 or 16 entries (the smallest that
+        // holds the widest row: padding entries still cost a gather and, in the log
+        // domain, an exp2); wider graphs, time-varying networks and commodity
         // capacities run on the CSR operators
-        const int Dp = D <= 8 ? 8 : 16;
+        const int Dp = D <= 4 ? 4 : D == 5 ? 5 : D <= 8 ? 8 : 16;
         s->ellD = (D >= 1 && D <= 16 && s->steps_k == 1 && !s->has_comm) ? Dp : 0;
       }
       if (s->ellD) {

@@ -43,7 +43,7 @@ struct StepArgs {
   const int* rp;        // operator CSR (rows = output states); unused when ellD > 0
   const int* ci;        // CSR column indices, or ELL [n][ellD] (padding: index = row)
   const V* kv;          // K values (scaled) or log2 K (log); ELL padding 0 / -inf
-  int ellD;             // > 0: ELL layout, rows of exactly this many entries (8 or 16, one gather batch)
+  int ellD;             // > 0: ELL layout, rows of exactly this many entries (4, 5, 8 or 16: one gather batch)
   const V* xin;         // input panel (already multiplied by K_L at its time)
   const V* uin;         // [n] u at the input time (a vector of ones -- zeros in the log domain -- where none)
   const V* fac;         // [Lp] per-column output factor 2^-c (scaled) or -c (log)

@@ -11,7 +11,7 @@
 // Mapping: a "row group" of G lanes (G = 64 when Lp >= 256 floats) owns one
 // output state; each lane holds 16 bytes (4 floats / 2 doubles) of the row per
 // 64*16-byte chunk.  Neighbour rows are gathered with coalesced 16-byte loads in
-// batches (an ELL row is exactly one batch of 8 or 16, loaded once per row; CSR
+// batches (an ELL row is exactly one batch of 4, 5, 8 or 16, loaded once per row; CSR
 // rows take batches of 16); the commodity reduction is a shuffle reduction inside
 // the group.  Four wavefronts per block, blocks ordered XCD-contiguously.
 #include "mmot_internal.h"
@@ -1136,6 +1136,8 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
   if (a.cw) MMOT_STEP_LAUNCH(false, 16, true);
   else if (a.ellD == 16) MMOT_STEP_LAUNCH(true, 16, false);
   else if (a.ellD == 8) MMOT_STEP_LAUNCH(true, 8, false);
+  else if (a.ellD == 5) MMOT_STEP_LAUNCH(true, 5, false);
+  else if (a.ellD == 4) MMOT_STEP_LAUNCH(true, 4, false);
   else MMOT_STEP_LAUNCH(false, 16, false);
 #undef MMOT_STEP_LAUNCH
 }
@@ -1235,15 +1237,18 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
     case IK_STEP_FWD:
     case IK_STEP_CHK: {
       const StepArgs<float>& sa = *static_cast<const StepArgs<float>*>(p);
-      const int e = sa.cw ? 3 : (sa.ellD == 16 ? 2 : (sa.ellD == 8 ? 1 : 0));
+      // 0: CSR, 1..4: ELL of width 8, 16, 5, 4, 5: CSR with commodity capacities
+      const int e = sa.cw ? 5 : (sa.ellD == 8 ? 1 : sa.ellD == 16 ? 2 : sa.ellD == 5 ? 3 : sa.ellD == 4 ? 4 : 0);
       if constexpr (LEAN) {
-        if (it.kind == IK_STEP_CHK || e == 3 || e == 0) {
+        if (it.kind == IK_STEP_CHK || e == 5 || e == 0) {
           if (bid == 0 && threadIdx.x == 0) atomicOr(sa.flags, FLAG_NONFINITE);
           break;
         }
 #define MMOT_STEP_ITEM(F, C)                                                                  \
         do {                                                                                  \
           if (e == 2) step_body<float, LOG, F, C, true, 16, false>(sa, bid, it.nblk);         \
+          else if (e == 3) step_body<float, LOG, F, C, true, 5, false>(sa, bid, it.nblk);     \
+          else if (e == 4) step_body<float, LOG, F, C, true, 4, false>(sa, bid, it.nblk);     \
           else step_body<float, LOG, F, C, true, 8, false>(sa, bid, it.nblk);                 \
         } while (0)
         if (it.kind == IK_STEP_BWD) MMOT_STEP_ITEM(false, false);
@@ -1252,9 +1257,11 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
       } else {
 #define MMOT_STEP_ITEM(F, C)                                                                  \
         do {                                                                                  \
-          if (e == 3) step_body<float, LOG, F, C, false, 16, true>(sa, bid, it.nblk);         \
+          if (e == 5) step_body<float, LOG, F, C, false, 16, true>(sa, bid, it.nblk);         \
           else if (e == 2) step_body<float, LOG, F, C, true, 16, false>(sa, bid, it.nblk);    \
           else if (e == 1) step_body<float, LOG, F, C, true, 8, false>(sa, bid, it.nblk);     \
+          else if (e == 3) step_body<float, LOG, F, C, true, 5, false>(sa, bid, it.nblk);     \
+          else if (e == 4) step_body<float, LOG, F, C, true, 4, false>(sa, bid, it.nblk);     \
           else step_body<float, LOG, F, C, false, 16, false>(sa, bid, it.nblk);               \
         } while (0)
         if (it.kind == IK_STEP_BWD) MMOT_STEP_ITEM(false, false);
@@ -1306,7 +1313,7 @@ bool pool_item_is_light(const PoolItem& it) {
   if (it.kind != IK_STEP_BWD && it.kind != IK_STEP_FWD && it.kind != IK_STEP_CHK) return true;
   if (it.kind == IK_STEP_CHK) return false;
   const StepArgs<float>& sa = *reinterpret_cast<const StepArgs<float>*>(it.args);
-  return !sa.cw && (sa.ellD == 16 || sa.ellD == 8);
+  return !sa.cw && (sa.ellD == 16 || sa.ellD == 8 || sa.ellD == 5 || sa.ellD == 4);
 }
 
 #define MMOT_INST(V, LOG)                                                                                         \
