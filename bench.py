@@ -73,9 +73,15 @@ def cpu_baseline(inst, budget_s=20.0):
     t0 = time.perf_counter()
     alg2.iterate(p, st, k)
     dt = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": k / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} Sinkhorn iterations of the same instance after 1 warm-up (FP64 numpy/scipy, "
-                      f"single-threaded sparse products)"}
+                      f"single-threaded sparse products); host {model}, {os.cpu_count()} hardware threads"}
 
 
 def serving(args):
