@@ -520,3 +520,52 @@ def test_comm_caps_converge_with_slackness():
     mass = alg2.projections(p, ost)["mass"][-1].sum()
     assert abs(alg2.dual_objective(p, ost, mass) - st["dual_obj"]) <= 1e-8 * abs(st["dual_obj"])
     S.close()
+
+
+# ---------------------------------------------------------------------------
+# dense workload at full size (n=4096, L=1024, T=32), as bench.py times it
+# ---------------------------------------------------------------------------
+
+def test_dense_full_size_sampled_and_invariants():
+    """The first iteration's backward sweep runs with u = 1, so each commodity's
+    Psi_1, and with it U01 = R01 ./ Psi_1, is a per-commodity computation the oracle
+    does exactly for a few sampled commodities at full size (on the FP32-rounded
+    marginals, as for the other dense FP32 comparisons).  Sampled log U01 (on
+    entries of R01 within the FP32 range) agree to 1e-4 for FP32 products; BF16
+    products round both operands to 2^-9 relative at each of the T = 32 products,
+    so their log U01 stays within T * 2^-8 = 0.125 (0.03 observed in the mean).
+    Then BF16 iterations and an FP32 polish keep every commodity's mass equal at all
+    times and the sink marginal exact, and the source residual falls."""
+    inst = instances.dense_blob_instance()
+    sample = np.array([0, 257, 640, 1023])
+    # the problem an FP32 solver represents: marginals rounded to FP32, whose support
+    # (entries that survive the rounding) fixes the initial U0T (see dense_oracle)
+    r32 = lambda a: a.astype(np.float32).astype(np.float64)
+    p = alg2.make_problem(inst.cost_dense, inst.eps, inst.T, r32(inst.src[sample]), r32(inst.dst[sample]),
+                          np.full(inst.n, np.inf))
+    st = alg2.initial_state(p)
+    alg2.backward_sweep(p, st)
+    alg2.source_update(p, st)
+    with np.errstate(divide="ignore"):
+        ref = np.log(st.U01)
+    fin = (inst.src[sample] > 1e-30) & np.isfinite(ref)
+    for prec, tol_max, tol_mean in (("fp32", 1e-4, 1e-5), ("bf16", 0.125, 0.03)):
+        S = _solver()(inst, precision=prec, domain="scaled")
+        S.iterate(1)
+        ls = S.log_duals()[0].cpu().numpy()[sample]
+        S.close()
+        d = np.abs(ls[fin] - ref[fin])
+        assert d.max() <= tol_max and d.mean() <= tol_mean, (prec, d.max(), d.mean())
+    S = _solver()(inst, precision="bf16", domain="auto")
+    s1 = S.iterate(20, stats=True)
+    S.set_precision("fp32")
+    s2 = S.iterate(20, stats=True)
+    occ, pc = S.occupancy(per_commodity=True)
+    pc = pc.cpu().numpy()
+    S.close()
+    mass = pc.sum(axis=2)                                   # (T+1, L)
+    m = inst.src.sum(axis=1)
+    assert np.abs(mass - m[None, :]).max() <= 1e-4 * m.max()
+    assert rel_l1(pc[-1], inst.dst) <= 1e-5                 # sink marginal after the sink update
+    assert s2["src_resid"] < s1["src_resid"]
+    assert s2["mass_drift"] <= 1e-4
