@@ -60,12 +60,14 @@ void launch_reduce_cost(const double*, const double*, int, int, double*, double*
 // dense_mfma.hip
 void launch_gemm(const GemmArgs&, bool, hipStream_t);
 int gemm_col_tiles(int);
-void launch_dense_rows(int, int, const float*, const float*, float*, int, double*, double*, const float*, uint16_t*, int,
+void launch_dense_rows(int, int, const float*, const float*, float*, int, double*, double*, const float*, uint16_t*,
+                       float*, int, int,
                        int, hipStream_t);
 void launch_dense_sink(int, int, int, const float*, const float*, float*, int, const double*, const double*,
                        uint32_t*, int, uint32_t*, size_t, int*, double*, double*, double*, int, hipStream_t);
 void launch_dense_gibbs(const double*, int, int, double, float*, float*, void*, void*, hipStream_t);
 void launch_dense_operand(int, int, const float*, const float*, uint16_t*, hipStream_t);
+void launch_dense_operand32(int, int, int, const float*, const float*, float*, hipStream_t);
 void launch_dense_rowsum_max(const float*, int, int, uint32_t*, hipStream_t);
 void launch_pool_tick(const TickArgs&, bool, hipStream_t);
 bool pool_item_is_light(const PoolItem&);
@@ -154,6 +156,7 @@ struct mmot_solver {
   float *Kd = nullptr, *Ktd = nullptr, *part_s = nullptr;
   void *Kb = nullptr, *Ktb = nullptr;
   uint16_t* Bbuf[2] = {nullptr, nullptr};   // BF16 products: next operand, u-scaled, k-blocked (rows padded to 64)
+  float* B32buf[2] = {nullptr, nullptr};     // FP32 products: the same in FP32, 32-row interleaved blocks
   int n8 = 0;
   // ELL copies of the operators (row width ellD, 0 = use CSR)
   int ellD = 0;
@@ -271,6 +274,7 @@ void carve(mmot_solver* s, Carver& c) {
     s->n8 = (int)((n + 63) / 64 * 64);
     for (int i = 0; i < 2; ++i)
       s->Bbuf[i] = s->has_bf16 ? c.take<uint16_t>((size_t)s->n8 * Lp) : nullptr;
+    for (int i = 0; i < 2; ++i) s->B32buf[i] = c.take<float>((size_t)s->n8 * Lp);
   }
   s->deg_b = c.take<int>(n);
   s->deg_f = c.take<int>(n);
@@ -357,14 +361,17 @@ struct Impl {
   // producer of the panel (the previous backward product's epilogue; the forward
   // capacity update); the first product of a sweep reads U0T / U01, converted at
   // the start of the sweep (k_dense_operand)
+  // FP32 products (the polish) read the operand in FP32, written by k_dense_operand32
+  // after each product and capacity update and at the start of each sweep
   static uint16_t* bbuf(mmot_solver* s, int t) { return s->Bbuf[t & 1]; }
+  static float* b32(mmot_solver* s, int t) { return s->B32buf[t & 1]; }
   static void dense_bwd(mmot_solver* s, int t, bool calib, hipStream_t st) {
     GemmArgs g = gemm_base(s, false);
-    g.B = reinterpret_cast<const float*>((t + 1 == s->T) ? s->U0T : static_cast<void*>(psi(s, t + 1)));
-    g.u = reinterpret_cast<const float*>(uat(s, t + 1));
     if (s->dense_bf16) {
       g.Bb = bbuf(s, t + 1);
       if (t >= 1) { g.bout = bbuf(s, t); g.uo = reinterpret_cast<const float*>(uat(s, t)); }
+    } else {
+      g.B32 = b32(s, t + 1);
     }
     g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
     g.out = reinterpret_cast<float*>(psi(s, t));
@@ -372,15 +379,17 @@ struct Impl {
     g.slots = calib ? s->slots_b + (size_t)t * s->Lp : nullptr;
     g.slot_stride = (size_t)(s->T + 1) * s->Lp;
     launch_gemm(g, s->dense_bf16, st);
+    if (!s->dense_bf16 && t >= 1)
+      launch_dense_operand32(s->n, s->n8, s->Lp, reinterpret_cast<const float*>(psi(s, t)),
+                             reinterpret_cast<const float*>(uat(s, t)), b32(s, t), st);
   }
   // dense forward product t -> t+1 with its epilogue kernels
   static void dense_fwd(mmot_solver* s, int t, int mode, bool calib, double* occ, double* pcomm, hipStream_t st) {
     const int T = s->T, to = t + 1;
     const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
     GemmArgs g = gemm_base(s, true);
-    g.B = reinterpret_cast<const float*>((t == 0) ? s->U01 : static_cast<void*>(zh(s, t)));
-    g.u = reinterpret_cast<const float*>(uat(s, t));
     if (s->dense_bf16) g.Bb = bbuf(s, t);
+    else g.B32 = b32(s, t);
     g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facf) + (size_t)to * Lp);
     g.out = reinterpret_cast<float*>(zh(s, to));
     g.slot_stride = (size_t)(T + 1) * Lp;
@@ -400,7 +409,8 @@ struct Impl {
                         reinterpret_cast<float*>(uat(s, to)), mode == 0 ? 1 : 0,
                         mode == 1 ? s->part + (size_t)to * pstride : nullptr,
                         (mode == 1 && occ) ? occ + (size_t)to * s->n : nullptr,
-                        reinterpret_cast<const float*>(zh(s, to)), s->dense_bf16 ? bbuf(s, to) : nullptr, s->Lp,
+                        reinterpret_cast<const float*>(zh(s, to)), s->dense_bf16 ? bbuf(s, to) : nullptr,
+                        s->dense_bf16 ? nullptr : b32(s, to), s->n8, s->Lp,
                         s->nblk, st);
     } else {
       launch_gemm(g, s->dense_bf16, st);   // hatPsi_T into the rolling buffer
@@ -449,6 +459,8 @@ struct Impl {
                             s->nslot, st);
     if (s->kind == MMOT_DENSE && s->dense_bf16)
       launch_dense_operand(s->n, s->Lp, static_cast<const float*>(s->U0T), nullptr, bbuf(s, T), st);
+    else if (s->kind == MMOT_DENSE)
+      launch_dense_operand32(s->n, s->n8, s->Lp, static_cast<const float*>(s->U0T), nullptr, b32(s, T), st);
     for (int t = T - 1; t >= 0; --t) {
       if (s->kind == MMOT_DENSE) dense_bwd(s, t, calib, st);
       else launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk, st);
@@ -536,6 +548,8 @@ struct Impl {
     }
     if (s->kind == MMOT_DENSE && s->dense_bf16)
       launch_dense_operand(s->n, s->Lp, static_cast<const float*>(s->U01), nullptr, bbuf(s, 0), st);
+    else if (s->kind == MMOT_DENSE)
+      launch_dense_operand32(s->n, s->n8, s->Lp, static_cast<const float*>(s->U01), nullptr, b32(s, 0), st);
     for (int t = 0; t < T; ++t) {
       if (s->kind == MMOT_DENSE) dense_fwd(s, t, mode, calib, occ, pcomm, st);
       else launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), mode == 0 ? 1 : 2, s->nblk, st);
@@ -555,9 +569,8 @@ struct Impl {
     auto launch_at = [&](int t) {
       if (s->kind == MMOT_DENSE) {
         GemmArgs g = gemm_base(s, fwd != 0);
-        g.B = reinterpret_cast<const float*>(psi(s, t + 1));
-        g.u = reinterpret_cast<const float*>(uat(s, t + 1));
         if (s->dense_bf16) g.Bb = bbuf(s, t + 1);   // the operand form of the sweep's products
+        else g.B32 = b32(s, t + 1);
         g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
         g.out = reinterpret_cast<float*>(zh(s, t & 1));
         if (fwd) {   // forward product with the capacity partial sums, as in the sweep
@@ -690,6 +703,8 @@ struct Impl {
     launch_fill<V>(static_cast<V*>(s->zh), 2 * n * Lp, zero, st);
     for (int i = 0; i < 2; ++i)   // BF16 operand buffers: padding rows must stay zero
       if (s->Bbuf[i]) launch_fill<uint32_t>(reinterpret_cast<uint32_t*>(s->Bbuf[i]), (size_t)s->n8 * Lp / 2, 0u, st);
+    for (int i = 0; i < 2; ++i)   // FP32 operand buffers: padding rows must stay zero
+      if (s->B32buf[i]) launch_fill<float>(s->B32buf[i], (size_t)s->n8 * Lp, 0.f, st);
     launch_fill<uint32_t>(s->slots_b, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
     launch_fill<uint32_t>(s->slots_f, (size_t)s->nslot * (T + 1) * Lp, 0u, st);
     launch_fill<uint32_t>(s->slotsE, (size_t)s->nslot * Lp, 0u, st);

@@ -8,13 +8,15 @@
 // major, padded leading dimension lda) and B a state-major panel.  The
 // dense-path cost is O(T L n^2) per sweep (remark after Corollary 1).
 //
-// Tiling for gfx950: 128 x 128 output tile per 256-thread workgroup, four
-// wavefronts in a 2 x 2 arrangement each owning 64 x 64 = 2 x 2 MFMA 32x32
-// tiles, K-depth 64 per LDS stage, two LDS buffers: the global loads of stage
-// k+1 are in flight (in registers) while stage k runs on the matrix cores.  BF16: v_mfma_f32_32x32x16_bf16, A stored
-// in BF16, B converted (and scaled by u) while staged.  FP32:
-// v_mfma_f32_32x32x2_f32, operands kept FP32 (k-interleaved in LDS so each
-// lane reads its 16 k-values with 16-byte loads).  Accumulation is FP32.
+// Tiling for gfx950: 128 x 128 output tile per 256-thread workgroup (the
+// 4096 x 1024 output of the benchmark is one tile per CU), four wavefronts in a
+// 2 x 2 arrangement each owning 64 x 64 = 2 x 2 MFMA 32x32 tiles.  Both
+// operands reach LDS by direct 16-byte global->LDS copies through a 4-stage
+// ring (k_gemm_lds): A = K or K^T as stored at setup, B = the next product's
+// operand diag(u) B written by its producer (k_dense_operand / k_dense_operand32
+// or the backward epilogue).  BF16: v_mfma_f32_32x32x16_bf16.  FP32:
+// v_mfma_f32_32x32x2_f32 on operands whose 32-k blocks are stored interleaved so
+// one 16-byte read holds a lane's values for four MFMAs.  Accumulation is FP32.
 //
 // Epilogue: per-column factor 2^-c (range offsets), K_L, store; for interior
 // forward times the partial capacity column sums over the tile's commodities
@@ -31,8 +33,9 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GBM = 128, GBN = 128, GBK = 64;
-constexpr int kPadB16 = 8;   // LDS row padding (elements) for bf16 tiles
-constexpr int kPadF32 = 4;
+// position of k inside its 32-block in the FP32 operand layouts (the two k values
+// of an MFMA k-pair sit 16 apart, so one 16-byte read holds four k-pairs)
+__host__ __device__ __forceinline__ int ipos32(int k) { return (k & ~31) | ((k & 1) << 4) | ((k & 31) >> 1); }
 
 // Epilogue shared by the product kernels: range factor, K_L, store, the next
 // product's BF16 operand, capacity partial sums, column levels.
@@ -147,200 +150,12 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2
   }
 }
 
-// Register-staged GEMM (FP32 products, and the first BF16 product of a sweep):
-// FP32 B is scaled by u and converted while it is written to LDS.
-template <bool BF16>
-__global__ __launch_bounds__(256) void k_gemm(GemmArgs a) {
-  using TA = typename std::conditional<BF16, __bf16, float>::type;
-  constexpr int PAD = BF16 ? kPadB16 : kPadF32;
-  constexpr int LDK = GBK + PAD;
-  constexpr int AV = BF16 ? 4 : 8;          // 16-byte A chunks per thread per stage
-  __shared__ TA As[2][GBM * LDK];
-  __shared__ TA Bs[2][GBN * LDK];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  // XCD-aware order: consecutive hardware blocks go to different XCDs; give each
-  // XCD a contiguous range of row tiles (all column tiles of them), so each A
-  // row tile is streamed from HBM/MALL by one XCD and reused from its L2
-  const int nbm = gridDim.x, nbn = gridDim.y;
-  const int hw = blockIdx.y * nbm + blockIdx.x;
-  const int tot = nbm * nbn;
-  int logical = hw;
-  if ((tot & 7) == 0) logical = (hw & 7) * (tot >> 3) + (hw >> 3);
-  const int bn = logical % nbn, bm = logical / nbn;
-  const int row0 = bm * GBM, col0 = bn * GBN;
-  const TA* A = static_cast<const TA*>(a.A);
-
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
-
-  // staged operands of one K-stage, held in registers between the global
-  // loads and the LDS writes (software pipeline: stage k+1 loads overlap
-  // stage k MFMAs).  All loads of a stage are unconditional (indices clamped,
-  // out-of-range values replaced by zero afterwards), so they issue back to
-  // back and the wave waits once per stage, not once per load.
-  uint4 ra[AV];
-  uint32_t aok = 0;   // bit v: chunk v of A lies inside the matrix (applied at the LDS write)
-  float4 rb[8];
-  float ru[8];
-  uint32_t bok = 0;   // bit e: k row e of the B chunk lies inside the matrix
-  // B: thread owns 4 consecutive columns (16-byte loads along the panel row)
-  // and 8 consecutive k of the stage
-  const int cq = tid & 31, kg = tid >> 5;
-  const int gcb = col0 + cq * 4;
-  const bool bcol_ok = gcb < a.Lp;            // Lp is a multiple of 4
-  const int gcb_c = bcol_ok ? gcb : 0;
-  const bool has_u = a.u != nullptr;
-
-  auto gload = [&](int k0) {
-#pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int c = tid + v * 256;
-      const int r = BF16 ? (c >> 3) : (c >> 4);
-      const int ch = BF16 ? (c & 7) : (c & 15);
-      const int gr = row0 + r, gk = k0 + ch * (BF16 ? 8 : 4);
-      const int grc = gr < a.n ? gr : a.n - 1;
-      const int gkc = gk < a.lda ? gk : 0;
-      ra[v] = *reinterpret_cast<const uint4*>(A + (size_t)grc * a.lda + gkc);
-      if (v == 0) aok = 0;
-      aok |= (gr < a.n && gk < a.lda) ? (1u << v) : 0u;
-    }
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int gk = k0 + kg * 8 + e;
-      const int gkc = gk < a.n ? gk : a.n - 1;
-      rb[e] = *reinterpret_cast<const float4*>(a.B + (size_t)gkc * a.Lp + gcb_c);
-      ru[e] = has_u ? a.u[gkc] : 1.f;
-    }
-    bok = 0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) bok |= (k0 + kg * 8 + e < a.n && bcol_ok) ? (1u << e) : 0u;
-  };
-  auto swrite = [&](int buf) {
-    TA* as = As[buf];
-    TA* bs = Bs[buf];
-#pragma unroll
-    for (int v = 0; v < AV; ++v) {
-      const int c = tid + v * 256;
-      if (!((aok >> v) & 1u)) ra[v] = make_uint4(0, 0, 0, 0);
-      if (BF16) {
-        const int r = c >> 3, ch = c & 7;
-        *reinterpret_cast<uint4*>(&as[r * LDK + ch * 8]) = ra[v];
-      } else {
-        // 16 chunks of 4 k per row; k-interleaved: position h*32 + s holds k = 2s + h
-        const int r = c >> 4, ch = c & 15;
-        float* dst = reinterpret_cast<float*>(&as[r * LDK]);
-        *reinterpret_cast<float2*>(&dst[ch * 2]) = make_float2(__uint_as_float(ra[v].x), __uint_as_float(ra[v].z));
-        *reinterpret_cast<float2*>(&dst[32 + ch * 2]) =
-            make_float2(__uint_as_float(ra[v].y), __uint_as_float(ra[v].w));
-      }
-    }
-    // scale by u (zero outside the matrix) and store column-major: Bs[col][k]
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      float x[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float b = (q == 0) ? rb[e].x : (q == 1) ? rb[e].y : (q == 2) ? rb[e].z : rb[e].w;
-        x[e] = ((bok >> e) & 1u) ? b * ru[e] : 0.f;
-      }
-      if (BF16) {
-        bf16x8 p;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) p[e] = (__bf16)x[e];
-        *reinterpret_cast<bf16x8*>(&bs[(cq * 4 + q) * LDK + kg * 8]) = p;
-      } else {
-        float* dst = reinterpret_cast<float*>(&bs[(cq * 4 + q) * LDK]);
-        *reinterpret_cast<float4*>(&dst[kg * 4]) = make_float4(x[0], x[2], x[4], x[6]);
-        *reinterpret_cast<float4*>(&dst[32 + kg * 4]) = make_float4(x[1], x[3], x[5], x[7]);
-      }
-    }
-  };
-
-  const int nk = (a.n + GBK - 1) / GBK;
-  gload(0);
-  swrite(0);
-  __syncthreads();
-  const int lr = lane & 31, lh = lane >> 5;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * GBK);
-    const TA* as = As[buf];
-    const TA* bs = Bs[buf];
-    if (BF16) {
-#pragma unroll
-      for (int ks = 0; ks < GBK / 16; ++ks) {
-        bf16x8 af[2], bf[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-          af[i] = *reinterpret_cast<const bf16x8*>(&as[(wm * 64 + i * 32 + lr) * LDK + ks * 16 + lh * 8]);
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          bf[j] = *reinterpret_cast<const bf16x8*>(&bs[(wn * 64 + j * 32 + lr) * LDK + ks * 16 + lh * 8]);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bf[j], acc[i][j], 0, 0, 0);
-      }
-    } else {
-      // FP32: accumulate the stage into fresh registers and add once per stage
-      // (blocked summation keeps the FP32 rounding of long K-sums small)
-      f32x16 sacc[2][2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) sacc[i][j][r] = 0.f;
-#pragma unroll
-      for (int s4 = 0; s4 < GBK / 2; s4 += 4) {
-        float4 av[2], bv[2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-          av[i] = *reinterpret_cast<const float4*>(
-              reinterpret_cast<const float*>(&as[(wm * 64 + i * 32 + lr) * LDK]) + lh * 32 + s4);
-#pragma unroll
-        for (int j = 0; j < 2; ++j)
-          bv[j] = *reinterpret_cast<const float4*>(
-              reinterpret_cast<const float*>(&bs[(wn * 64 + j * 32 + lr) * LDK]) + lh * 32 + s4);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-#pragma unroll
-          for (int i = 0; i < 2; ++i) {
-            const float aq = (q == 0) ? av[i].x : (q == 1) ? av[i].y : (q == 2) ? av[i].z : av[i].w;
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              const float bq = (q == 0) ? bv[j].x : (q == 1) ? bv[j].y : (q == 2) ? bv[j].z : bv[j].w;
-              sacc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(aq, bq, sacc[i][j], 0, 0, 0);
-            }
-          }
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] += sacc[i][j];
-    }
-    if (kt + 1 < nk) swrite(buf ^ 1);
-    __syncthreads();
-  }
-
-  gemm_epilogue(a, acc, row0, col0, bn, logical);
-}
-
 // ---------------------------------------------------------------------------
-// BF16 product with both operands in BF16 (A = K or K^T, B = the pre-scaled
-// k-blocked operand): a four-stage ring of LDS buffers filled by direct
-// global->LDS 16-byte loads (no registers in between), so three K-stages are
-// in flight while one is on the matrix cores.  Tile 128 x 128, K-depth 64 per
-// stage, four waves 2 x 2 as in k_gemm.  Rows of a stage are 8 chunks of 16
+// Products with both operands prepared (A = K or K^T, B = the pre-scaled
+// operand): a four-stage ring of LDS buffers filled by direct global->LDS
+// 16-byte loads (no registers in between), so three K-stages are in flight
+// while one is on the matrix cores.  Tile 128 x 128, four waves 2 x 2, K-depth
+// 64 (BF16) or 32 (FP32) per stage.  Rows of a stage are 8 chunks of 16
 // bytes; chunk c of row r sits at slot 8r + (c ^ ((r >> 1) & 7)), which keeps
 // the MFMA operand reads of 16 consecutive rows on distinct LDS banks.  The K
 // extent is padded with zeros to a multiple of 64 in both operands (lda and
@@ -371,7 +186,17 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// F32 = false: BF16 products (v_mfma_f32_32x32x16_bf16), a stage is 64 k, the B
+// operand Bb k-blocked by 8.  F32 = true: FP32 products (v_mfma_f32_32x32x2_f32),
+// a stage is 32 k; A (the FP32 K) and the B operand B32 hold each 32-k block
+// interleaved (position (k%2)*16 + k/2), so the 16 bytes a lane reads are its
+// values for four consecutive MFMAs; each stage is summed into fresh
+// accumulators that are added once per stage (blocked summation keeps the FP32
+// rounding of the long K sums small).  Either way a stage row is 128 bytes.
+template <bool F32>
 __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
+  constexpr int KS = F32 ? 32 : 64;          // k per stage
+  constexpr int ES = F32 ? 4 : 2;            // element bytes
   __shared__ uint4 lds[kStages][2][kSlots];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -383,23 +208,27 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
   if ((tot & 7) == 0) logical = (hw & 7) * (tot >> 3) + (hw >> 3);
   const int bn = logical % nbn, bm = logical / nbn;
   const int row0 = bm * GBM, col0 = bn * GBN;
-  const uint16_t* A = static_cast<const uint16_t*>(a.A);
+  const char* A = static_cast<const char*>(a.A);
+  const char* B = F32 ? reinterpret_cast<const char*>(a.B32) : reinterpret_cast<const char*>(a.Bb);
 
-  // this lane's four slots per operand and stage (wave instruction q covers 64 slots)
+  // this lane's four slots per operand and stage (wave instruction q covers 64
+  // slots); byte offsets at k0 = 0
   size_t aoff[4], boff[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const int slot = (wave * 4 + q) * 64 + lane;
     const int r = slot >> 3, c = (slot & 7) ^ ((r >> 1) & 7);
     const int gr = min(row0 + r, a.n - 1), gc = min(col0 + r, a.Lp - 1);
-    aoff[q] = (size_t)gr * a.lda + c * 8;            // + k0
-    boff[q] = ((size_t)c * a.Lp + gc) * 8;           // + (k0 / 8) * Lp * 8
+    aoff[q] = ((size_t)gr * a.lda) * ES + c * 16;
+    boff[q] = F32 ? ((size_t)gc * 32) * 4 + c * 16              // + (k0/32) Lp 32 floats
+                  : ((size_t)c * a.Lp + gc) * 16;               // + (k0/8) Lp 8 bf16
   }
-  auto issue = [&](int st, int k0) {
+  const size_t bstage = (size_t)a.Lp * (F32 ? 32 * 4 : 8 * 8 * 2);   // bytes per stage of B
+  auto issue = [&](int st, int kt) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      lds_copy16(A + aoff[q] + k0, lds_addr(&lds[st][0][(wave * 4 + q) * 64]));
-      lds_copy16(a.Bb + boff[q] + (size_t)(k0 >> 3) * a.Lp * 8, lds_addr(&lds[st][1][(wave * 4 + q) * 64]));
+      lds_copy16(A + aoff[q] + (size_t)kt * KS * ES, lds_addr(&lds[st][0][(wave * 4 + q) * 64]));
+      lds_copy16(B + boff[q] + (size_t)kt * bstage, lds_addr(&lds[st][1][(wave * 4 + q) * 64]));
     }
   };
 
@@ -411,8 +240,8 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
 
-  const int nk = (a.n + GBK - 1) / GBK;
-  for (int st = 0; st < kStages - 1 && st < nk; ++st) issue(st, st * GBK);
+  const int nk = (a.n + KS - 1) / KS;
+  for (int st = 0; st < kStages - 1 && st < nk; ++st) issue(st, st);
   const int lr = lane & 31, lh = lane >> 5;
   for (int kt = 0; kt < nk; ++kt) {
     // this thread's loads of stage kt have landed once at most the later
@@ -425,32 +254,65 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
     // a bare barrier: the waits above already made this thread's ring writes
     // complete; a fenced barrier would also wait for the stages still in flight
     asm volatile("s_barrier" ::: "memory");
-    if (kt + kStages - 1 < nk) issue((kt + kStages - 1) % kStages, (kt + kStages - 1) * GBK);
+    if (kt + kStages - 1 < nk) issue((kt + kStages - 1) % kStages, kt + kStages - 1);
     const uint4* as = lds[kt % kStages][0];
     const uint4* bs = lds[kt % kStages][1];
-    // operand fragments in two register sets: the reads of k-step ks+1 are in
-    // flight while the MFMAs of k-step ks run
-    bf16x8 af[2][2], bf[2][2];
+    // operand fragments in two register sets: the reads of step ks+1 are in
+    // flight while the MFMAs of step ks run
+    uint4 af[2][2], bf[2][2];
+    // BF16: step ks covers 16 k (chunks 2ks + lh); FP32: step ks covers 4 k-pairs
+    // (chunk 4 lh + ks of the interleaved row)
     auto frag = [&](int ks, int set) {
+      const int ch = F32 ? lh * 4 + ks : ks * 2 + lh;
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-        af[set][i] = __builtin_bit_cast(bf16x8, as[swz_slot(wm * 64 + i * 32 + lr, ks * 2 + lh)]);
+      for (int i = 0; i < 2; ++i) af[set][i] = as[swz_slot(wm * 64 + i * 32 + lr, ch)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        bf[set][j] = __builtin_bit_cast(bf16x8, bs[swz_slot(wn * 64 + j * 32 + lr, ks * 2 + lh)]);
+      for (int j = 0; j < 2; ++j) bf[set][j] = bs[swz_slot(wn * 64 + j * 32 + lr, ch)];
     };
-    frag(0, 0);
-#pragma unroll
-    for (int ks = 0; ks < GBK / 16; ++ks) {
-      if (ks + 1 < GBK / 16) frag(ks + 1, (ks + 1) & 1);
-      // keep the reads above the MFMAs (the scheduler would otherwise sink them
-      // below and reuse one register set, exposing the LDS latency every k-step)
-      __builtin_amdgcn_sched_barrier(0);
+    f32x16 sacc[2][2];
+    if constexpr (F32) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ks & 1][i], bf[ks & 1][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+          for (int r = 0; r < 16; ++r) sacc[i][j][r] = 0.f;
+    }
+    frag(0, 0);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      if (ks + 1 < 4) frag(ks + 1, (ks + 1) & 1);
+      // keep the reads above the MFMAs (the scheduler would otherwise sink them
+      // below and reuse one register set, exposing the LDS latency every step)
+      __builtin_amdgcn_sched_barrier(0);
+      if constexpr (F32) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const uint4 av = af[ks & 1][i], bv = bf[ks & 1][j];
+              const uint32_t aq = q == 0 ? av.x : q == 1 ? av.y : q == 2 ? av.z : av.w;
+              const uint32_t bq = q == 0 ? bv.x : q == 1 ? bv.y : q == 2 ? bv.z : bv.w;
+              sacc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(aq), __uint_as_float(bq),
+                                                                sacc[i][j], 0, 0, 0);
+            }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[ks & 1][i]),
+                                                                __builtin_bit_cast(bf16x8, bf[ks & 1][j]),
+                                                                acc[i][j], 0, 0, 0);
+      }
+    }
+    if constexpr (F32) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] += sacc[i][j];
     }
   }
   __syncthreads();
@@ -603,7 +465,7 @@ __global__ void k_dense_gibbs(const double* __restrict__ C, int n, int lda, doub
     }
     tile[r][tx] = v;
     if (i < n && j < lda) {
-      K[(size_t)i * lda + j] = v;
+      K[(size_t)i * lda + ipos32(j)] = v;
       if (Kb) Kb[(size_t)i * lda + j] = (__bf16)v;
     }
   }
@@ -612,7 +474,7 @@ __global__ void k_dense_gibbs(const double* __restrict__ C, int n, int lda, doub
     const int j = j0 + r, i = i0 + tx;   // Kt[j][i] = K[i][j]
     if (j < n && i < lda) {
       const float v = (i < n) ? tile[tx][r] : 0.f;
-      Kt[(size_t)j * lda + i] = v;
+      Kt[(size_t)j * lda + ipos32(i)] = v;
       if (Ktb) Ktb[(size_t)j * lda + i] = (__bf16)v;
     }
   }
@@ -622,7 +484,7 @@ __global__ void k_dense_rowsum_max(const float* __restrict__ K, int n, int lda, 
   const int i = blockIdx.x;
   __shared__ double red[256];
   double s = 0;
-  for (int j = threadIdx.x; j < n; j += blockDim.x) s += (double)K[(size_t)i * lda + j];
+  for (int j = threadIdx.x; j < lda; j += blockDim.x) s += (double)K[(size_t)i * lda + j];   // (zero padding)
   red[threadIdx.x] = s;
   __syncthreads();
   for (int k = blockDim.x / 2; k > 0; k >>= 1) {
@@ -634,21 +496,46 @@ __global__ void k_dense_rowsum_max(const float* __restrict__ K, int n, int lda, 
 
 // launchers
 void launch_dense_operand(int n, int Lp, const float* x, const float* u, uint16_t* bout, hipStream_t s);
+void launch_dense_operand32(int n, int n8, int Lp, const float* x, const float* u, float* bout, hipStream_t s);
 void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
   dim3 grid((a.n + GBM - 1) / GBM, (a.Lp + GBN - 1) / GBN);
-  if (bf16 && a.Bb) hipLaunchKernelGGL(k_gemm_lds, grid, dim3(256), 0, s, a);
-  else if (bf16) hipLaunchKernelGGL((k_gemm<true>), grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL((k_gemm<false>), grid, dim3(256), 0, s, a);
+  if (bf16) hipLaunchKernelGGL(k_gemm_lds<false>, grid, dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_gemm_lds<true>, grid, dim3(256), 0, s, a);
 }
 int gemm_col_tiles(int Lp) { return (Lp + GBN - 1) / GBN; }
 void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, float* u, int update, double* part,
-                       double* occ, const float* x, uint16_t* bout, int Lp, int nblk, hipStream_t s) {
+                       double* occ, const float* x, uint16_t* bout, float* bout32, int n8, int Lp, int nblk,
+                       hipStream_t s) {
   // statistics come as one partial per block of the check pass's fixed grid; the
   // update alone needs one thread per state
   const int g = part ? nblk : (n + 255) / 256;
   hipLaunchKernelGGL(k_dense_rows, dim3(g), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ);
-  // the next product's operand, bf16(u_j x_j), once u is final
+  // the next product's operand, u_j x_j in BF16 or FP32, once u is final
   if (bout) launch_dense_operand(n, Lp, x, u, bout, s);
+  if (bout32) launch_dense_operand32(n, n8, Lp, x, u, bout32, s);
+}
+// FP32 operand of the next product, u_j x_j in 32-row blocks per column with the
+// rows of a block interleaved (element (j, c) at ((j/32) Lp + c) 32 + ipos32(j%32));
+// rows past n store 0.  One thread per (block, column): 32 loads down the column,
+// eight 16-byte stores.
+__global__ void k_dense_operand32(int n, int Lp, const float* __restrict__ x, const float* __restrict__ u,
+                                  float* __restrict__ bout) {
+  const int kb = blockIdx.x, c = blockIdx.y * blockDim.x + threadIdx.x;
+  if (c >= Lp) return;
+  float v[32];
+#pragma unroll
+  for (int e = 0; e < 32; ++e) {
+    const int j = kb * 32 + e;
+    const int jc = j < n ? j : n - 1;
+    const float y = x[(size_t)jc * Lp + c] * (u ? u[jc] : 1.f);
+    v[ipos32(e)] = (j < n) ? y : 0.f;
+  }
+  float4* o = reinterpret_cast<float4*>(bout + ((size_t)kb * Lp + c) * 32);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) o[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+}
+void launch_dense_operand32(int n, int n8, int Lp, const float* x, const float* u, float* bout, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_operand32, dim3(n8 / 32, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout);
 }
 void launch_dense_operand(int n, int Lp, const float* x, const float* u, uint16_t* bout, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_operand, dim3((n + 7) / 8, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout);

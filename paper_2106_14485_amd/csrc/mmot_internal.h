@@ -172,12 +172,15 @@ struct Reduce2Args {
 struct GemmArgs {
   int n, Lp, L, lda;
   const void* A;        // [n][lda] (bf16 or f32), lda a multiple of 64, zero beyond n
-  const float* B;       // panel [n][Lp] (FP32 operand), scaled by u while staged
-  const float* u;       // [n] scaling of the B rows, nullptr = 1
   // BF16 operand already scaled by u, k-blocked: element (k, c) at ((k/8)*Lp + c)*8 + k%8,
-  // rows padded to a multiple of 64 with zeros; when set, B and u are not read
+  // rows padded to a multiple of 64 with zeros
   const uint16_t* Bb;
   int n8;               // rows of Bb (n rounded up to 64, zero padding)
+  // FP32 operand already scaled by u, in 32-row blocks per column with the k
+  // values of a block interleaved: element (k, c) at ((k/32)*Lp + c)*32 + ipos(k%32),
+  // ipos(k) = (k%2)*16 + k/2 (rows padded to n8 with zeros).  The FP32 K of these
+  // products is stored with the same interleave inside each 32-column block.
+  const float* B32;
   const float* fac;     // [Lp] output column factor
   float* out;           // [n][Lp]
   const float* kl;      // [n][Lp] K_L multiplied into the stored output, nullptr = none
