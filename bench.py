@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "529ef9d8bfa72914d9b8f0f179004d2527cdce41c6f83420ed84da6064827156",
-                "fetch_kib": 2421.189, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "41d4e0427c2784fd1a9c5dab99896743ee2d3de0668a5ec2139e23aa7f4c4a5f",
+                "fetch_kib": 2423.142, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
