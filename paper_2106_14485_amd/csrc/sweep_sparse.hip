@@ -338,16 +338,20 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
         // and is not evaluated)
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
+          // (the maximum and the sum start from the first term: the compiler keeps
+          // a -inf or 0 start, which IEEE semantics do not let it drop)
           V y[KB];
-          V bm = ninf<V>();
 #pragma unroll
-          for (int k = 0; k < KB; ++k) { y[k] = b.cf[k] + b.x[k][v]; bm = fmax(bm, y[k]); }
-          const V nm = fmax(m[v], bm);
+          for (int k = 0; k < KB; ++k) y[k] = b.cf[k] + b.x[k][v];
+          V bm = y[0];
+#pragma unroll
+          for (int k = 1; k < KB; ++k) bm = fmax(bm, y[k]);
+          const V nm = (batch > 0) ? fmax(m[v], bm) : bm;
           const V bb = (nm == ninf<V>()) ? V(0) : nm;
-          V acc = V(0);
-          if (batch > 0) acc = sm[v] * lexp2(m[v] - bb);
+          V acc = lexp2(y[0] - bb);
+          if (batch > 0) acc = sm[v] * lexp2(m[v] - bb) + acc;
 #pragma unroll
-          for (int k = 0; k < KB; ++k) acc += lexp2(y[k] - bb);
+          for (int k = 1; k < KB; ++k) acc += lexp2(y[k] - bb);
           sm[v] = acc;
           m[v] = nm;
         }
@@ -480,14 +484,21 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
 #pragma unroll
           for (int v = 0; v < NV; ++v) ssum = fma(o[v] * w[v], g[v], ssum);
         } else {
+          // the lane's NV terms against their common maximum, then one rescale of
+          // the running sum (NV + 1 exponentials instead of 2 NV)
+          V y[NV];
+          V nm = lm;
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            const V y = o[v] + w[v] + g[v];
-            const V nm = fmax(lm, y);
-            const V b = (nm == ninf<V>()) ? V(0) : nm;
-            ls = ls * lexp2(lm - b) + lexp2(y - b);
-            lm = nm;
+            y[v] = o[v] + w[v] + g[v];
+            nm = fmax(nm, y[v]);
           }
+          const V b = (nm == ninf<V>()) ? V(0) : nm;
+          V sum = ls * lexp2(lm - b);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sum += lexp2(y[v] - b);
+          ls = sum;
+          lm = nm;
         }
         if (CHK && (a.pcomm || a.kl || comm)) {
           // update-free pass: u is final, P_{0,t} = hatPsi (.) Psi (.) K_L w_t u_t (eq. proj_0t);

@@ -312,6 +312,23 @@ def test_road_grid_small_log_domain():
     compare(g64, o, 1e-12, duals_tol=1e-8)
 
 
+@pytest.mark.parametrize("L,domain", [(600, "log"), (1000, "log"), (600, "scaled")])
+def test_road_grid_rows_of_several_chunks(L, domain):
+    """More commodities than one wave covers (L > 256: rows of 3 or 4 column
+    chunks in FP32, 5 or 8 in FP64) on the 5-wide ELL operator of a road grid,
+    where each step issues the loads of two chunks before processing either;
+    odd chunk counts re-read their last chunk.  FP64 to 1e-12; FP32 to 1e-5, or
+    its log-domain floor where that is larger (eps = 1 keeps the scaled domain's
+    range small)."""
+    log = domain == "log"
+    inst = instances.road_grid_instance(side=8, L=L, T=10, eps=0.1 if log else 1.0, seed=L)
+    o = oracle_outputs(inst, 8, log=log)
+    g64 = gpu_outputs(inst, 8, "fp64", domain)
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+    g = gpu_outputs(inst, 8, "fp32", domain)
+    compare(g, o, max(1e-5, o["floor"]))
+
+
 def test_road_grid_full_size_invariants():
     """The 100 x 100 road grid with 2000 commodities and T = 120 (9.6 GB of stored
     messages): too large for the oracle, so the properties every iterate has are
