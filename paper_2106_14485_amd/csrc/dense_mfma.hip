@@ -362,21 +362,56 @@ __global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, c
   }
 }
 
+// The capacity update of the R rows r0.. (as in k_dense_rows, same order of the
+// partial sums, so the same u) computed inside an operand kernel: into LDS for
+// the block, and into u by the blocks of the first column range.  Every thread
+// of the block reaches the barrier.
+template <int R>
+__device__ __forceinline__ void rows_update(int n, int ntn, const float* __restrict__ part_s,
+                                            const float* __restrict__ cap, float* __restrict__ u, int r0,
+                                            float* us) {
+  if ((int)threadIdx.x < R) {
+    const int j = r0 + threadIdx.x;
+    float uj = 0.f;
+    if (j < n) {
+      float s = 0.f;
+      for (int p = 0; p < ntn; ++p) s += part_s[(size_t)p * n + j];
+      const float d = cap[j];
+      uj = (s <= d) ? 1.f : d / s;
+      if (blockIdx.y == 0) u[j] = uj;
+    }
+    us[threadIdx.x] = uj;
+  }
+  __syncthreads();
+}
+
 // BF16 operand of the next product, bf16(u_j x_j) k-blocked (element (j, c) at
 // ((j/8) Lp + c) 8 + j%8), one 16-byte store per k-block and column; rows past n
 // (the zero padding of the last k-block) store 0.  u == nullptr: no scaling (the
-// first product of a sweep, which reads U0T or U01)
+// first product of a sweep, which reads U0T or U01).  part_s != nullptr: the
+// capacity update of the block's rows is done here first (u written, then used).
 __global__ void k_dense_operand(int n, int Lp, const float* __restrict__ x, const float* __restrict__ u,
-                                uint16_t* __restrict__ bout) {
+                                uint16_t* __restrict__ bout, int ntn, const float* __restrict__ part_s,
+                                const float* __restrict__ cap, float* __restrict__ uw) {
   const int kb = blockIdx.x, c = blockIdx.y * blockDim.x + threadIdx.x;
+  __shared__ float us[8];
+  // the panel values are requested before the update's partial sums, so both are in flight together
+  const int cc = c < Lp ? c : Lp - 1;
+  float xv[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int j = kb * 8 + e;
+    xv[e] = x[(size_t)(j < n ? j : n - 1) * Lp + cc];
+  }
+  if (part_s) rows_update<8>(n, ntn, part_s, cap, uw, kb * 8, us);
   if (c >= Lp) return;
   bf16x8 p;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const int j = kb * 8 + e;
     const int jc = j < n ? j : n - 1;
-    const float v = x[(size_t)jc * Lp + c] * (u ? u[jc] : 1.f);
-    p[e] = (j < n) ? (__bf16)v : (__bf16)0.f;
+    const float sc = part_s ? us[e] : (u ? u[jc] : 1.f);
+    p[e] = (j < n) ? (__bf16)(xv[e] * sc) : (__bf16)0.f;
   }
   *reinterpret_cast<bf16x8*>(bout + ((size_t)kb * Lp + c) * 8) = p;
 }
@@ -503,11 +538,24 @@ void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
   else hipLaunchKernelGGL(k_gemm_lds<true>, grid, dim3(256), 0, s, a);
 }
 int gemm_col_tiles(int Lp) { return (Lp + GBN - 1) / GBN; }
+__global__ void k_dense_operand32(int n, int Lp, const float* __restrict__ x, const float* __restrict__ u,
+                                  float* __restrict__ bout, int ntn, const float* __restrict__ part_s,
+                                  const float* __restrict__ cap, float* __restrict__ uw);
 void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, float* u, int update, double* part,
                        double* occ, const float* x, uint16_t* bout, float* bout32, int n8, int Lp, int nblk,
                        hipStream_t s) {
-  // statistics come as one partial per block of the check pass's fixed grid; the
-  // update alone needs one thread per state
+  // an update that feeds a next product is done by the operand kernel itself (one
+  // launch); statistics come as one partial per block of the check pass's fixed
+  // grid, and an update alone needs one thread per state
+  if (update && !part && (bout || bout32)) {
+    if (bout)
+      hipLaunchKernelGGL(k_dense_operand, dim3((n + 7) / 8, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout,
+                         ntn, part_s, cap, u);
+    else
+      hipLaunchKernelGGL(k_dense_operand32, dim3(n8 / 32, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout32,
+                         ntn, part_s, cap, u);
+    return;
+  }
   const int g = part ? nblk : (n + 255) / 256;
   hipLaunchKernelGGL(k_dense_rows, dim3(g), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ);
   // the next product's operand, u_j x_j in BF16 or FP32, once u is final
@@ -519,15 +567,26 @@ void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, fl
 // rows past n store 0.  One thread per (block, column): 32 loads down the column,
 // eight 16-byte stores.
 __global__ void k_dense_operand32(int n, int Lp, const float* __restrict__ x, const float* __restrict__ u,
-                                  float* __restrict__ bout) {
+                                  float* __restrict__ bout, int ntn, const float* __restrict__ part_s,
+                                  const float* __restrict__ cap, float* __restrict__ uw) {
   const int kb = blockIdx.x, c = blockIdx.y * blockDim.x + threadIdx.x;
+  __shared__ float us[32];
+  // the panel values are requested before the update's partial sums, so both are in flight together
+  const int cc = c < Lp ? c : Lp - 1;
+  float xv[32];
+#pragma unroll
+  for (int e = 0; e < 32; ++e) {
+    const int j = kb * 32 + e;
+    xv[e] = x[(size_t)(j < n ? j : n - 1) * Lp + cc];
+  }
+  if (part_s) rows_update<32>(n, ntn, part_s, cap, uw, kb * 32, us);
   if (c >= Lp) return;
   float v[32];
 #pragma unroll
   for (int e = 0; e < 32; ++e) {
     const int j = kb * 32 + e;
     const int jc = j < n ? j : n - 1;
-    const float y = x[(size_t)jc * Lp + c] * (u ? u[jc] : 1.f);
+    const float y = xv[e] * (part_s ? us[e] : (u ? u[jc] : 1.f));
     v[ipos32(e)] = (j < n) ? y : 0.f;
   }
   float4* o = reinterpret_cast<float4*>(bout + ((size_t)kb * Lp + c) * 32);
@@ -535,10 +594,12 @@ __global__ void k_dense_operand32(int n, int Lp, const float* __restrict__ x, co
   for (int q = 0; q < 8; ++q) o[q] = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
 }
 void launch_dense_operand32(int n, int n8, int Lp, const float* x, const float* u, float* bout, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_operand32, dim3(n8 / 32, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout);
+  hipLaunchKernelGGL(k_dense_operand32, dim3(n8 / 32, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout, 0,
+                     nullptr, nullptr, nullptr);
 }
 void launch_dense_operand(int n, int Lp, const float* x, const float* u, uint16_t* bout, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_operand, dim3((n + 7) / 8, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout);
+  hipLaunchKernelGGL(k_dense_operand, dim3((n + 7) / 8, (Lp + 255) / 256), dim3(256), 0, s, n, Lp, x, u, bout, 0,
+                     nullptr, nullptr, nullptr);
 }
 void launch_dense_sink(int n, int Lp, int L, const float* hat, const float* rdst, float* u0t, int update,
                        const double* sigT, const double* sighT, uint32_t* slotsE, int nslot, uint32_t* slots_o,
