@@ -8,9 +8,10 @@
 // major, padded leading dimension lda) and B a state-major panel.  The
 // dense-path cost is O(T L n^2) per sweep (remark after Corollary 1).
 //
-// Tiling for gfx950: 128 x 128 output tile per 256-thread workgroup (the
-// 4096 x 1024 output of the benchmark is one tile per CU), four wavefronts in a
-// 2 x 2 arrangement each owning 64 x 64 = 2 x 2 MFMA 32x32 tiles.  Both
+// Tiling for gfx950: 128 x 128 output tile per 512-thread workgroup (the
+// 4096 x 1024 output of the benchmark is one tile per CU), two groups of four
+// wavefronts, each group in a 2 x 2 arrangement of 64 x 64 = 2 x 2 MFMA 32x32
+// tiles over half of the k-steps (two waves per SIMD).  Both
 // operands reach LDS by direct 16-byte global->LDS copies through a 4-stage
 // ring (k_gemm_lds): A = K or K^T as stored at setup, B = the next product's
 // operand diag(u) B written by its producer (k_dense_operand / k_dense_operand32
@@ -25,6 +26,7 @@
 #include "mmot_internal.h"
 #include <hip/hip_bf16.h>
 #include <math.h>
+#include <type_traits>
 
 namespace mmot {
 
@@ -37,14 +39,20 @@ constexpr int GBM = 128, GBN = 128, GBK = 64;
 // of an MFMA k-pair sit 16 apart, so one 16-byte read holds four k-pairs)
 __host__ __device__ __forceinline__ int ipos32(int k) { return (k & ~31) | ((k & 1) << 4) | ((k & 31) >> 1); }
 
-// Epilogue shared by the product kernels: range factor, K_L, store, the next
-// product's BF16 operand, capacity partial sums, column levels.
+// Epilogue of the product kernel: range factor, K_L, store, the next product's
+// BF16 operand, capacity partial sums, column levels.  Two wave groups of four
+// (2 x 2 over the tile) hold the whole sum; group g handles the 32-column half
+// j = g of its wave's 64 x 64 quadrant.  smem: LDS that no wave reads any more
+// (the operand ring), 2 * 256 + 2 * GBN floats.
+constexpr int NG = 2;
 __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2][2], int row0, int col0, int bn,
-                                              int logical) {
-  __shared__ float red[2][2][64];   // capacity partial sums across the two column waves
-  __shared__ float cmx[2][GBN];     // column maxima across the two row waves
+                                              int logical, float* smem) {
+  // red[g][wm][wn][64]: capacity partial sums across the column waves (and groups)
+  float (*red)[2][2][64] = reinterpret_cast<float (*)[2][2][64]>(smem);
+  float (*cmx)[GBN] = reinterpret_cast<float (*)[GBN]>(smem + NG * 2 * 2 * 64);   // column maxima
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int grp = wave >> 2, wq = wave & 3;
+  const int wm = wq >> 1, wn = wq & 1;
   const int lr = lane & 31, lh = lane >> 5;
   (void)lane;
   float colmax[2] = {-INFINITY, -INFINITY};
@@ -55,6 +63,7 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2
     for (int r = 0; r < 16; ++r) rsum[i][r] = 0.f;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
+    if (j != grp) continue;
     const int gc = col0 + wn * 64 + j * 32 + lr;
     const bool cok = gc < a.Lp;
     const int gcc = cok ? gc : 0;
@@ -124,18 +133,20 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) red[wm][wn][i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)] = rsum[i][r];
+        for (int r = 0; r < 16; ++r) red[grp][wm][wn][i * 32 + 8 * (r >> 2) + 4 * lh + (r & 3)] = rsum[i][r];
     }
     __syncthreads();
     if (tid < 128) {
       const int wmr = tid >> 6, rr = tid & 63;
       const int gr = row0 + wmr * 64 + rr;
-      if (gr < a.n) a.part_s[(size_t)bn * a.n + gr] = red[wmr][0][rr] + red[wmr][1][rr];
+      const float v = red[0][wmr][0][rr] + red[0][wmr][1][rr] + red[1][wmr][0][rr] + red[1][wmr][1][rr];
+      if (gr < a.n) a.part_s[(size_t)bn * a.n + gr] = v;
     }
   }
   if (a.slots) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
+      if (j != grp) continue;
       float m = colmax[j];
       m = fmaxf(m, __shfl_xor(m, 32, 64));
       if (lh == 0) cmx[wm][wn * 64 + j * 32 + lr] = m;
@@ -154,8 +165,8 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2
 // Products with both operands prepared (A = K or K^T, B = the pre-scaled
 // operand): a four-stage ring of LDS buffers filled by direct global->LDS
 // 16-byte loads (no registers in between), so three K-stages are in flight
-// while one is on the matrix cores.  Tile 128 x 128, four waves 2 x 2, K-depth
-// 64 (BF16) or 32 (FP32) per stage.  Rows of a stage are 8 chunks of 16
+// while one is on the matrix cores.  Tile 128 x 128, two groups of four waves
+// 2 x 2, K-depth 64 (BF16) or 32 (FP32) per stage.  Rows of a stage are 8 chunks of 16
 // bytes; chunk c of row r sits at slot 8r + (c ^ ((r >> 1) & 7)), which keeps
 // the MFMA operand reads of 16 consecutive rows on distinct LDS banks.  The K
 // extent is padded with zeros to a multiple of 64 in both operands (lda and
@@ -186,21 +197,31 @@ __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-// F32 = false: BF16 products (v_mfma_f32_32x32x16_bf16), a stage is 64 k, the B
-// operand Bb k-blocked by 8.  F32 = true: FP32 products (v_mfma_f32_32x32x2_f32),
-// a stage is 32 k; A (the FP32 K) and the B operand B32 hold each 32-k block
-// interleaved (position (k%2)*16 + k/2), so the 16 bytes a lane reads are its
-// values for four consecutive MFMAs; each stage is summed into fresh
-// accumulators that are added once per stage (blocked summation keeps the FP32
-// rounding of the long K sums small).  Either way a stage row is 128 bytes.
+// The product kernel.  F32 = false: BF16 products (v_mfma_f32_32x32x16_bf16), a
+// stage is 64 k (four steps of 16), the B operand Bb k-blocked by 8.  F32 = true:
+// FP32 products (v_mfma_f32_32x32x2_f32), a stage is 32 k (four steps of four
+// k-pairs); A (the FP32 K) and the B operand B32 hold each 32-k block interleaved
+// (position (k%2)*16 + k/2), so the 16 bytes a lane reads are its values for four
+// consecutive MFMAs, and each stage is summed into fresh accumulators that are
+// added once per stage (blocked summation keeps the FP32 rounding of the long K
+// sums small).  Either way a stage row is 128 bytes.
+//
+// Two groups of four waves per tile (eight waves, two per SIMD): each group
+// computes the whole 128 x 128 tile 2 x 2 (64 x 64 per wave) over half of every
+// stage's steps (group g: steps 2g and 2g+1), so while one wave of a SIMD waits
+// for its LDS reads or at the stage barrier the other can issue MFMAs (one group
+// of four waves took 53.2 us per BF16 product, two take 50.3 us).  At the end
+// each group posts the 32-column half that the other group stores, adds the half
+// it keeps, and the two groups share the epilogue.
 template <bool F32>
-__global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
+__global__ __launch_bounds__(512) void k_gemm_lds(GemmArgs a) {
   constexpr int KS = F32 ? 32 : 64;          // k per stage
   constexpr int ES = F32 ? 4 : 2;            // element bytes
   __shared__ uint4 lds[kStages][2][kSlots];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = wave >> 1, wn = wave & 1;
+  const int grp = wave >> 2, wq = wave & 3;
+  const int wm = wq >> 1, wn = wq & 1;
   const int nbm = gridDim.x, nbn = gridDim.y;
   const int hw = blockIdx.y * nbm + blockIdx.x;
   const int tot = nbm * nbn;
@@ -211,12 +232,11 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
   const char* A = static_cast<const char*>(a.A);
   const char* B = F32 ? reinterpret_cast<const char*>(a.B32) : reinterpret_cast<const char*>(a.Bb);
 
-  // this lane's four slots per operand and stage (wave instruction q covers 64
-  // slots); byte offsets at k0 = 0
-  size_t aoff[4], boff[4];
+  // this lane's two slots per operand and stage (byte offsets at k0 = 0)
+  size_t aoff[2], boff[2];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int slot = (wave * 4 + q) * 64 + lane;
+  for (int q = 0; q < 2; ++q) {
+    const int slot = (wave * 2 + q) * 64 + lane;
     const int r = slot >> 3, c = (slot & 7) ^ ((r >> 1) & 7);
     const int gr = min(row0 + r, a.n - 1), gc = min(col0 + r, a.Lp - 1);
     aoff[q] = ((size_t)gr * a.lda) * ES + c * 16;
@@ -226,9 +246,9 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
   const size_t bstage = (size_t)a.Lp * (F32 ? 32 * 4 : 8 * 8 * 2);   // bytes per stage of B
   auto issue = [&](int st, int kt) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      lds_copy16(A + aoff[q] + (size_t)kt * KS * ES, lds_addr(&lds[st][0][(wave * 4 + q) * 64]));
-      lds_copy16(B + boff[q] + (size_t)kt * bstage, lds_addr(&lds[st][1][(wave * 4 + q) * 64]));
+    for (int q = 0; q < 2; ++q) {
+      lds_copy16(A + aoff[q] + (size_t)kt * KS * ES, lds_addr(&lds[st][0][(wave * 2 + q) * 64]));
+      lds_copy16(B + boff[q] + (size_t)kt * bstage, lds_addr(&lds[st][1][(wave * 2 + q) * 64]));
     }
   };
 
@@ -244,79 +264,104 @@ __global__ __launch_bounds__(256) void k_gemm_lds(GemmArgs a) {
   for (int st = 0; st < kStages - 1 && st < nk; ++st) issue(st, st);
   const int lr = lane & 31, lh = lane >> 5;
   for (int kt = 0; kt < nk; ++kt) {
-    // this thread's loads of stage kt have landed once at most the later
-    // stages' loads (8 per stage) are outstanding; the barrier extends that to
-    // the whole block and frees the ring slot read in the previous stage
+    // stage kt has landed once at most the later stages' copies (4 per stage and
+    // thread) are outstanding; the barrier extends that to the block and frees
+    // the ring slot read in the previous stage
     const int later = min(kStages - 2, nk - 1 - kt);
-    if (later >= 2) wait_vm<16>();
-    else if (later == 1) wait_vm<8>();
+    if (later >= 2) wait_vm<8>();
+    else if (later == 1) wait_vm<4>();
     else wait_vm<0>();
-    // a bare barrier: the waits above already made this thread's ring writes
-    // complete; a fenced barrier would also wait for the stages still in flight
     asm volatile("s_barrier" ::: "memory");
     if (kt + kStages - 1 < nk) issue((kt + kStages - 1) % kStages, kt + kStages - 1);
     const uint4* as = lds[kt % kStages][0];
     const uint4* bs = lds[kt % kStages][1];
-    // operand fragments in two register sets: the reads of step ks+1 are in
-    // flight while the MFMAs of step ks run
+    // both of this group's steps read at once; BF16: step ks covers 16 k (chunks
+    // 2 ks + lh); FP32: step ks covers 4 k-pairs (chunk 4 lh + ks of the
+    // interleaved row)
     uint4 af[2][2], bf[2][2];
-    // BF16: step ks covers 16 k (chunks 2ks + lh); FP32: step ks covers 4 k-pairs
-    // (chunk 4 lh + ks of the interleaved row)
-    auto frag = [&](int ks, int set) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int ks = grp * 2 + h;
       const int ch = F32 ? lh * 4 + ks : ks * 2 + lh;
 #pragma unroll
-      for (int i = 0; i < 2; ++i) af[set][i] = as[swz_slot(wm * 64 + i * 32 + lr, ch)];
+      for (int i = 0; i < 2; ++i) af[h][i] = as[swz_slot(wm * 64 + i * 32 + lr, ch)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) bf[set][j] = bs[swz_slot(wn * 64 + j * 32 + lr, ch)];
-    };
-    f32x16 sacc[2][2];
+      for (int j = 0; j < 2; ++j) bf[h][j] = bs[swz_slot(wn * 64 + j * 32 + lr, ch)];
+    }
+    __builtin_amdgcn_sched_barrier(0);
     if constexpr (F32) {
+      // the stage's products summed apart and added once (blocked summation)
+      f32x16 sacc[2][2];
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
 #pragma unroll
           for (int r = 0; r < 16; ++r) sacc[i][j][r] = 0.f;
-    }
-    frag(0, 0);
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      if (ks + 1 < 4) frag(ks + 1, (ks + 1) & 1);
-      // keep the reads above the MFMAs (the scheduler would otherwise sink them
-      // below and reuse one register set, exposing the LDS latency every step)
-      __builtin_amdgcn_sched_barrier(0);
-      if constexpr (F32) {
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
         for (int q = 0; q < 4; ++q)
 #pragma unroll
           for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-              const uint4 av = af[ks & 1][i], bv = bf[ks & 1][j];
+              const uint4 av = af[h][i], bv = bf[h][j];
               const uint32_t aq = q == 0 ? av.x : q == 1 ? av.y : q == 2 ? av.z : av.w;
               const uint32_t bq = q == 0 ? bv.x : q == 1 ? bv.y : q == 2 ? bv.z : bv.w;
               sacc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(aq), __uint_as_float(bq),
                                                                 sacc[i][j], 0, 0, 0);
             }
-      } else {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[ks & 1][i]),
-                                                                __builtin_bit_cast(bf16x8, bf[ks & 1][j]),
-                                                                acc[i][j], 0, 0, 0);
-      }
-    }
-    if constexpr (F32) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] += sacc[i][j];
+    } else {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, af[h][i]),
+                                                                __builtin_bit_cast(bf16x8, bf[h][j]), acc[i][j], 0,
+                                                                0, 0);
     }
   }
+  // group g keeps column half j = g of its quadrant: it posts its half 1 - g (two
+  // 32 x 32 tiles, 8 KB per wave) and adds the other group's half g
   __syncthreads();
-  gemm_epilogue(a, acc, row0, col0, bn, logical);
+  float4* rbuf = reinterpret_cast<float4*>(&lds[0][0][0]);
+  auto post = [&](auto jc) {
+    constexpr int J = decltype(jc)::value;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        rbuf[((wave * 2 + i) * 4 + r) * 64 + lane] =
+            make_float4(acc[i][J][4 * r], acc[i][J][4 * r + 1], acc[i][J][4 * r + 2], acc[i][J][4 * r + 3]);
+  };
+  auto take = [&](auto jc) {
+    constexpr int J = decltype(jc)::value;
+    const int src = (1 - grp) * 4 + wq;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float4 v = rbuf[((src * 2 + i) * 4 + r) * 64 + lane];
+        acc[i][J][4 * r] += v.x;
+        acc[i][J][4 * r + 1] += v.y;
+        acc[i][J][4 * r + 2] += v.z;
+        acc[i][J][4 * r + 3] += v.w;
+      }
+  };
+  if (grp == 0) post(std::integral_constant<int, 1>{});
+  else post(std::integral_constant<int, 0>{});
+  __syncthreads();
+  if (grp == 0) take(std::integral_constant<int, 0>{});
+  else take(std::integral_constant<int, 1>{});
+  __syncthreads();
+  gemm_epilogue(a, acc, row0, col0, bn, logical, reinterpret_cast<float*>(&lds[0][0][0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -534,8 +579,8 @@ void launch_dense_operand(int n, int Lp, const float* x, const float* u, uint16_
 void launch_dense_operand32(int n, int n8, int Lp, const float* x, const float* u, float* bout, hipStream_t s);
 void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
   dim3 grid((a.n + GBM - 1) / GBM, (a.Lp + GBN - 1) / GBN);
-  if (bf16) hipLaunchKernelGGL(k_gemm_lds<false>, grid, dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_gemm_lds<true>, grid, dim3(256), 0, s, a);
+  if (bf16) hipLaunchKernelGGL(k_gemm_lds<false>, grid, dim3(512), 0, s, a);
+  else hipLaunchKernelGGL(k_gemm_lds<true>, grid, dim3(512), 0, s, a);
 }
 int gemm_col_tiles(int Lp) { return (Lp + GBN - 1) / GBN; }
 __global__ void k_dense_operand32(int n, int Lp, const float* __restrict__ x, const float* __restrict__ u,
