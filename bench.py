@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "41d4e0427c2784fd1a9c5dab99896743ee2d3de0668a5ec2139e23aa7f4c4a5f",
-                "fetch_kib": 2423.142, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "93ce95139aaec1b738458132efa7990a572043e11877c26c05ded5fd00750f0a",
+                "fetch_kib": 2422.620, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
