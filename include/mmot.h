@@ -38,7 +38,7 @@ extern "C" {
 
 typedef enum mmot_status {
   MMOT_OK = 0,
-  MMOT_EINVAL = 1,        /* bad sizes, eps, NaN/negative data, unsorted CSR, unequal masses */
+  MMOT_EINVAL = 1,        /* bad sizes, eps, NaN/negative data, unsorted CSR, unequal or zero masses */
   MMOT_ENOMEM = 2,        /* workspace smaller than mmot_query_workspace reported */
   MMOT_EINFEASIBLE = 3,   /* a positive source/sink entry faces a zero message (Theorem 4 support) */
   MMOT_ENUMERIC = 4,      /* non-finite values appeared (range exceeded in the scaled domain) */
@@ -63,7 +63,8 @@ enum { MMOT_DOMAIN_AUTO = 0, MMOT_DOMAIN_SCALED = 1, MMOT_DOMAIN_LOG = 2 };
  * or NULL (K_L = 1).  cap: n values (cap_per_step = 0, same at every interior
  * time) or (T-1) x n (cap_per_step = 1); +INF = uncapacitated; must be > 0.
  * src = R^(0,1), dst = R^(0,TT): L x n, >= 0, each commodity's row sums equal
- * (relative 1e-9). */
+ * (relative 1e-9) and positive (a commodity without mass is rejected: drop it
+ * from the problem instead). */
 typedef struct mmot_problem {
   int32_t n, L, T;
   double eps;

@@ -43,6 +43,11 @@ def test_bad_data_is_rejected():
     _expect(dataclasses.replace(b, src=src), _lib.MMOT_EINVAL)                       # negative mass
     dst = b.dst.copy(); dst[1] *= 1.5
     _expect(dataclasses.replace(b, dst=dst), _lib.MMOT_EINVAL)                       # unequal masses
+    src, dst = b.src.copy(), b.dst.copy(); src[2] = 0.0; dst[2] = 0.0
+    _expect(dataclasses.replace(b, src=src, dst=dst), _lib.MMOT_EINVAL)              # a commodity without mass
+    d = instances.dense_blob_instance(n=64, L=8, T=4, seed=1)
+    src, dst = d.src.copy(), d.dst.copy(); src[3] = 0.0; dst[3] = 0.0
+    _expect(dataclasses.replace(d, src=src, dst=dst), _lib.MMOT_EINVAL)              # (dense as well)
     cost = b.cost.copy(); cost[3] = np.nan
     _expect(dataclasses.replace(b, cost=cost), _lib.MMOT_EINVAL)                     # NaN cost
     cap = b.cap_full(); cap[0, 0] = 0.0

@@ -6,6 +6,8 @@ per-commodity marginals P_{0,t}, edge flows) are unique functions of the
 scalings, so they are compared element by element (relative L1).
 Tolerances: FP64 instantiation 1e-12; FP32 1e-5 (flows, marginals).
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -125,6 +127,20 @@ def test_ragged_shapes(L, T, n):
         for dom in ("scaled", "log"):
             g = gpu_outputs(inst, 8, prec, dom)
             compare(g, o, tol)
+
+
+def test_single_state():
+    """The degenerate network of one state with a waiting move: every commodity
+    stays put, the capacity binds at every interior time or not at all."""
+    inst = instances.Instance(name="single", n=1, L=2, T=3, eps=0.1, kind="csr",
+                              src=np.array([[1.0], [2.0]]), dst=np.array([[1.0], [2.0]]), cap=np.array([5.0]),
+                              rowptr=np.array([0, 1], dtype=np.int32), colidx=np.array([0], dtype=np.int32),
+                              cost=np.array([0.1]))
+    o = oracle_outputs(inst, 5)
+    assert np.allclose(o["Pt"], 3.0)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        for dom in ("scaled", "log"):
+            compare(gpu_outputs(inst, 5, prec, dom), o, tol)
 
 
 def test_state_costs_and_per_step_capacity():
@@ -454,7 +470,6 @@ def _with_comm_caps(inst, seed, frac=0.3, ratio=0.6, zero_frac=0.01, per_step=Tr
     go), D = ratio times that mass; and a few zero bounds that close a lightly
     used state to one commodity (never its own source or sink).  per_step=False
     keeps the bounds drawn for the middle time, as one (L, n) bound for all times."""
-    import dataclasses
     rng = np.random.default_rng(seed)
     p = to_oracle(inst)
     if log:
