@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "93ce95139aaec1b738458132efa7990a572043e11877c26c05ded5fd00750f0a",
-                "fetch_kib": 2422.620, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "ad43efe711293d1e992e425ad14364aa01f86dedb987fff009ef85709d3fe792",
+                "fetch_kib": 2420.636, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 

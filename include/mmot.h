@@ -170,6 +170,16 @@ mmot_status mmot_stats_now(mmot_solver* s, mmot_stats* stats_host);
  * Asynchronous (device outputs). */
 mmot_status mmot_occupancy(mmot_solver* s, double* occ, double* per_comm);
 
+/* The same for a window of commodities (a full P_{0,t} of a large problem is
+ * (T+1) x L x n doubles; the window pages through it): occ as above;
+ * per_comm[(T+1) * comm_count * n] = P_{0,t} of commodities comm_first ..
+ * comm_first + comm_count - 1 (index (t*comm_count + k)*n + i for commodity
+ * comm_first + k), optional (NULL: comm_first and comm_count are ignored).
+ * MMOT_EINVAL unless 0 <= comm_first and 1 <= comm_count <= L - comm_first.
+ * Asynchronous (device outputs). */
+mmot_status mmot_occupancy_window(mmot_solver* s, double* occ, double* per_comm, int32_t comm_first,
+                                  int32_t comm_count);
+
 /* Aggregate edge flows (bi-marginal projections P_{t,t+1} summed over
  * commodities, eq. proj_discrete_bi): flow[t * nnz + e] = mass moving along
  * CSR entry e between times t and t+1, t = 0..T-1.  CSR problems only

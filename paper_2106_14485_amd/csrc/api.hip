@@ -43,7 +43,7 @@ void launch_source(int, int, int, int, const V*, const V*, V*, uint32_t*, int, s
                    size_t, int, hipStream_t);
 template <typename V, bool LOG>
 void launch_check0(int, int, int, int, int, const V*, const V*, const V*, const double*, const double*, double*,
-                   double*, double*, int, hipStream_t);
+                   double*, double*, int, int, int, hipStream_t);
 template <typename V, bool LOG>
 void launch_flows(int, int, int, int, int, const int*, const int*, const V*, const double*, const V*, const V*,
                   const V*, const V*, const double*, const double*, double*, double*, int, hipStream_t);
@@ -64,7 +64,8 @@ void launch_dense_rows(int, int, const float*, const float*, float*, int, double
                        float*, int, int,
                        int, hipStream_t);
 void launch_dense_sink(int, int, int, const float*, const float*, float*, int, const double*, const double*,
-                       uint32_t*, int, uint32_t*, size_t, int*, double*, double*, double*, int, hipStream_t);
+                       uint32_t*, int, uint32_t*, size_t, int*, double*, double*, double*, int, int, int,
+                       hipStream_t);
 void launch_dense_gibbs(const double*, int, int, double, float*, float*, void*, void*, hipStream_t);
 void launch_dense_operand(int, int, const float*, const float*, uint16_t*, hipStream_t);
 void launch_dense_operand32(int, int, int, const float*, const float*, float*, hipStream_t);
@@ -158,6 +159,8 @@ struct mmot_solver {
   uint16_t* Bbuf[2] = {nullptr, nullptr};   // BF16 products: next operand, u-scaled, k-blocked (rows padded to 64)
   float* B32buf[2] = {nullptr, nullptr};     // FP32 products: the same in FP32, 32-row interleaved blocks
   int n8 = 0;
+  // per-commodity output window of the output pass: commodities pc_lo .. pc_lo + pc_cnt - 1
+  int pc_lo = 0, pc_cnt = 0;
   // ELL copies of the operators (row width ellD, 0 = use CSR)
   int ellD = 0;
   int *ell_ci_b = nullptr, *ell_ci_f = nullptr, *deg_b = nullptr, *deg_f = nullptr, *maxdeg = nullptr;
@@ -402,7 +405,9 @@ struct Impl {
       g.slots = (mode == 0 && calib) ? s->slots_f + (size_t)to * Lp : nullptr;
       if (mode == 1) {
         g.ucur = reinterpret_cast<const float*>(uat(s, to));
-        g.pcomm = pcomm ? pcomm + (size_t)to * s->L * s->n : nullptr;
+        g.pcomm = pcomm ? pcomm + (size_t)to * s->pc_cnt * s->n : nullptr;
+        g.pc_lo = s->pc_lo;
+        g.pc_cnt = s->pc_cnt;
       }
       launch_gemm(g, s->dense_bf16, st);
       launch_dense_rows(s->n, s->ntn, s->part_s, reinterpret_cast<const float*>(static_cast<V*>(s->cap) + (size_t)(to - 1) * s->n),
@@ -420,7 +425,8 @@ struct Impl {
                         (mode == 0 && calib) ? s->slots_f + (size_t)T * Lp : nullptr, (size_t)(T + 1) * Lp, s->flags,
                         mode == 1 ? s->part + (size_t)T * pstride : nullptr,
                         (mode == 1 && occ) ? occ + (size_t)T * s->n : nullptr,
-                        (mode == 1 && pcomm) ? pcomm + (size_t)T * s->L * s->n : nullptr, s->nblk, st);
+                        (mode == 1 && pcomm) ? pcomm + (size_t)T * s->pc_cnt * s->n : nullptr, s->pc_lo, s->pc_cnt,
+                        s->nblk, st);
     }
   }
 
@@ -482,7 +488,9 @@ struct Impl {
     if (mode == 1) {
       a.part = s->part + (size_t)to * pstride;
       a.occ = occ ? occ + (size_t)to * s->n : nullptr;
-      a.pcomm = pcomm ? pcomm + (size_t)to * s->L * s->n : nullptr;
+      a.pcomm = pcomm ? pcomm + (size_t)to * s->pc_cnt * s->n : nullptr;
+      a.pc_lo = s->pc_lo;
+      a.pc_cnt = s->pc_cnt;
     }
     if (to < T) {
       a.epi = 1;
@@ -544,7 +552,8 @@ struct Impl {
                             static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, s->lvl0, s->slotsS, s->nslot, st);
     if (mode == 1) {
       launch_check0<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->U01),
-                            static_cast<const V*>(s->R01), s->sigf, s->sigb, s->part, occ, pcomm, s->nblk, st);
+                            static_cast<const V*>(s->R01), s->sigf, s->sigb, s->part, occ, pcomm, s->pc_lo,
+                            s->pc_cnt, s->nblk, st);
     }
     if (s->kind == MMOT_DENSE && s->dense_bf16)
       launch_dense_operand(s->n, s->Lp, static_cast<const float*>(s->U01), nullptr, bbuf(s, 0), st);
@@ -987,9 +996,18 @@ mmot_status mmot_set_precision(mmot_solver* s, int32_t precision) {
   return MMOT_OK;
 }
 
-mmot_status mmot_occupancy(mmot_solver* s, double* occ, double* per_comm) {
+mmot_status mmot_occupancy_window(mmot_solver* s, double* occ, double* per_comm, int32_t comm_first,
+                                  int32_t comm_count) {
   if (!s || !occ) return MMOT_EINVAL;
+  if (per_comm && (comm_first < 0 || comm_count < 1 || comm_first > s->L - comm_count)) return MMOT_EINVAL;
+  s->pc_lo = per_comm ? comm_first : 0;
+  s->pc_cnt = per_comm ? comm_count : 0;
   return check_pass(s, occ, per_comm, nullptr);
+}
+
+mmot_status mmot_occupancy(mmot_solver* s, double* occ, double* per_comm) {
+  if (!s) return MMOT_EINVAL;
+  return mmot_occupancy_window(s, occ, per_comm, 0, s->L);
 }
 
 mmot_status mmot_edge_flows(mmot_solver* s, double* flow, double* cost_host) {

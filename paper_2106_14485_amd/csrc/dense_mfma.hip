@@ -93,9 +93,9 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2
         if (ok) a.out[off] = z;
         if (ok && z > 0.f) colmax[j] = fmaxf(colmax[j], z);
         if (ok && capc) rsum[i][r] = fmaf(o * wv[r], g, rsum[i][r]);
-        if (a.pcomm && ok && capc) {
+        if (a.pcomm && ok && capc && (unsigned)(gc - a.pc_lo) < (unsigned)a.pc_cnt) {
           const double P = (double)o * (double)wv[r] * (double)g * (double)a.ucur[gr];
-          a.pcomm[(size_t)gc * a.n + gr] = P;
+          a.pcomm[(size_t)(gc - a.pc_lo) * a.n + gr] = P;
         }
       }
       if (a.bout && cok) {
@@ -469,7 +469,8 @@ __global__ void k_dense_operand(int n, int Lp, const float* __restrict__ x, cons
 __global__ void k_dense_sink(int n, int Lp, int L, const float* __restrict__ hat, const float* __restrict__ rdst,
                              float* __restrict__ u0t, int update, const double* __restrict__ sigT,
                              const double* __restrict__ sighT, uint32_t* slotsE, int nslot, uint32_t* slots_o,
-                             size_t stride_o, int* flags, double* part, double* occ, double* pcomm) {
+                             size_t stride_o, int* flags, double* part, double* occ, double* pcomm, int pc_lo,
+                             int pc_cnt) {
   double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
   const int per = (n + gridDim.x - 1) / gridDim.x;
   const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
@@ -495,7 +496,7 @@ __global__ void k_dense_sink(int n, int Lp, int L, const float* __restrict__ hat
         st[ST_MASS] += P;
         st[ST_DUAL] += (double)r * lnU;
         st[ST_GAP] += lnU * (P - (double)r);
-        if (pcomm) pcomm[(size_t)l * n + j] = P;
+        if (pcomm && (unsigned)(l - pc_lo) < (unsigned)pc_cnt) pcomm[(size_t)(l - pc_lo) * n + j] = P;
       }
     }
     if (update && r1 > r0) {
@@ -648,10 +649,10 @@ void launch_dense_operand(int n, int Lp, const float* x, const float* u, uint16_
 }
 void launch_dense_sink(int n, int Lp, int L, const float* hat, const float* rdst, float* u0t, int update,
                        const double* sigT, const double* sighT, uint32_t* slotsE, int nslot, uint32_t* slots_o,
-                       size_t stride_o, int* flags, double* part, double* occ, double* pcomm, int nblk,
-                       hipStream_t s) {
+                       size_t stride_o, int* flags, double* part, double* occ, double* pcomm, int pc_lo,
+                       int pc_cnt, int nblk, hipStream_t s) {
   hipLaunchKernelGGL(k_dense_sink, dim3(nblk), dim3(256), 0, s, n, Lp, L, hat, rdst, u0t, update, sigT, sighT,
-                     slotsE, nslot, slots_o, stride_o, flags, part, occ, pcomm);
+                     slotsE, nslot, slots_o, stride_o, flags, part, occ, pcomm, pc_lo, pc_cnt);
 }
 void launch_dense_gibbs(const double* C, int n, int lda, double eps, float* K, float* Kt, void* Kb, void* Ktb,
                         hipStream_t s) {

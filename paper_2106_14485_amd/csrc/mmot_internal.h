@@ -85,7 +85,8 @@ struct StepArgs {
   double* part;         // [nblk][kNSt] stats partials of this time (nullptr = no stats)
   int tout;             // output time (for per-commodity output)
   double* occ;          // [n] occupancy at the output time (output pass), nullptr = none
-  double* pcomm;        // [L][n] per-commodity marginal at the output time, nullptr = none
+  double* pcomm;        // [pc_cnt][n] per-commodity marginal at the output time, nullptr = none
+  int pc_lo, pc_cnt;    // commodities pc_lo .. pc_lo + pc_cnt - 1 go to pcomm (row l - pc_lo)
 };
 
 // source update U01 = R01 ./ Psi_1 (row kernel)
@@ -113,7 +114,8 @@ struct Check0Args {
   const double* sigb0;
   double* part;
   double* occ;
-  double* pcomm;
+  double* pcomm;        // [pc_cnt][n], commodities pc_lo .. pc_lo + pc_cnt - 1
+  int pc_lo, pc_cnt;
 };
 template <typename V>
 struct PrepBwdArgs {
@@ -193,7 +195,8 @@ struct GemmArgs {
   const float* wgt;     // [Lp]
   float* part_s;        // [nTN][n] partial column sums
   const float* ucur;    // check pass: u at the output time (per-commodity output)
-  double* pcomm;        // check pass: [L][n] per-commodity marginal, nullptr = none
+  double* pcomm;        // check pass: [pc_cnt][n] per-commodity marginal, nullptr = none
+  int pc_lo, pc_cnt;    // (commodities pc_lo .. pc_lo + pc_cnt - 1)
   uint32_t* slots;      // column levels of the stored output, nullptr = off
   int nslot;
   size_t slot_stride;

@@ -444,7 +444,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             st[ST_DUAL] += R * lnU;
             st[ST_GAP] += lnU * (P - R);
             occ_row += P;
-            if (a.pcomm) a.pcomm[(size_t)l * a.n + row] = P;
+            if (a.pcomm && (unsigned)(l - a.pc_lo) < (unsigned)a.pc_cnt) a.pcomm[(size_t)(l - a.pc_lo) * a.n + row] = P;
           }
         }
       } else {
@@ -514,7 +514,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
             double P = LOG ? ((o[v] == ninf<V>() || w[v] == ninf<V>()) ? 0.0
                                 : exp2((double)o[v] + (double)w[v] + (double)g[v] + (double)ur))
                            : (double)o[v] * (double)w[v] * (double)g[v] * (double)ur;
-            if (a.pcomm) a.pcomm[(size_t)l * a.n + row] = P;
+            if (a.pcomm && (unsigned)(l - a.pc_lo) < (unsigned)a.pc_cnt) a.pcomm[(size_t)(l - a.pc_lo) * a.n + row] = P;
             if (a.kl && P > 0.0) {
               const double cl = LOG ? -(double)k[v] * a.eps * M_LN2 : -a.eps * log((double)k[v]);
               st[ST_SCOST] += P * cl;
@@ -737,7 +737,7 @@ __device__ __forceinline__ void check0_body(const Check0Args<V>& A, int bid, int
       st[ST_GAP] += lnU * (P - R);
       if (!isfinite(P)) st[ST_NONFINITE] += 1.0;
       occ_row += P;
-      if (pcomm) pcomm[(size_t)l * n + row] = P;
+      if (pcomm && (unsigned)(l - A.pc_lo) < (unsigned)A.pc_cnt) pcomm[(size_t)(l - A.pc_lo) * n + row] = P;
     }
   }
   if (occ) {
@@ -1163,9 +1163,9 @@ void launch_source(int n, int Lp, int G, int nchunk, const V* psi0, const V* rsr
 }
 template <typename V, bool LOG>
 void launch_check0(int n, int Lp, int L, int G, int nchunk, const V* psi0, const V* u01, const V* rsrc,
-                   const double* sigf0, const double* sigb0, double* part, double* occ, double* pcomm, int nblk,
-                   hipStream_t s) {
-  const Check0Args<V> A{n, Lp, L, G, nchunk, psi0, u01, rsrc, sigf0, sigb0, part, occ, pcomm};
+                   const double* sigf0, const double* sigb0, double* part, double* occ, double* pcomm, int pc_lo,
+                   int pc_cnt, int nblk, hipStream_t s) {
+  const Check0Args<V> A{n, Lp, L, G, nchunk, psi0, u01, rsrc, sigf0, sigb0, part, occ, pcomm, pc_lo, pc_cnt};
   if (record_item(IK_CHECK0, LOG, nblk, &A, sizeof(A))) return;
   hipLaunchKernelGGL((k_check0<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, A);
 }
@@ -1332,7 +1332,7 @@ bool pool_item_is_light(const PoolItem& it) {
   template void launch_source<V, LOG>(int, int, int, int, const V*, const V*, V*, uint32_t*, int, size_t, int*,   \
                                       unsigned long long*, int, size_t, int, hipStream_t);                        \
   template void launch_check0<V, LOG>(int, int, int, int, int, const V*, const V*, const V*, const double*,      \
-                                      const double*, double*, double*, double*, int, hipStream_t);               \
+                                      const double*, double*, double*, double*, int, int, int, hipStream_t);     \
   template void launch_flows<V, LOG>(int, int, int, int, int, const int*, const int*, const V*, const double*,   \
                                      const V*, const V*, const V*, const V*, const double*, const double*,       \
                                      double*, double*, int, hipStream_t);                                        \

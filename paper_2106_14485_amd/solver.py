@@ -117,11 +117,18 @@ class Solver:
         return int(_lib.lib().mmot_iterations(self._h))
 
     # -- outputs ---------------------------------------------------------
-    def occupancy(self, per_commodity: bool = False):
+    def occupancy(self, per_commodity: bool = False, commodities=None):
+        """Occupancy P_t, (T+1) x n; with per_commodity also P_{0,t}, (T+1) x L x n, or
+        for commodities = (first, count) only that window, (T+1) x count x n."""
         occ = torch.empty((self.T + 1, self.n), dtype=torch.float64, device=self.device)
-        pc = torch.empty((self.T + 1, self.L, self.n), dtype=torch.float64, device=self.device) if per_commodity else None
-        check(_lib.lib().mmot_occupancy(self._h, _ptr(occ), _ptr(pc)), "mmot_occupancy")
-        return (occ, pc) if per_commodity else occ
+        if not per_commodity:
+            check(_lib.lib().mmot_occupancy(self._h, _ptr(occ), None), "mmot_occupancy")
+            return occ
+        first, count = (0, self.L) if commodities is None else (int(commodities[0]), int(commodities[1]))
+        # (one row at least, so that an empty window reaches the library and is rejected there)
+        pc = torch.empty((self.T + 1, max(count, 1), self.n), dtype=torch.float64, device=self.device)
+        check(_lib.lib().mmot_occupancy_window(self._h, _ptr(occ), _ptr(pc), first, count), "mmot_occupancy_window")
+        return occ, pc
 
     def edge_flows(self):
         flow = torch.empty((self.T, self.nnz), dtype=torch.float64, device=self.device)

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import alg2
-from paper_2106_14485_amd import instances
+from paper_2106_14485_amd import _lib, instances
 from tests.helpers import fp32_log_floor, rel_l1, to_oracle
 
 pytestmark = pytest.mark.gpu
@@ -141,6 +141,30 @@ def test_single_state():
     for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
         for dom in ("scaled", "log"):
             compare(gpu_outputs(inst, 5, prec, dom), o, tol)
+
+
+@pytest.mark.parametrize("kind", ["sparse_fp32_log", "sparse_fp64_scaled", "dense_fp32"])
+def test_per_commodity_window(kind):
+    """mmot_occupancy_window: the per-commodity marginals of a window of commodities
+    are the same rows of the full output (bitwise: the same arithmetic), the
+    occupancy is unchanged, and windows outside [0, L) are rejected (EINVAL)."""
+    if kind == "dense_fp32":
+        inst, prec, dom = instances.dense_blob_instance(n=130, L=40, T=5, seed=2), "fp32", "auto"
+    else:
+        inst = instances.rgg_instance(n=300, L=37, T=8, seed=4)
+        prec, dom = ("fp32", "log") if kind == "sparse_fp32_log" else ("fp64", "scaled")
+    S = _solver()(inst, precision=prec, domain=dom)
+    S.iterate(6)
+    occ, full = S.occupancy(per_commodity=True)
+    for first, count in ((0, 1), (5, 13), (inst.L - 7, 7)):
+        o2, w = S.occupancy(per_commodity=True, commodities=(first, count))
+        assert torch.equal(o2, occ)
+        assert torch.equal(w, full[:, first:first + count, :])
+    for bad in ((-1, 3), (0, 0), (inst.L - 2, 3)):
+        with pytest.raises(_lib.MmotError) as e:
+            S.occupancy(per_commodity=True, commodities=bad)
+        assert e.value.status == _lib.MMOT_EINVAL
+    S.close()
 
 
 def test_state_costs_and_per_step_capacity():
