@@ -44,12 +44,12 @@ __host__ __device__ __forceinline__ int ipos32(int k) { return (k & ~31) | ((k &
 // (2 x 2 over the tile) hold the whole sum; group g handles the 32-column half
 // j = g of its wave's 64 x 64 quadrant.  smem: LDS that no wave reads any more
 // (the operand ring), 2 * 256 + 2 * GBN floats.
-constexpr int NG = 2;
+constexpr int kWaveGroups = 2;
 __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2][2], int row0, int col0, int bn,
                                               int logical, float* smem) {
   // red[g][wm][wn][64]: capacity partial sums across the column waves (and groups)
   float (*red)[2][2][64] = reinterpret_cast<float (*)[2][2][64]>(smem);
-  float (*cmx)[GBN] = reinterpret_cast<float (*)[GBN]>(smem + NG * 2 * 2 * 64);   // column maxima
+  float (*cmx)[GBN] = reinterpret_cast<float (*)[GBN]>(smem + kWaveGroups * 2 * 2 * 64);   // column maxima
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = wave >> 2, wq = wave & 3;
   const int wm = wq >> 1, wn = wq & 1;
