@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "fe8f3358d8a678c67d68de187f719d90e5cbbadf81978de340a0e03e810d01ff",
-                "fetch_kib": 2420.609, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "600bcb8ce6241d9ed29d657e1bbd08bf603e2425bac39b2c5fb2591f13d0e028",
+                "fetch_kib": 2424.548, "write_kib": 2096.924, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 

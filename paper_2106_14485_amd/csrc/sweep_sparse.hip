@@ -227,8 +227,10 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   double occ_row = 0.0;             // sink / output: occupancy of this row
   // commodity capacities: w_t, projected before u_t with the u_t of the last sweep
   constexpr bool comm = CM;
+  // (the update-free pass reads u only where it outputs per-commodity terms, below:
+  // a load here would be waited for with everything issued before it)
   V ucur = LOG ? V(0) : V(1);
-  if (FWD && a.epi == 1 && (CHK || comm)) ucur = a.uout[rowc];
+  if (FWD && a.epi == 1 && comm) ucur = a.uout[rowc];
 
   for (int ch = 0; ch < a.nchunk; ++ch) {
     const int col = (ch * G + gl) * NV;
@@ -517,7 +519,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
           // update-free pass: u is final, P_{0,t} = hatPsi (.) Psi (.) K_L w_t u_t (eq. proj_0t);
           // with state costs also accumulate <C_L, P_{0,t}> (cost tensor, eq. cost_multicommodity);
           // with commodity capacities their violation, dual term and gap term
-          const V ur = ucur;
+          const V ur = comm ? ucur : a.uout[rowc];
           V k[NV];
           if (a.kl) vld(a.kl + row * Lp + col, k);
 #pragma unroll
