@@ -50,3 +50,7 @@ def test_host_only_entry_points():
     p.eps = 0.05
     p.T = 0
     assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_EINVAL
+    # entry points given no solver reject the call without touching the device
+    assert L.mmot_occupancy(None, None, None) == _lib.MMOT_EINVAL
+    assert L.mmot_occupancy_window(None, None, None, 0, 1) == _lib.MMOT_EINVAL
+    assert L.mmot_edge_flows(None, None, None) == _lib.MMOT_EINVAL
