@@ -367,6 +367,29 @@ __global__ __launch_bounds__(512) void k_gemm_lds(GemmArgs a) {
 // ---------------------------------------------------------------------------
 // row kernels of the dense path
 // ---------------------------------------------------------------------------
+// The block's statistics partial: each of the kNSt values summed (the capacity
+// violation maximised) over the 256 threads, within each wave by shuffles, then
+// over the four waves in order; thread k writes part[block][k].
+__device__ __forceinline__ void block_partials(const double (&st)[kNSt], double* part) {
+  __shared__ double red[4][kNSt];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < kNSt; ++k) {
+    double v = st[k];
+    for (int m = 32; m > 0; m >>= 1) {
+      const double o = __shfl_xor(v, m, 64);
+      v = (k == ST_CAP_VIOL) ? fmax(v, o) : v + o;
+    }
+    if (lane == 0) red[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kNSt) {
+    const int k = threadIdx.x;
+    double v = red[0][k];
+    for (int w = 1; w < 4; ++w) v = (k == ST_CAP_VIOL) ? fmax(v, red[w][k]) : v + red[w][k];
+    part[(size_t)blockIdx.x * kNSt + k] = v;
+  }
+}
 // capacity update (Corollary 1 + Proposition 1) from the column-tile partial
 // sums: s_j = sum_p part_s[p][j]; update: u_j = 1 if s_j <= d_j else d_j / s_j;
 // check: occupancy u_j s_j and the capacity / dual / gap statistics.
@@ -393,18 +416,7 @@ __global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, c
       if (occ) occ[j] = occv;
     }
   }
-  if (part) {
-    __shared__ double red[256][kNSt];
-#pragma unroll
-    for (int k = 0; k < kNSt; ++k) red[threadIdx.x][k] = st[k];
-    __syncthreads();
-    if (threadIdx.x < kNSt) {
-      const int k = threadIdx.x;
-      double v = red[0][k];
-      for (int i = 1; i < (int)blockDim.x; ++i) v = (k == ST_CAP_VIOL) ? fmax(v, red[i][k]) : v + red[i][k];
-      part[(size_t)blockIdx.x * kNSt + k] = v;
-    }
-  }
+  if (part) block_partials(st, part);
 }
 
 // The capacity update of the R rows r0.. (as in k_dense_rows, same order of the
@@ -515,18 +527,7 @@ __global__ void k_dense_sink(int n, int Lp, int L, const float* __restrict__ hat
       if (lane == 0) occ[j] = s;
     }
   }
-  if (part) {
-    __shared__ double red[256][kNSt];
-#pragma unroll
-    for (int k = 0; k < kNSt; ++k) red[threadIdx.x][k] = st[k];
-    __syncthreads();
-    if (threadIdx.x < kNSt) {
-      const int k = threadIdx.x;
-      double v = red[0][k];
-      for (int i = 1; i < (int)blockDim.x; ++i) v = (k == ST_CAP_VIOL) ? fmax(v, red[i][k]) : v + red[i][k];
-      part[(size_t)blockIdx.x * kNSt + k] = v;
-    }
-  }
+  if (part) block_partials(st, part);
 }
 
 // ---------------------------------------------------------------------------
