@@ -50,7 +50,7 @@ def rel_l1(a, b):
     return float(np.abs(a - b).sum() / (den if den > 0 else 1.0))
 
 
-def fp32_log_floor(proj, T):
+def fp32_log_floor(proj, T, per_commodity=False):
     """Precision floor of an FP32 log-domain solve, from the oracle's log messages.
 
     The GPU log domain stores log2-messages relative to per-commodity offsets
@@ -61,10 +61,12 @@ def fp32_log_floor(proj, T):
     relative error u (g_b + g_f).  The plan-weighted mean of g_b + g_f over the
     interior times gives the first-order relative-L1 error of the marginals;
     the floor is four times it, covering the re-rounding along the T-step
-    recursions and the exp2 / log2 instruction errors.
+    recursions and the exp2 / log2 instruction errors.  per_commodity=True
+    returns the same figure for each commodity's own marginals (length L).
     """
     P, lpsi, lh = proj["P0t"], proj["lpsi"], proj["lpsihat"]
-    num = den = 0.0
+    L = P.shape[1]
+    num = np.zeros(L); den = np.zeros(L)
     for t in range(1, T):
         b, f = lpsi[t], lh[t]
         plan = np.where(np.isfinite(b) & np.isfinite(f), b + f, -np.inf)
@@ -74,6 +76,8 @@ def fp32_log_floor(proj, T):
         for m in (b, f):
             ref = m[rows, peak][:, None]
             gaps = gaps + np.where(np.isfinite(m) & np.isfinite(ref), np.abs(m - ref), 0.0)
-        num += float((P[t] * gaps).sum())
-        den += float(P[t].sum())
-    return 4.0 * 2.0 ** -24 * (num / den if den > 0 else 0.0)
+        num += (P[t] * gaps).sum(axis=1)
+        den += P[t].sum(axis=1)
+    if per_commodity:
+        return 4.0 * 2.0 ** -24 * np.where(den > 0, num / np.where(den > 0, den, 1.0), 0.0)
+    return 4.0 * 2.0 ** -24 * (num.sum() / den.sum() if den.sum() > 0 else 0.0)

@@ -42,12 +42,22 @@ def oracle_outputs(inst, n_iter, log=False):
         g = st.g
     rows = np.repeat(np.arange(inst.n), np.diff(inst.rowptr))
     flows = np.stack([np.asarray(f.tocsr()[rows, inst.colidx]).ravel() for f in out["flows"]])
-    return dict(Pt=out["Pt"], P0t=out["P0t"], flows=flows, cost=out["cost"], duals=duals, g=g, floor=floor)
+    floor_l = fp32_log_floor(out, inst.T, per_commodity=True) if log else np.zeros(inst.L)
+    return dict(Pt=out["Pt"], P0t=out["P0t"], flows=flows, cost=out["cost"], duals=duals, g=g, floor=floor,
+                floor_l=floor_l)
 
 
-def gpu_outputs(inst, n_iter, precision, domain, **kw):
+def gpu_outputs(inst, n_iter, precision, domain, chunks=None, **kw):
+    """chunks: run the iterations as S.iterate(k, stats=True) for each k (the
+    schedule of mmot_solve and bench.py, where each check pass's fresh backward
+    sweep stands in for the next chunk's first one) instead of one call."""
     S = _solver()(inst, precision=precision, domain=domain, **kw)
-    S.iterate(n_iter)
+    if chunks is None:
+        S.iterate(n_iter)
+    else:
+        assert sum(chunks) == n_iter
+        for k in chunks:
+            S.iterate(k, stats=True)
     st = S.stats()
     occ, pc = S.occupancy(per_commodity=True)
     flows, cost = S.edge_flows()
@@ -60,10 +70,29 @@ def gpu_outputs(inst, n_iter, precision, domain, **kw):
 
 
 def compare(g, o, tol, duals_tol=None):
+    """Aggregate relative L1 of occupancy, per-commodity marginals and edge flows,
+    and the same per commodity (each commodity's own P_{0,t}, all times) and per
+    time step (occupancy and flows of each step), so that one wrong commodity,
+    padding column or time step cannot hide in the aggregate.  For FP32
+    tolerances (>= 1e-5) a commodity's own bound is max(tol, 2 x its own
+    log-domain floor) and a time step's max(tol, 2 x the aggregate floor)."""
     assert rel_l1(g["Pt"], o["Pt"]) <= tol, ("occupancy", rel_l1(g["Pt"], o["Pt"]))
     assert rel_l1(g["P0t"], o["P0t"]) <= tol, ("per-commodity", rel_l1(g["P0t"], o["P0t"]))
     assert rel_l1(g["flows"], o["flows"]) <= tol, ("flows", rel_l1(g["flows"], o["flows"]))
     assert abs(g["cost"] - o["cost"]) <= tol * abs(o["cost"]), ("cost", g["cost"], o["cost"])
+    L = o["P0t"].shape[1]
+    fp32 = tol >= 1e-5          # FP32 tolerances may rest on the log-domain floor, FP64 ones never
+    tol_l = np.maximum(tol, 2.0 * o.get("floor_l", np.zeros(L))) if fp32 else np.full(L, tol)
+    for l in range(L):
+        e = rel_l1(g["P0t"][:, l, :], o["P0t"][:, l, :])
+        assert e <= tol_l[l], ("commodity", l, e, tol_l[l])
+    tol_t = max(tol, 2.0 * o.get("floor", 0.0)) if fp32 else tol
+    for t in range(o["Pt"].shape[0]):
+        e = rel_l1(g["Pt"][t], o["Pt"][t])
+        assert e <= tol_t, ("occupancy at time", t, e)
+    for t in range(o["flows"].shape[0]):
+        e = rel_l1(g["flows"][t], o["flows"][t])
+        assert e <= tol_t, ("flows at step", t, e)
     if duals_tol is not None:
         for a, b in zip(g["duals"], o["duals"]):
             fin = np.isfinite(b)
@@ -186,6 +215,18 @@ def test_rgg_full_size_fp32():
     g = gpu_outputs(inst, 10, "fp32", "auto")
     assert g["stats"]["domain"] == 1
     compare(g, o, 1e-5)
+
+
+def test_bench_schedule_matches_oracle():
+    """The benchmark workload under the benchmark's own schedule: three chunks of
+    ten iterations, each ended by the convergence check pass, against 30
+    oracle iterations."""
+    inst = instances.rgg_instance()
+    o = oracle_outputs(inst, 30)
+    g = gpu_outputs(inst, 30, "fp32", "auto", chunks=[10, 10, 10])
+    assert g["stats"]["domain"] == 1 and g["iters"] == 30
+    compare(g, o, 1e-5)
+    assert abs(g["stats"]["dual_obj"] - o["g"][-1]) <= 1e-5 * abs(o["g"][-1])
 
 
 def test_deterministic_repeat():
@@ -367,6 +408,55 @@ def test_road_grid_rows_of_several_chunks(L, domain):
     compare(g64, o, 1e-12, duals_tol=1e-8)
     g = gpu_outputs(inst, 8, "fp32", domain)
     compare(g, o, max(1e-5, o["floor"]))
+
+
+@pytest.mark.parametrize("side,L,T,chunks", [(12, 2000, 24, [1, 2]), (20, 64, 120, [3])])
+def test_road_grid_full_commodities_and_full_depth(side, L, T, chunks):
+    """The traffic-routing workload's two large dimensions at oracle-sized grids:
+    its 2000 commodities (rows of eight column chunks, the last one ragged:
+    2000 = 7 x 256 + 208) on a 12 x 12 grid, and its 120 time steps on a
+    20 x 20 grid; three iterations, iterate for iterate against the log-domain
+    oracle, at max(1e-5, FP32 log floor).  The first case runs the schedule of
+    mmot_solve (check passes between chunks)."""
+    inst = instances.road_grid_instance(side=side, L=L, T=T, eps=0.05, seed=side)
+    o = oracle_outputs(inst, 3, log=True)
+    g = gpu_outputs(inst, 3, "fp32", "auto", chunks=chunks)
+    assert g["stats"]["domain"] == 2
+    compare(g, o, max(1e-5, o["floor"]))
+
+
+def test_road_grid_full_size_first_sweep_sampled():
+    """At full size (100 x 100, L = 2000, T = 120) the first iteration's backward
+    sweep runs with u = 1, so each commodity's Psi_1 -- and U01 = R01 ./ Psi_1 --
+    is a per-commodity computation the log oracle does exactly for sampled
+    commodities.  FP32 log-domain rounding is at most 2^-24 of a stored value per
+    product, and the log-sum-exp is 1-Lipschitz, so the error of log Psi_1 is at
+    most 2 T 2^-24 times the commodity's message range (the spread of its finite
+    log-messages, which bounds a stored value relative to any offset inside it)."""
+    inst = instances.road_grid_instance()
+    sample = np.array([0, 331, 1000, 1517, 1999])
+    p = alg2.make_problem(inst.cost_csr(), inst.eps, inst.T, inst.src[sample], inst.dst[sample],
+                          np.full(inst.n, np.inf))
+    lst = alg2.iterate_log(p, alg2.initial_log_state(p), 1)
+    ref = lst.lU01
+    rng_l = np.zeros(len(sample))
+    for t in range(inst.T):
+        m = lst.lpsi[t]
+        fin = np.isfinite(m)
+        hi = np.where(fin, m, -np.inf).max(axis=1)
+        lo = np.where(fin, m, np.inf).min(axis=1)
+        rng_l = np.maximum(rng_l, np.where(np.isfinite(hi), hi - lo, 0.0))
+    tol = 2.0 * inst.T * 2.0 ** -24 * rng_l + 1e-9           # natural-log units, per commodity
+    S = _solver()(inst, precision="fp32", domain="auto")
+    S.iterate(1)
+    st = S.stats()
+    assert st["domain"] == 2
+    ls = S.log_duals()[0].cpu().numpy()[sample]
+    S.close()
+    fin = np.isfinite(ref)
+    assert np.array_equal(np.isfinite(ls), fin)
+    err = np.where(fin, np.abs(ls - np.where(fin, ref, 0.0)), 0.0).max(axis=1)
+    assert np.all(err <= tol), (err, tol)
 
 
 def test_road_grid_full_size_invariants():

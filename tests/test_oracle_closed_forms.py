@@ -64,3 +64,24 @@ def test_two_marginal_limit_is_diagonal_scaling():
     assert np.allclose(M.sum(1), a[0], rtol=1e-9, atol=0)
     assert np.allclose(M.sum(0), b[0], rtol=1e-12, atol=0)
     assert closed_forms.rank_one_residual(M, alg2.gibbs(p), None, None) < 1e-10
+
+
+def test_rank_one_residual_rejects_a_non_scaling():
+    """The residual is not blind: a matrix that is not diag(a) K diag(b) -- one
+    entry of a scaled kernel moved by a factor 1.5, or the kernel of another
+    cost -- leaves a misfit the row and column terms cannot absorb."""
+    rng = np.random.default_rng(3)
+    n = 6
+    C = rng.uniform(0, 1, (n, n))
+    C[rng.random((n, n)) < 0.3] = np.inf
+    np.fill_diagonal(C, 0.1)
+    K = np.exp(-C / 0.3)
+    a = rng.uniform(0.5, 2.0, n); b = rng.uniform(0.5, 2.0, n)
+    M = a[:, None] * K * b[None, :]
+    assert closed_forms.rank_one_residual(M, K, None, None) < 1e-12
+    bad = M.copy()
+    i, j = 2, 2                                   # a diagonal entry: its row and column hold others
+    bad[i, j] *= 1.5
+    assert closed_forms.rank_one_residual(bad, K, None, None) > 1e-3
+    other = a[:, None] * np.exp(-np.where(np.isfinite(C), C ** 2, np.inf) / 0.3) * b[None, :]
+    assert closed_forms.rank_one_residual(other, K, None, None) > 1e-3
