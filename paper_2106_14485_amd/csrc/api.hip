@@ -55,8 +55,8 @@ void launch_prep_fwd(int, int, int, const double*, double*, const double*, V*, V
 void launch_growth(double*, const float*, int, int, int, hipStream_t);
 void launch_levels(uint32_t*, float*, int, int, int, hipStream_t);
 void launch_levels64(unsigned long long*, uint32_t*, float*, int, int, int, int, hipStream_t);
-void launch_reduce_stats(const double*, int, int, double*, double, double*, hipStream_t);
-void launch_reduce_cost(const double*, const double*, int, int, double*, double*, double*, hipStream_t);
+void launch_reduce_stats(const double*, int, int, int, int, double*, double, double*, hipStream_t);
+void launch_reduce_cost(const double*, const double*, int, int, int, int, double*, double*, double*, hipStream_t);
 // dense_mfma.hip
 void launch_gemm(const GemmArgs&, bool, hipStream_t);
 int gemm_col_tiles(int);
@@ -126,6 +126,9 @@ struct mmot_solver {
   hipStream_t stream = nullptr;
   // geometry
   int vsize = 4, Lp = 0, G = 64, nchunk = 1, nblk = 8, nslot = 1;
+  // sparse sweep steps: 2^lwpr waves per whole-wave row, nblk_s blocks (>= nblk,
+  // the block count of the row kernels); stats partials are nblk_s apart per time
+  int lwpr = 0, nblk_s = 8;
   // device buffers (carved from the workspace)
   int *rp_b = nullptr, *ci_b = nullptr, *rp_f = nullptr, *ci_f = nullptr;
   int *cnt = nullptr, *cursor = nullptr, *srcpos = nullptr;
@@ -181,6 +184,7 @@ struct mmot_solver {
 namespace {
 
 int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
+constexpr int64_t kStepWaves = 2048;    // a sweep step of fewer waves (two per SIMD) splits its rows
 constexpr int kEllMax = 16;    // widest ELL row (one gather batch); wider graphs use CSR
 
 void set_geometry(mmot_solver* s) {
@@ -194,6 +198,19 @@ void set_geometry(mmot_solver* s) {
   int nblk = (s->n + rows_per_block - 1) / rows_per_block;
   nblk = (nblk + 7) / 8 * 8;
   s->nblk = nblk;
+  // Sweep steps with few rows of several column chunks (a few hundred states with
+  // hundreds of commodities) would leave most SIMDs idle with one wave per row,
+  // so whole-wave rows are split over two or four waves until the step has about
+  // two waves per SIMD.  Steps that already fill the GPU keep one wave per row:
+  // on the 10^4-row road grid, splitting its rows of eight chunks over two or
+  // four waves measured 1% and 3% slower (the per-row set-up and the commodity
+  // reduction are repeated per wave, and the per-chunk work does not change).
+  s->lwpr = 0;
+  if (s->kind == MMOT_CSR && s->G == 64) {
+    while (s->lwpr < 2 && (2 << s->lwpr) <= s->nchunk && (int64_t)s->n << s->lwpr < kStepWaves) ++s->lwpr;
+  }
+  const int rows_per_block_s = (kWaves >> s->lwpr) * (64 / s->G);
+  s->nblk_s = ((s->n + rows_per_block_s - 1) / rows_per_block_s + 7) / 8 * 8;
   s->nslot = std::max(1, std::min(32, nblk / 16));
   s->ncslot = std::min(s->nslot, 8);
   if (s->kind == MMOT_DENSE) {
@@ -252,9 +269,9 @@ void carve(mmot_solver* s, Carver& c) {
   s->levb = c.take<float>((T + 1) * Lp);
   s->levf = c.take<float>((T + 1) * Lp);
   s->rho = c.take<uint32_t>(2);
-  s->part = c.take<double>((T + 1) * (size_t)s->nblk * kNSt);
+  s->part = c.take<double>((T + 1) * (size_t)s->nblk_s * kNSt);
   s->tpart = c.take<double>((T + 1) * kNSt);
-  s->part_flow = c.take<double>((T + 1) * (size_t)s->nblk * kNSt);
+  s->part_flow = c.take<double>((T + 1) * (size_t)s->nblk_s * kNSt);
   s->tpart_flow = c.take<double>((T + 1) * kNSt);
   s->stats_dev = c.take<double>(8);
   s->masses = c.take<double>(s->L);
@@ -340,7 +357,7 @@ struct Impl {
   static StepArgs<V> base_args(mmot_solver* s) {
     StepArgs<V> a;
     std::memset(&a, 0, sizeof(a));
-    a.n = s->n; a.Lp = s->Lp; a.L = s->L; a.G = s->G; a.nchunk = s->nchunk;
+    a.n = s->n; a.Lp = s->Lp; a.L = s->L; a.G = s->G; a.nchunk = s->nchunk; a.lwpr = s->lwpr;
     a.eps = s->eps;
     a.nslot = s->nslot;
     a.nslot_stride = (size_t)(s->T + 1) * s->Lp;
@@ -389,7 +406,7 @@ struct Impl {
   // dense forward product t -> t+1 with its epilogue kernels
   static void dense_fwd(mmot_solver* s, int t, int mode, bool calib, double* occ, double* pcomm, hipStream_t st) {
     const int T = s->T, to = t + 1;
-    const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
+    const size_t Lp = s->Lp, pstride = (size_t)s->nblk_s * kNSt;
     GemmArgs g = gemm_base(s, true);
     if (s->dense_bf16) g.Bb = bbuf(s, t);
     else g.B32 = b32(s, t);
@@ -469,14 +486,14 @@ struct Impl {
       launch_dense_operand32(s->n, s->n8, s->Lp, static_cast<const float*>(s->U0T), nullptr, b32(s, T), st);
     for (int t = T - 1; t >= 0; --t) {
       if (s->kind == MMOT_DENSE) dense_bwd(s, t, calib, st);
-      else launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk, st);
+      else launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk_s, st);
     }
   }
 
   // forward product t -> t+1; mode 0 Sinkhorn update, mode 1 update-free pass
   static StepArgs<V> fwd_args(mmot_solver* s, int t, int mode, bool calib, double* occ, double* pcomm) {
     const int T = s->T;
-    const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
+    const size_t Lp = s->Lp, pstride = (size_t)s->nblk_s * kNSt;
     StepArgs<V> a = base_args(s);
     a.rp = s->rp_f; a.ci = s->ci_f; a.kv = kvat(s, s->kv_f, t);
     if (s->ellD) { a.ellD = s->ellD; a.ci = s->ell_ci_f; a.kv = static_cast<const V*>(s->ell_kv_f); }
@@ -561,7 +578,7 @@ struct Impl {
       launch_dense_operand32(s->n, s->n8, s->Lp, static_cast<const float*>(s->U01), nullptr, b32(s, 0), st);
     for (int t = 0; t < T; ++t) {
       if (s->kind == MMOT_DENSE) dense_fwd(s, t, mode, calib, occ, pcomm, st);
-      else launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), mode == 0 ? 1 : 2, s->nblk, st);
+      else launch_step<V, LOG>(fwd_args(s, t, mode, calib, occ, pcomm), mode == 0 ? 1 : 2, s->nblk_s, st);
     }
   }
 
@@ -592,7 +609,7 @@ struct Impl {
       } else {
         StepArgs<V> a = fwd ? fwd_args(s, t, 0, false, nullptr, nullptr) : bwd_args(s, t, false);
         if (fwd && a.epi == 1) { a.uout = reinterpret_cast<V*>(s->exc_row); a.cwo = nullptr; }
-        launch_step<V, LOG>(a, fwd, s->nblk, s->stream);
+        launch_step<V, LOG>(a, fwd, s->nblk_s, s->stream);
       }
     };
     HIPCK(hipEventRecord(e0, s->stream));
@@ -611,7 +628,7 @@ struct Impl {
   // and interleave the SDDMM at each time
   static void flows_pass(mmot_solver* s, double* flow, hipStream_t st) {
     const int T = s->T;
-    const size_t Lp = s->Lp, pstride = (size_t)s->nblk * kNSt;
+    const size_t Lp = s->Lp, pstride = (size_t)s->nblk_s * kNSt;
     launch_prep_fwd<V, LOG>(T, s->Lp, 1, s->cf, s->sigf, s->sigb, static_cast<V*>(s->facf),
                             static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, s->lvl0, s->slotsS, s->nslot, st);
     for (int t = 0; t < T; ++t) {
@@ -621,9 +638,10 @@ struct Impl {
                            s->cost + (s->steps_k > 1 ? (size_t)t * s->nnz : 0), xin, uat(s, t), (tb == T) ? static_cast<const V*>(s->U0T) : psi(s, tb),
                            uat(s, tb), s->sigf + (size_t)t * Lp, s->sigb + (size_t)tb * Lp,
                            flow + (size_t)t * s->nnz, s->part_flow + (size_t)t * pstride, s->nblk, st);
-      if (tb < T) launch_step<V, LOG>(fwd_args(s, t, 1, false, nullptr, nullptr), 2, s->nblk, st);
+      if (tb < T) launch_step<V, LOG>(fwd_args(s, t, 1, false, nullptr, nullptr), 2, s->nblk_s, st);
     }
-    launch_reduce_cost(s->part_flow, s->part, s->nblk, T, s->tpart_flow, s->tpart, s->stats_dev + 7, st);
+    launch_reduce_cost(s->part_flow, s->part, s->nblk, s->nblk_s, s->nblk_s, T, s->tpart_flow, s->tpart,
+                       s->stats_dev + 7, st);
   }
 
   static mmot_status setup(mmot_solver* s, const mmot_problem* p) {
@@ -801,7 +819,7 @@ void ensure_fresh(mmot_solver* s) {
 }
 
 mmot_status collect_stats(mmot_solver* s, mmot_stats* out) {
-  launch_reduce_stats(s->part, s->nblk, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
+  launch_reduce_stats(s->part, s->nblk, s->nblk_s, s->nblk_s, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
   HIPCK(hipMemcpyAsync(s->host_stats, s->stats_dev, 8 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
   mmot_status fs = read_flags(s);
   if (out) {
@@ -1184,7 +1202,7 @@ mmot_status pool_program(mmot_pool* P, mmot_pool::Req* r) {
   run_iterations(s, k);
   ensure_fresh(s);
   dispatch(s, [&](auto impl) { decltype(impl)::forward(s, 1, false, false, nullptr, nullptr, s->stream); return 0; });
-  launch_reduce_stats(s->part, s->nblk, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
+  launch_reduce_stats(s->part, s->nblk, s->nblk_s, s->nblk_s, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
   s->opt.use_graph = saved_graph;
   tl_recorder = nullptr;
   r->iters_planned += k;
@@ -1231,7 +1249,7 @@ mmot_status lane_chunk(mmot_pool::Req* r) {
   if (st != MMOT_OK) return st;
   st = check_pass(s, nullptr, nullptr, nullptr);
   if (st != MMOT_OK) return st;
-  launch_reduce_stats(s->part, s->nblk, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
+  launch_reduce_stats(s->part, s->nblk, s->nblk_s, s->nblk_s, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
   r->iters_planned += k;
   return pool_fetch_stats(r, s->stream);
 }

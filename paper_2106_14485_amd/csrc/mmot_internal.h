@@ -39,6 +39,7 @@ enum { FLAG_INFEASIBLE = 1, FLAG_NONFINITE = 2, FLAG_BADINPUT = 4, FLAG_BADCSR =
 template <typename V>
 struct StepArgs {
   int n, Lp, L, G, nchunk;
+  int lwpr;             // log2 of the waves sharing one whole-wave row (0, 1 or 2; 0 when G < 64)
   double eps;
   const int* rp;        // operator CSR (rows = output states); unused when ellD > 0
   const int* ci;        // CSR column indices, or ELL [n][ellD] (padding: index = row)
@@ -159,8 +160,9 @@ struct GrowthArgs {
   int T, Lp, dir;
 };
 struct Reduce1Args {
-  const double* part;
-  int nblk;
+  const double* part;   // [slot][stride][kNSt]
+  int nblk0, nblk;      // partials of slot 0 (the time-0 row kernel) and of the other slots
+  int stride;
   double* tpart;
 };
 struct Reduce2Args {

@@ -102,9 +102,12 @@ __device__ void block_stats(double (&st)[kNSt], double* part, int blk) {
 
 // Column maxima of a chunk of the stored panel -> encoded atomicMax into one
 // calibration slot.  cal holds, per lane, the value to calibrate on (the max
-// over this lane's rows; identity for invalid lanes).
+// over this lane's rows; identity for invalid lanes).  Chunk index: the block's
+// waves are in 2^lw sets (wave w in set w mod 2^lw); at loop step `it` set b
+// holds column chunk it * 2^lw + b of its rows, so the maxima are taken over
+// the waves of one set.
 template <typename V, bool LOG>
-__device__ void calib_chunk(const V (&val)[VT<V>::N], int G, int chunk_col0, int Lp, uint32_t* slot) {
+__device__ void calib_chunk(const V (&val)[VT<V>::N], int G, int it, int lw, int Lp, uint32_t* slot) {
   constexpr int NV = VT<V>::N;
   __shared__ float cm[kWaves][64 * 4];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -123,10 +126,11 @@ __device__ void calib_chunk(const V (&val)[VT<V>::N], int G, int chunk_col0, int
   }
   __syncthreads();
   const int ncol = G * NV;
-  for (int k = threadIdx.x; k < ncol; k += kBlock) {
-    float m = cm[0][k];
-    for (int w = 1; w < kWaves; ++w) m = fmaxf(m, cm[w][k]);
-    const int col = chunk_col0 + k;
+  for (int k = threadIdx.x; k < (ncol << lw); k += kBlock) {
+    const int b = k / ncol, kk = k - b * ncol;
+    float m = cm[b][kk];
+    for (int w = b + (1 << lw); w < kWaves; w += 1 << lw) m = fmaxf(m, cm[w][kk]);
+    const int col = ((it << lw) + b) * ncol + kk;
     if (col < Lp && m > -INFINITY) atomicMax(slot + col, enc_f32(m));
   }
   __syncthreads();
@@ -142,7 +146,7 @@ __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long x,
 // keeps the stored value at the state where the plan peaks.  Entries with a
 // non-finite plan level or value are skipped.
 template <typename V>
-__device__ void corr_chunk(const V (&pl)[VT<V>::N], const V (&val)[VT<V>::N], int G, int chunk_col0, int Lp,
+__device__ void corr_chunk(const V (&pl)[VT<V>::N], const V (&val)[VT<V>::N], int G, int it, int lw, int Lp,
                            unsigned long long* slot) {
   constexpr int NV = VT<V>::N;
   __shared__ unsigned long long ck[kWaves][64 * 4];
@@ -166,10 +170,11 @@ __device__ void corr_chunk(const V (&pl)[VT<V>::N], const V (&val)[VT<V>::N], in
   }
   __syncthreads();
   const int ncol = G * NV;
-  for (int k = threadIdx.x; k < ncol; k += kBlock) {
-    unsigned long long m = ck[0][k];
-    for (int w = 1; w < kWaves; ++w) m = ck[w][k] > m ? ck[w][k] : m;
-    const int col = chunk_col0 + k;
+  for (int k = threadIdx.x; k < (ncol << lw); k += kBlock) {
+    const int b = k / ncol, kk = k - b * ncol;
+    unsigned long long m = ck[b][kk];
+    for (int w = b + (1 << lw); w < kWaves; w += 1 << lw) m = ck[w][kk] > m ? ck[w][kk] : m;
+    const int col = ((it << lw) + b) * ncol + kk;
     if (col < Lp && m) atomicMax(slot + col, m);
   }
   __syncthreads();
@@ -189,7 +194,12 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   const int grp = lane / G, gl = lane & (G - 1);
   const int rpw = 64 / G;
   const int lb = xcd_block(bid, nblk);
-  const int row = (lb * kWaves + wave) * rpw + grp;
+  // 2^lw waves share a whole-wave row (lw = 0 when G < 64): wave w works on the
+  // row's column chunks congruent to w mod 2^lw, so that a step with few rows
+  // of many chunks still launches enough short waves to keep every SIMD busy
+  const int lw = a.lwpr;
+  const int rslot = wave >> lw, sub = wave & ((1 << lw) - 1);
+  const int row = ((lb * kWaves >> lw) + rslot) * rpw + grp;
   const bool valid = row < a.n;
   constexpr bool ell = ELL;
   // CSR batches need the row start at once (wave-uniform for whole-wave rows);
@@ -232,7 +242,10 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   V ucur = LOG ? V(0) : V(1);
   if (FWD && a.epi == 1 && comm) ucur = a.uout[rowc];
 
-  for (int ch = 0; ch < a.nchunk; ++ch) {
+  // (the same trip count for every wave of the block: the calibration steps hold barriers)
+  const int nit = (a.nchunk + (1 << lw) - 1) >> lw;
+  for (int it = 0; it < nit; ++it) {
+    const int ch = (it << lw) + sub;
     const int col = (ch * G + gl) * NV;
     const bool cv = valid && col < a.Lp;
     V o[NV];
@@ -566,24 +579,24 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
         for (int v = 0; v < NV; ++v) z[v] = LOG ? ninf<V>() : V(0);
       }
     }
-    if (a.slots) calib_chunk<V, LOG>(z, G, ch * G * NV, a.Lp, a.slots + (size_t)(bid % a.nslot) * a.nslot_stride);
+    if (a.slots) calib_chunk<V, LOG>(z, G, it, lw, a.Lp, a.slots + (size_t)(bid % a.nslot) * a.nslot_stride);
     if (LOG && FWD && !CHK && a.epi == 1 && a.cslots_b) {
       // plan level at the output time: hatPsi + (Psi (.) K_L), up to per-column constants
       V pl[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) pl[v] = cv ? o[v] + w[v] : ninf<V>();
       const size_t cs = (size_t)(bid % a.ncslot) * a.cslot_stride;
-      corr_chunk<V>(pl, w, G, ch * G * NV, a.Lp, a.cslots_b + cs);
-      corr_chunk<V>(pl, z, G, ch * G * NV, a.Lp, a.cslots_f + cs);
+      corr_chunk<V>(pl, w, G, it, lw, a.Lp, a.cslots_b + cs);
+      corr_chunk<V>(pl, z, G, it, lw, a.Lp, a.cslots_f + cs);
     }
     if (LOG && FWD && !CHK && a.epi == 2 && a.cslots_f)
-      corr_chunk<V>(plT, o, G, ch * G * NV, a.Lp, a.cslots_f + (size_t)(bid % a.ncslot) * a.cslot_stride);
+      corr_chunk<V>(plT, o, G, it, lw, a.Lp, a.cslots_f + (size_t)(bid % a.ncslot) * a.cslot_stride);
     if (FWD && a.slots_o) {
       if (!cv) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) o[v] = LOG ? ninf<V>() : V(0);
       }
-      calib_chunk<V, LOG>(o, G, ch * G * NV, a.Lp, a.slots_o + (size_t)(bid % a.nslot) * a.nslot_stride_o);
+      calib_chunk<V, LOG>(o, G, it, lw, a.Lp, a.slots_o + (size_t)(bid % a.nslot) * a.nslot_stride_o);
     }
   }
 
@@ -591,8 +604,30 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
   if (FWD && a.epi == 1) {
     V sv;
     if (!LOG) sv = group_sum(ssum, G);
-    else { group_lse(lm, ls, G); sv = (ls > V(0)) ? lm + llog2(ls) : ninf<V>(); }
-    if (valid && gl == 0) {
+    else group_lse(lm, ls, G);
+    if (lw) {
+      // the row's waves combine their partial sums in wave order (deterministic)
+      __shared__ V xm[kWaves], xs[kWaves];
+      if (lane == 0) {
+        if (!LOG) xs[wave] = sv;
+        else { xm[wave] = lm; xs[wave] = ls; }
+      }
+      __syncthreads();
+      if (sub == 0) {
+        for (int k = 1; k < (1 << lw); ++k) {
+          if (!LOG) sv += xs[wave + k];
+          else {
+            const V om = xm[wave + k], os = xs[wave + k];
+            const V nm = fmax(lm, om);
+            const V base = (nm == ninf<V>()) ? V(0) : nm;
+            ls = ls * lexp2(lm - base) + os * lexp2(om - base);
+            lm = nm;
+          }
+        }
+      }
+    }
+    if (LOG) sv = (ls > V(0)) ? lm + llog2(ls) : ninf<V>();
+    if (valid && gl == 0 && sub == 0) {
       const V d = a.cap[row];
       V u;
       if (!CHK) {
@@ -621,13 +656,182 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
     }
   }
   if (CHK && a.epi == 2) {
-    // gather the row's occupancy across the group lanes for the output
+    // gather the row's occupancy across the group lanes (and the row's waves) for the output
     double t = occ_row;
     for (int m = G >> 1; m > 0; m >>= 1) t += __shfl_xor(t, m, 64);
-    if (valid && gl == 0 && a.occ) a.occ[row] = t;
+    if (lw) {
+      __shared__ double xo[kWaves];
+      if (lane == 0) xo[wave] = t;
+      __syncthreads();
+      if (sub == 0)
+        for (int k = 1; k < (1 << lw); ++k) t += xo[wave + k];
+    }
+    if (valid && gl == 0 && sub == 0 && a.occ) a.occ[row] = t;
   }
   if (CHK && a.part) block_stats(st, a.part, bid);
 }
+// ---------------------------------------------------------------------------
+// the steady-state ELL step
+// ---------------------------------------------------------------------------
+// Every step of a sweep on an ELL operator except the sink update: backward
+// products and forward products with the capacity update, outside calibration
+// sweeps and check passes, without state costs or commodity capacities.  The
+// arithmetic is step_body's, operation for operation (the results are bitwise
+// the same); the difference is that nothing here is decided at run time, so
+// a chunk's loads -- the neighbour rows, the factor row and (forward) the
+// backward panel row and the weights -- are all issued before any is used, in
+// straight-line code, and the kernel keeps no registers for the other epilogues.
+template <typename V>
+__host__ __device__ __forceinline__ bool ell_fast(const StepArgs<V>& a) {
+  return a.ellD > 0 && !a.cw && !a.kl && !a.slots && !a.slots_o && !a.cslots_b && !a.cslots_f && a.epi != 2 &&
+         (a.epi == 0 || a.update) && !a.part && !a.occ && !a.pcomm && a.out;
+}
+
+template <typename V, bool LOG, bool FWD, int KB>
+__device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int nblk) {
+  constexpr int NV = VT<V>::N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int G = a.G;
+  const int grp = lane / G, gl = lane & (G - 1);
+  const int rpw = 64 / G;
+  const int lb = xcd_block(bid, nblk);
+  const int lw = a.lwpr;
+  const int rslot = wave >> lw, sub = wave & ((1 << lw) - 1);
+  const int row = ((lb * kWaves >> lw) + rslot) * rpw + grp;
+  const bool valid = row < a.n;
+  const int rowc = valid ? row : 0;
+  const size_t Lp = (size_t)a.Lp;
+  const V pad = LOG ? ninf<V>() : V(0);
+
+  // the row's entries and the u values at its neighbours, once per row
+  int eidx[KB];
+  V ecf[KB], euu[KB];
+  const int e0 = rowc * a.ellD;
+#pragma unroll
+  for (int k = 0; k < KB; ++k) {
+    eidx[k] = a.ci[e0 + k];
+    ecf[k] = a.kv[e0 + k];
+  }
+#pragma unroll
+  for (int k = 0; k < KB; ++k) euu[k] = a.uin[eidx[k]];
+
+  V ssum = 0;
+  V lm = ninf<V>(), ls = 0;
+  const int nit = (a.nchunk + (1 << lw) - 1) >> lw;
+  for (int it = 0; it < nit; ++it) {
+    const int ch = (it << lw) + sub;
+    const int col = (ch * G + gl) * NV;
+    const bool cv = valid && col < a.Lp;
+    const int colc = cv ? col : 0;
+    // all loads of the chunk, at clamped addresses (a row of 16 skips its padding
+    // entries: their term is exactly zero, and for whole-wave rows the test is uniform)
+    V x[KB][NV];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      if (KB < 16 || ecf[k] != pad) {
+        vld(a.xin + eidx[k] * Lp + colc, x[k]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) x[k][v] = V(0);
+      }
+    }
+    V f[NV], w[NV], g[NV];
+    vld(a.fac + colc, f);
+    if (FWD) {
+      vld(a.wpan + rowc * Lp + colc, w);
+      vld(a.wgt + colc, g);
+    }
+    V o[NV];
+    if (!LOG) {
+      V acc[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) acc[v] = 0;
+#pragma unroll
+      for (int k = 0; k < KB; ++k) {
+        const V c = ecf[k] * euu[k];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = fma(c, x[k][v], acc[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) o[v] = acc[v] * f[v];
+    } else {
+      V c[KB];
+#pragma unroll
+      for (int k = 0; k < KB; ++k) c[k] = ecf[k] + euu[k];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        V y[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) y[k] = c[k] + x[k][v];
+        V bm = y[0];
+#pragma unroll
+        for (int k = 1; k < KB; ++k) bm = fmax(bm, y[k]);
+        const V bb = (bm == ninf<V>()) ? V(0) : bm;
+        V acc = lexp2(y[0] - bb);
+#pragma unroll
+        for (int k = 1; k < KB; ++k) acc += lexp2(y[k] - bb);
+        o[v] = (acc > V(0)) ? bm + llog2(acc) + f[v] : ninf<V>();
+      }
+    }
+    if (FWD && cv) {
+      if (!LOG) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ssum = fma(o[v] * w[v], g[v], ssum);
+      } else {
+        V y[NV];
+        V nm = lm;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          y[v] = o[v] + w[v] + g[v];
+          nm = fmax(nm, y[v]);
+        }
+        const V b = (nm == ninf<V>()) ? V(0) : nm;
+        V sum = ls * lexp2(lm - b);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sum += lexp2(y[v] - b);
+        ls = sum;
+        lm = nm;
+      }
+    }
+    if (cv) vst(a.out + row * Lp + col, o);
+  }
+
+  if (FWD) {
+    V sv;
+    if (!LOG) sv = group_sum(ssum, G);
+    else group_lse(lm, ls, G);
+    if (lw) {
+      __shared__ V xm[kWaves], xs[kWaves];
+      if (lane == 0) {
+        if (!LOG) xs[wave] = sv;
+        else { xm[wave] = lm; xs[wave] = ls; }
+      }
+      __syncthreads();
+      if (sub == 0) {
+        for (int k = 1; k < (1 << lw); ++k) {
+          if (!LOG) sv += xs[wave + k];
+          else {
+            const V om = xm[wave + k], os = xs[wave + k];
+            const V nm = fmax(lm, om);
+            const V base = (nm == ninf<V>()) ? V(0) : nm;
+            ls = ls * lexp2(lm - base) + os * lexp2(om - base);
+            lm = nm;
+          }
+        }
+      }
+    }
+    if (LOG) sv = (ls > V(0)) ? lm + llog2(ls) : ninf<V>();
+    if (valid && gl == 0 && sub == 0) {
+      const V d = a.cap[row];
+      a.uout[row] = !LOG ? ((sv <= d) ? V(1) : d / sv) : fmin(V(0), d - sv);
+    }
+  }
+}
+template <typename V, bool LOG, bool FWD, int KB>
+__global__ __launch_bounds__(kBlock) void k_ell_step(StepArgs<V> a) {
+  ell_step_body<V, LOG, FWD, KB>(a, blockIdx.x, gridDim.x);
+}
+
 // (at least two waves per SIMD: the wide CSR variants would otherwise take the
 // whole register file for one)
 template <typename V, bool LOG, bool FWD, bool CHK, bool ELL, int KB, bool CM>
@@ -688,10 +892,10 @@ __device__ __forceinline__ void source_body(const SourceArgs<V>& A, int bid, int
 #pragma unroll
       for (int v = 0; v < NV; ++v) z[v] = LOG ? ninf<V>() : V(0);
     }
-    if (slots) calib_chunk<V, LOG>(z, G, ch * G * NV, Lp, slots + (size_t)(bid % nslot) * slot_stride);
+    if (slots) calib_chunk<V, LOG>(z, G, ch, 0, Lp, slots + (size_t)(bid % nslot) * slot_stride);
     // log domain calibration: Psi_1 at the plan peak (the plan at time 0 is R01)
     if (LOG && A.cslots)
-      corr_chunk<V>(pl, xs, G, ch * G * NV, Lp, A.cslots + (size_t)(bid % A.ncslot) * A.cslot_stride);
+      corr_chunk<V>(pl, xs, G, ch, 0, Lp, A.cslots + (size_t)(bid % A.ncslot) * A.cslot_stride);
   }
 }
 template <typename V, bool LOG>
@@ -1071,14 +1275,14 @@ __global__ void k_prep_fwd(PrepFwdArgs<V> A) { prep_fwd_body<V, LOG>(A, blockIdx
 // ---------------------------------------------------------------------------
 // deterministic two-stage reduction of the stats partials
 // ---------------------------------------------------------------------------
-// stage 1: one block per time slot, sums its nblk partials in block order
+// stage 1: one block per time slot, sums its partials in block order
 __device__ __forceinline__ void reduce1_body(const Reduce1Args& A, int bid, int nblk_grid) {
   const double* __restrict__ part = A.part;
-  const int nblk = A.nblk;
   double* __restrict__ tpart = A.tpart;
 
   const int t = bid;
-  const double* p = part + (size_t)t * nblk * kNSt;
+  const int nblk = (t == 0) ? A.nblk0 : A.nblk;
+  const double* p = part + (size_t)t * A.stride * kNSt;
   __shared__ double red[kBlock][kNSt];
   double acc[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < nblk; b += kBlock) {
@@ -1159,6 +1363,19 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
     else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, E, K, C>), dim3(nblk), dim3(kBlock), 0, s, a); \
     else hipLaunchKernelGGL((k_step<V, LOG, false, false, E, K, C>), dim3(nblk), dim3(kBlock), 0, s, a);       \
   } while (0)
+#define MMOT_ELL_LAUNCH(K)                                                                                   \
+  do {                                                                                                      \
+    if (fwd == 1) hipLaunchKernelGGL((k_ell_step<V, LOG, true, K>), dim3(nblk), dim3(kBlock), 0, s, a);      \
+    else hipLaunchKernelGGL((k_ell_step<V, LOG, false, K>), dim3(nblk), dim3(kBlock), 0, s, a);              \
+  } while (0)
+  if (fwd != 2 && ell_fast(a)) {
+    if (a.ellD == 16) MMOT_ELL_LAUNCH(16);
+    else if (a.ellD == 8) MMOT_ELL_LAUNCH(8);
+    else if (a.ellD == 5) MMOT_ELL_LAUNCH(5);
+    else MMOT_ELL_LAUNCH(4);
+#undef MMOT_ELL_LAUNCH
+    return;
+  }
   if (a.cw) MMOT_STEP_LAUNCH(false, 16, true);
   else if (a.ellD == 16) MMOT_STEP_LAUNCH(true, 16, false);
   else if (a.ellD == 8) MMOT_STEP_LAUNCH(true, 8, false);
@@ -1226,9 +1443,9 @@ void launch_levels(uint32_t* slots, float* lev, int T1, int Lp, int nslot, hipSt
   if (record_item(IK_LEVELS, 0, nb, &A, sizeof(A))) return;
   hipLaunchKernelGGL(k_levels, dim3(nb), dim3(256), 0, s, A);
 }
-void launch_reduce_stats(const double* part, int nblk, int T1, double* tpart, double eps, double* out,
-                         hipStream_t s) {
-  const Reduce1Args A{part, nblk, tpart};
+void launch_reduce_stats(const double* part, int nblk0, int nblk, int stride, int T1, double* tpart, double eps,
+                         double* out, hipStream_t s) {
+  const Reduce1Args A{part, nblk0, nblk, stride, tpart};
   const Reduce2Args B{tpart, T1, eps, out};
   if (record_item(IK_REDUCE1, 0, T1, &A, sizeof(A))) {
     record_item(IK_REDUCE2, 0, 1, &B, sizeof(B));
@@ -1237,10 +1454,12 @@ void launch_reduce_stats(const double* part, int nblk, int T1, double* tpart, do
   hipLaunchKernelGGL(k_reduce_stats1, dim3(T1), dim3(kBlock), 0, s, A);
   hipLaunchKernelGGL(k_reduce_stats2, dim3(1), dim3(64), 0, s, B);
 }
-void launch_reduce_cost(const double* pflow, const double* pstate, int nblk, int T, double* tflow, double* tstate,
-                        double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, Reduce1Args{pflow, nblk, tflow});
-  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s, Reduce1Args{pstate, nblk, tstate});
+void launch_reduce_cost(const double* pflow, const double* pstate, int nblk_flow, int nblk_state, int stride, int T,
+                        double* tflow, double* tstate, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s,
+                     Reduce1Args{pflow, nblk_flow, nblk_flow, stride, tflow});
+  hipLaunchKernelGGL(k_reduce_stats1, dim3(T), dim3(kBlock), 0, s,
+                     Reduce1Args{pstate, nblk_state, nblk_state, stride, tstate});
   hipLaunchKernelGGL(k_reduce_cost, dim3(1), dim3(64), 0, s, tflow, tstate, T, out);
 }
 
@@ -1263,6 +1482,20 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
     case IK_STEP_FWD:
     case IK_STEP_CHK: {
       const StepArgs<float>& sa = *static_cast<const StepArgs<float>*>(p);
+      if (it.kind != IK_STEP_CHK && ell_fast(sa)) {
+        const bool fw = it.kind == IK_STEP_FWD;
+#define MMOT_ELL_ITEM(K)                                                              \
+        do {                                                                          \
+          if (fw) ell_step_body<float, LOG, true, K>(sa, bid, it.nblk);               \
+          else ell_step_body<float, LOG, false, K>(sa, bid, it.nblk);                 \
+        } while (0)
+        if (sa.ellD == 16) MMOT_ELL_ITEM(16);
+        else if (sa.ellD == 8) MMOT_ELL_ITEM(8);
+        else if (sa.ellD == 5) MMOT_ELL_ITEM(5);
+        else MMOT_ELL_ITEM(4);
+#undef MMOT_ELL_ITEM
+        break;
+      }
       // 0: CSR, 1..4: ELL of width 8, 16, 5, 4, 5: CSR with commodity capacities
       const int e = sa.cw ? 5 : (sa.ellD == 8 ? 1 : sa.ellD == 16 ? 2 : sa.ellD == 5 ? 3 : sa.ellD == 4 ? 4 : 0);
       if constexpr (LEAN) {
