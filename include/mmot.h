@@ -41,7 +41,8 @@ typedef enum mmot_status {
   MMOT_EINVAL = 1,        /* bad sizes, eps, NaN/negative data, unsorted CSR, unequal or zero masses */
   MMOT_ENOMEM = 2,        /* workspace smaller than mmot_query_workspace reported */
   MMOT_EINFEASIBLE = 3,   /* a positive source/sink entry faces a zero message (Theorem 4 support) */
-  MMOT_ENUMERIC = 4,      /* non-finite values appeared (range exceeded in the scaled domain) */
+  MMOT_ENUMERIC = 4,      /* non-finite values appeared, or a scaled-domain solver that passed its
+                             AUTO probe met a zero message later (range exceeded in the scaled domain) */
   MMOT_EHIP = 5,          /* a HIP runtime call failed */
   MMOT_EAGAIN = 6,        /* pool: request does not fit the HBM budget right now */
   MMOT_EUNSUPPORTED = 7   /* option combination not implemented */
@@ -252,19 +253,29 @@ mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double
  * plain solver.  Admission is by HBM footprint: the sum of admitted workspace
  * sizes never exceeds the budget.  Set-up work (validation, operators, the
  * domain probe) runs on a pool-owned stream and does not wait for queued
- * ticks.  Besides the workspaces, the pool allocates small device and pinned
- * buffers for each batched request's recorded work items (about 340 bytes per
- * kernel of a check_every-iteration chunk) and frees them at release.
+ * ticks.  The pool allocates no device memory: a request's workspace (sized by
+ * mmot_pool_query_workspace) holds its solver and, after it, the program area
+ * of its recorded work items (368 bytes per kernel of a check_every-iteration
+ * chunk plus its check pass), so the budget counts every byte a request uses.
+ * A tick runs at most 64 requests' items; the others wait for later ticks
+ * (round-robin), each request's items always running in their recorded order.
  * ------------------------------------------------------------------------- */
 typedef struct mmot_pool mmot_pool;
 
-/* hbm_budget: bytes of workspace the pool may have admitted at once. */
+/* hbm_budget: bytes of workspace (mmot_pool_query_workspace sizes) the pool
+ * may have admitted at once. */
 mmot_status mmot_pool_create(size_t hbm_budget, void* stream, mmot_pool** out);
 
-/* Admit one request: validates and sets up a solver in ws (>= the queried
- * workspace size; the caller keeps it alive until mmot_pool_release) and
- * schedules it.  EAGAIN when admitting it would exceed the budget (nothing is
- * done; retry after a release); EUNSUPPORTED unless CSR and MMOT_FP32.
+/* Workspace bytes of one pool request: the solver's (mmot_query_workspace)
+ * plus its program area, (check_every + 1) * (2 T + 8) + 8 work items of 368
+ * bytes.  Same errors as mmot_query_workspace. */
+mmot_status mmot_pool_query_workspace(const mmot_problem* prob, const mmot_options* opt, size_t* bytes);
+
+/* Admit one request: validates and sets up a solver in ws (>= the size from
+ * mmot_pool_query_workspace, ENOMEM otherwise; the caller keeps it alive until
+ * mmot_pool_release) and schedules it.  EAGAIN when admitting it would exceed
+ * the budget (nothing is done; retry after a release); EUNSUPPORTED unless CSR
+ * and MMOT_FP32, or if a recorded chunk would not fit its program area.
  * *ticket identifies the request.  Synchronous with respect to its own set-up
  * only. */
 mmot_status mmot_pool_submit(mmot_pool* pool, const mmot_problem* prob, const mmot_options* opt, void* ws,

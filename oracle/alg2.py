@@ -285,14 +285,15 @@ def iterate(p: Problem, st: State, n_iter: int) -> State:
     return st
 
 
-def projections(p: Problem, st: State):
+def projections(p: Problem, st: State, want_flows: bool = True):
     """Exact projections of K (.) U at the current scalings.
 
     Runs a fresh backward sweep and an update-free forward sweep (Theorem 5),
     then forms (Corollary 1, eq. proj_0t, eq. proj_discrete_bi):
       P0t  (T+1, L, n)  bi-marginal projections on (commodity, time tau)
       Pt   (T+1, n)     occupancy marginals
-      flows list of T sparse (n x n) matrices, flows[tau][i, j] = total mass
+      flows list of T (n x n) matrices (sparse for a sparse K, dense for a dense K),
+            flows[tau][i, j] = total mass
             moving i -> j between tau and tau+1:
             K_ij * sum_l A_tau[l, i] B_{tau+1}[l, j], with A_0 = U01,
             A_tau = hatPsi_tau (.) KL (.) u_tau, B_T = U0T,
@@ -313,21 +314,31 @@ def projections(p: Problem, st: State):
     for tau in range(1, T):
         P0t[tau] = hats[tau] * tmp.psi[tau] * _klw(KL, tmp.w, tau) * tmp.u[tau - 1][None, :]
     P0t[T] = tmp.U0T * ph_T
+    if not want_flows:
+        return dict(P0t=P0t, Pt=P0t.sum(axis=1), mass=P0t.sum(axis=2), psi=tmp.psi, psihat=hats)
     A = [tmp.U01] + [hats[tau] * _klw(KL, tmp.w, tau) * tmp.u[tau - 1][None, :] for tau in range(1, T)]
     B = [None] + [tmp.psi[tau] * _klw(KL, tmp.w, tau) * tmp.u[tau - 1][None, :] for tau in range(1, T)] + [tmp.U0T]
     flows = []
     for tau in range(T):
         Kt = _kat(K, tau)
-        Kc = (sp.csr_matrix(Kt) if not sp.issparse(Kt) else Kt.tocsr()).tocoo()
-        vals = Kc.data * np.einsum("li,li->i", A[tau][:, Kc.row], B[tau + 1][:, Kc.col])
-        flows.append(sp.csr_matrix((vals, (Kc.row, Kc.col)), shape=(n, n)))
+        if sp.issparse(Kt):
+            Kc = Kt.tocoo()
+            vals = Kc.data * np.einsum("li,li->i", A[tau][:, Kc.row], B[tau + 1][:, Kc.col])
+            flows.append(sp.csr_matrix((vals, (Kc.row, Kc.col)), shape=(n, n)))
+        else:
+            # dense K: the same entries, K_ij sum_l A[l, i] B[l, j], as one matrix product
+            flows.append(Kt * (A[tau].T @ B[tau + 1]))
     cost = 0.0
     for tau in range(T):
-        F = flows[tau].tocoo()
         Ct = _kat(p.C, tau)
-        cvals = np.asarray(Ct[F.row, F.col]).ravel() if sp.issparse(Ct) else Ct[F.row, F.col]
-        m = F.data > 0                       # a closed move (+inf cost) carries no mass
-        cost += float((cvals[m] * F.data[m]).sum())
+        if sp.issparse(flows[tau]):
+            F = flows[tau].tocoo()
+            cvals = np.asarray(Ct[F.row, F.col]).ravel() if sp.issparse(Ct) else Ct[F.row, F.col]
+            fv = F.data
+        else:
+            cvals, fv = Ct.ravel(), flows[tau].ravel()
+        m = fv > 0                           # a closed move (+inf cost) carries no mass
+        cost += float((cvals[m] * fv[m]).sum())
     if p.state_cost is not None:
         for tau in range(1, T):
             cost += float((p.state_cost * P0t[tau]).sum())

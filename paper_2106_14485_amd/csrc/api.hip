@@ -172,6 +172,7 @@ struct mmot_solver {
   int64_t iters = 0;
   bool psi_fresh = false, pend_b = false, pend_f = false;
   int force_calib = 0;
+  bool probe_clean = false;        // the scaled domain passed the AUTO probe iteration
   hipStream_t cap_stream = nullptr;
   std::map<int, hipGraphExec_t> graphs;
   double* host_stats = nullptr;   // pinned
@@ -764,11 +765,20 @@ auto dispatch(mmot_solver* s, F&& f) {
   return f(Impl<float, false>());
 }
 
+// A zero message facing a positive source or sink entry.  Reachability is a
+// property of the network and T alone, and the first iteration (u = 1) shows it;
+// once a scaled-domain solver has passed its probe iteration without one, a
+// later zero message comes from the range of the scalings (u -> 0 underflowing
+// a message), a numeric failure and not infeasibility.
+mmot_status zero_message_status(const mmot_solver* s) {
+  return (s->dom == MMOT_DOMAIN_SCALED && s->probe_clean) ? MMOT_ENUMERIC : MMOT_EINFEASIBLE;
+}
+
 mmot_status read_flags(mmot_solver* s) {
   HIPCK(hipMemcpyAsync(s->host_flags, s->flags, sizeof(int), hipMemcpyDeviceToHost, s->stream));
   HIPCK(hipStreamSynchronize(s->stream));
   const int f = *s->host_flags;
-  if (f & FLAG_INFEASIBLE) return MMOT_EINFEASIBLE;
+  if (f & FLAG_INFEASIBLE) return zero_message_status(s);
   if (f & FLAG_NONFINITE) return MMOT_ENUMERIC;
   return MMOT_OK;
 }
@@ -853,6 +863,18 @@ mmot_status check_pass(mmot_solver* s, double* occ, double* pcomm, mmot_stats* o
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+namespace {
+// Items of one recorded chunk of check_every iterations plus the check pass, at
+// most: per iteration a backward sweep (T steps, the offset preparation and the
+// level/growth pair) and a forward sweep (T steps, source update, offsets,
+// level/growth pair); the check pass a fresh backward sweep, an update-free
+// forward sweep with its time-0 statistics and the two-stage reduction.
+int64_t pool_prog_items(int T, int check_every) {
+  const int k = check_every < 1 ? 10 : check_every;
+  return (int64_t)(k + 1) * (2 * (int64_t)T + 8) + 8;
+}
+}  // namespace
+
 extern "C" {
 
 void mmot_default_options(mmot_options* o) {
@@ -882,6 +904,15 @@ mmot_status mmot_query_workspace(const mmot_problem* p, const mmot_options* o, s
   Carver c{nullptr};
   carve(&tmp, c);
   *bytes = c.off + 256;
+  return MMOT_OK;
+}
+
+mmot_status mmot_pool_query_workspace(const mmot_problem* p, const mmot_options* o, size_t* bytes) {
+  if (!bytes || !o) return MMOT_EINVAL;
+  size_t need = 0;
+  const mmot_status st = mmot_query_workspace(p, o, &need);
+  if (st != MMOT_OK) return st;
+  *bytes = need + 256 + (size_t)pool_prog_items(p->T, o->check_every) * sizeof(PoolItem);
   return MMOT_OK;
 }
 
@@ -955,6 +986,7 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
     const mmot_status fs = read_flags(s);
     if (fs == MMOT_EINFEASIBLE || fs == MMOT_ENUMERIC) s->dom = MMOT_DOMAIN_LOG;
     else if (fs != MMOT_OK) return fail(fs);
+    else s->probe_clean = true;
     s->iters = 0;
     s->psi_fresh = s->pend_b = s->pend_f = false;
     s->force_calib = 0;
@@ -1162,11 +1194,14 @@ struct mmot_pool {
     int32_t state = 0;       // 0 running, 1 done, 2 failed
     int32_t status = MMOT_OK;
     int lane = -1;           // -1: batched lane, -2: waiting for a dedicated lane, else its stream index
-    // batched lane: the current chunk's program, resident on the device
+    // batched lane: the current chunk's program, resident on the device in the
+    // program area at the end of the request's workspace (prog_cap items)
     PoolItem* d_prog = nullptr;
-    PoolItem* h_prog = nullptr;
-    int prog_cap = 0, len = 0, maxblk = 0;
-    int64_t base = 0;        // tick that runs the chunk's first item
+    std::vector<PoolItem> h_prog;   // host copy (the upload's source until the chunk has run)
+    int prog_cap = 0, len = 0;
+    int pc = 0;              // next item of the chunk: it advances only when a tick runs the item
+    hipEvent_t up_ev = nullptr;     // the chunk's upload (on the set-up stream)
+    bool upload_wait = false;       // the tick stream has yet to wait for up_ev
     bool awaiting = false;   // chunk enqueued, its statistics not yet read
     hipEvent_t ev = nullptr;
     mmot_stats stats{};
@@ -1174,6 +1209,7 @@ struct mmot_pool {
   };
   std::map<uint64_t, Req*> reqs;
   int64_t ticks = 0;
+  uint64_t rr = 0;                    // round-robin start among the ready batched requests
   static constexpr int kLead = 16;    // ticks the host may run ahead of the device
   hipEvent_t lead_ev[kLead] = {};
 };
@@ -1182,12 +1218,6 @@ namespace {
 
 constexpr int kFillBlocks = 256;      // a step of at least this many blocks fills the GPU alone
 
-void free_prog(mmot_pool::Req* r) {
-  if (r->d_prog) (void)hipFree(r->d_prog);
-  if (r->h_prog) (void)hipHostFree(r->h_prog);
-  r->d_prog = r->h_prog = nullptr;
-  r->prog_cap = 0;
-}
 
 // Batched lane: record the next chunk of a request's work -- the same calls
 // mmot_solve makes (check_every iterations, then the check pass up to its
@@ -1205,26 +1235,23 @@ mmot_status pool_program(mmot_pool* P, mmot_pool::Req* r) {
   launch_reduce_stats(s->part, s->nblk, s->nblk_s, s->nblk_s, s->T + 1, s->tpart, s->eps, s->stats_dev, s->stream);
   s->opt.use_graph = saved_graph;
   tl_recorder = nullptr;
-  r->iters_planned += k;
+  // an item whose arguments did not fit, or a chunk longer than the program area,
+  // would run incomplete: refuse the request instead
   const int n = (int)rec.items.size();
-  if (n > r->prog_cap) {
-    // the previous chunk has run to completion (its statistics were read), so
-    // no queued tick refers to the old buffers
-    free_prog(r);
-    if (hipMalloc(reinterpret_cast<void**>(&r->d_prog), sizeof(PoolItem) * n) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&r->h_prog), sizeof(PoolItem) * n, 0) != hipSuccess) {
-      free_prog(r);
-      return MMOT_EHIP;
-    }
-    r->prog_cap = n;
-  }
-  int mb = 0;
-  for (int i = 0; i < n; ++i) { r->h_prog[i] = rec.items[i]; mb = std::max(mb, rec.items[i].nblk); }
-  if (hipMemcpyAsync(r->d_prog, r->h_prog, sizeof(PoolItem) * n, hipMemcpyHostToDevice, P->stream) != hipSuccess)
+  if (!rec.ok || n > r->prog_cap || n == 0) return MMOT_EUNSUPPORTED;
+  r->iters_planned += k;
+  // The previous chunk has run to completion (its statistics were read), so no
+  // queued tick reads the program area.  The upload runs on the set-up stream
+  // (its host-side staging does not wait for queued ticks); the tick stream
+  // waits for it before the chunk's first item.
+  r->h_prog.assign(rec.items.begin(), rec.items.end());
+  if (hipMemcpyAsync(r->d_prog, r->h_prog.data(), sizeof(PoolItem) * n, hipMemcpyHostToDevice, P->setup) !=
+          hipSuccess ||
+      hipEventRecord(r->up_ev, P->setup) != hipSuccess)
     return MMOT_EHIP;
+  r->upload_wait = true;
   r->len = n;
-  r->maxblk = mb;
-  r->base = P->ticks;
+  r->pc = 0;
   r->awaiting = false;
   return MMOT_OK;
 }
@@ -1271,7 +1298,7 @@ mmot_status pool_finish_chunk(mmot_pool* P, mmot_pool::Req* r) {
   o.mass = s->host_stats[5];
   o.converged = (o.src_resid <= s->opt.tol && o.cap_viol <= s->opt.tol) ? 1 : 0;
   mmot_status st = MMOT_OK;
-  if (f & FLAG_INFEASIBLE) st = MMOT_EINFEASIBLE;
+  if (f & FLAG_INFEASIBLE) st = zero_message_status(s);
   else if ((f & FLAG_NONFINITE) || s->host_stats[6] > 0 || !std::isfinite(s->host_stats[0])) st = MMOT_ENUMERIC;
   if (st == MMOT_OK && !o.converged && r->iters_planned < r->max_iter)
     return r->lane >= 0 ? lane_chunk(r) : pool_program(P, r);
@@ -1311,14 +1338,16 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
                              size_t ws_bytes, int32_t max_iter, uint64_t* ticket) {
   if (!P || !prob || !opt || !ticket || max_iter < 1) return MMOT_EINVAL;
   if (prob->kind != MMOT_CSR || opt->precision != MMOT_FP32) return MMOT_EUNSUPPORTED;
-  size_t need = 0;
-  mmot_status st = mmot_query_workspace(prob, opt, &need);
+  size_t need = 0, solver_need = 0;
+  mmot_status st = mmot_pool_query_workspace(prob, opt, &need);
   if (st != MMOT_OK) return st;
+  if (!ws || ws_bytes < need) return MMOT_ENOMEM;
+  (void)mmot_query_workspace(prob, opt, &solver_need);
   if (P->used + need > P->budget) return MMOT_EAGAIN;
   // set-up runs on the pool's own set-up stream and ends synchronised, so it
   // never waits for queued ticks; the solver then moves to its lane
   mmot_solver* s = nullptr;
-  st = mmot_create(prob, opt, ws, ws_bytes, P->setup, &s);
+  st = mmot_create(prob, opt, ws, solver_need, P->setup, &s);
   if (st != MMOT_OK) return st;
   auto* r = new (std::nothrow) mmot_pool::Req();
   if (!r) { mmot_destroy(s); return MMOT_ENOMEM; }
@@ -1326,7 +1355,15 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
   r->s = s;
   r->bytes = need;
   r->max_iter = max_iter;
+  // the program area: after the solver's workspace, 256-byte aligned
+  uintptr_t pa = reinterpret_cast<uintptr_t>(ws) + solver_need;
+  pa = (pa + 255) & ~uintptr_t(255);
+  r->d_prog = reinterpret_cast<PoolItem*>(pa);
+  r->prog_cap = (int)pool_prog_items(prob->T, s->opt.check_every);
   if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) { mmot_destroy(s); delete r; return MMOT_EHIP; }
+  if (hipEventCreateWithFlags(&r->up_ev, hipEventDisableTiming) != hipSuccess) {
+    mmot_destroy(s); (void)hipEventDestroy(r->ev); delete r; return MMOT_EHIP;
+  }
   if (s->nblk >= kFillBlocks) {
     r->lane = -2;                      // started by mmot_pool_run when a lane is free
     P->lane_queue.push_back(r->ticket);
@@ -1336,7 +1373,8 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
   }
   if (st != MMOT_OK) {
     if (r->lane == -2) P->lane_queue.pop_back();
-    mmot_destroy(s); (void)hipEventDestroy(r->ev); free_prog(r); delete r; return st;
+    (void)hipStreamSynchronize(P->setup);
+    mmot_destroy(s); (void)hipEventDestroy(r->ev); (void)hipEventDestroy(r->up_ev); delete r; return st;
   }
   P->used += need;
   P->reqs[r->ticket] = r;
@@ -1369,34 +1407,46 @@ mmot_status mmot_pool_run(mmot_pool* P, int32_t max_ticks, int32_t* n_running) {
       if (st != MMOT_OK) { r->state = 2; r->status = st; r->s->stream = P->stream; continue; }
       ++lanes_busy;
     }
-    // one tick of the batched lane: the next item of every batched request
+    // one tick of the batched lane: the next item of up to kTickSlots batched
+    // requests, taken round-robin among those with an item ready; a request
+    // left out waits for a later tick (its program counter moves only when its
+    // item runs)
+    std::vector<mmot_pool::Req*> ready;
+    for (auto& kv : P->reqs) {
+      mmot_pool::Req* r = kv.second;
+      if (r->state != 0 || r->lane >= 0 || r->awaiting || r->pc >= r->len) continue;
+      ready.push_back(r);
+    }
+    if (ready.empty()) break;   // nothing batched to run now: let the caller admit and poll
     TickArgs ta;
     ta.nslot = 0;
     int total = 0;
     bool lean = true;   // every item of the tick is light: the leaner tick kernel
-    for (auto& kv : P->reqs) {
-      mmot_pool::Req* r = kv.second;
-      if (r->state != 0 || r->lane >= 0 || r->awaiting) continue;
-      const int64_t idx = P->ticks - r->base;
-      if (idx < 0 || idx >= r->len || ta.nslot == kTickSlots) continue;
+    mmot_pool::Req* in_tick[kTickSlots];
+    const size_t start = (size_t)(P->rr++ % ready.size());
+    for (size_t q = 0; q < ready.size() && ta.nslot < kTickSlots; ++q) {
+      mmot_pool::Req* r = ready[(start + q) % ready.size()];
+      if (r->upload_wait) {
+        if (hipStreamWaitEvent(P->stream, r->up_ev, 0) != hipSuccess) return MMOT_EHIP;
+        r->upload_wait = false;
+      }
+      const PoolItem& it = r->h_prog[r->pc];
       ta.prefix[ta.nslot] = total;
-      ta.idx[ta.nslot] = (int)idx;
+      ta.idx[ta.nslot] = r->pc;
       ta.prog[ta.nslot] = r->d_prog;
-      lean = lean && pool_item_is_light(r->h_prog[idx]);
-      total += r->maxblk;
-      ++ta.nslot;
+      lean = lean && pool_item_is_light(it);
+      total += it.nblk;
+      in_tick[ta.nslot++] = r;
     }
     ta.prefix[ta.nslot] = total;
-    if (ta.nslot == 0) break;   // nothing batched to run now: let the caller admit and poll
     const int li = (int)(P->ticks % mmot_pool::kLead);
     if (P->ticks >= mmot_pool::kLead) (void)hipEventSynchronize(P->lead_ev[li]);
     launch_pool_tick(ta, lean, P->stream);
     if (hipEventRecord(P->lead_ev[li], P->stream) != hipSuccess) return MMOT_EHIP;
     // requests whose chunk ended with this tick: fetch their statistics
-    for (auto& kv : P->reqs) {
-      mmot_pool::Req* r = kv.second;
-      if (r->state != 0 || r->lane >= 0 || r->awaiting) continue;
-      if (P->ticks - r->base == r->len - 1)
+    for (int q = 0; q < ta.nslot; ++q) {
+      mmot_pool::Req* r = in_tick[q];
+      if (++r->pc == r->len)
         if (pool_fetch_stats(r, P->stream) != MMOT_OK) return MMOT_EHIP;
     }
     ++P->ticks;
@@ -1436,9 +1486,10 @@ mmot_status mmot_pool_release(mmot_pool* P, uint64_t ticket) {
   mmot_pool::Req* r = it->second;
   if (r->state == 0) return MMOT_EAGAIN;
   (void)hipStreamSynchronize(r->s->stream);
+  (void)hipStreamSynchronize(P->setup);
   mmot_destroy(r->s);
   (void)hipEventDestroy(r->ev);
-  free_prog(r);
+  if (r->up_ev) (void)hipEventDestroy(r->up_ev);
   P->used -= r->bytes;
   delete r;
   P->reqs.erase(it);
@@ -1451,7 +1502,7 @@ void mmot_pool_destroy(mmot_pool* P) {
   for (auto& kv : P->reqs) {
     mmot_destroy(kv.second->s);
     if (kv.second->ev) (void)hipEventDestroy(kv.second->ev);
-    free_prog(kv.second);
+    if (kv.second->up_ev) (void)hipEventDestroy(kv.second->up_ev);
     delete kv.second;
   }
   for (int i = 0; i < mmot_pool::kLead; ++i)

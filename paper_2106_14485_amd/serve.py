@@ -38,8 +38,8 @@ class Pool:
     def workspace_bytes(self, inst) -> int:
         p, keep = _problem_sizes(inst)
         nb = ctypes.c_size_t(0)
-        check(_lib.lib().mmot_query_workspace(ctypes.byref(p), ctypes.byref(self.opts), ctypes.byref(nb)),
-              "mmot_query_workspace")
+        check(_lib.lib().mmot_pool_query_workspace(ctypes.byref(p), ctypes.byref(self.opts), ctypes.byref(nb)),
+              "mmot_pool_query_workspace")
         return nb.value
 
     def submit(self, inst, max_iter=500):

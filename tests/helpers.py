@@ -44,6 +44,11 @@ def random_tiny(n=4, T=4, L=2, seed=0, density=0.6, state_cost=True, cap_scale=0
     return alg2.make_problem(Cm, eps, T, src, dst, cap, sc), C
 
 
+def dense_flow(f):
+    """An oracle flow matrix as a dense array (sparse for a sparse K, dense for a dense K)."""
+    return f.toarray() if sp.issparse(f) else np.asarray(f)
+
+
 def rel_l1(a, b):
     a = np.asarray(a, dtype=np.float64); b = np.asarray(b, dtype=np.float64)
     den = np.abs(b).sum()

@@ -488,6 +488,77 @@ def test_road_grid_full_size_invariants():
     S.close()
 
 
+def test_road_grid_full_size_converges():
+    """The traffic-routing workload at full size (100 x 100, L = 2000, T = 120,
+    FP32 log domain) solved by mmot_solve to tolerance 1e-3 (source residual
+    and relative capacity violation; the FP32 floor of the source residual here
+    is ~3e-5): the instance is feasible -- the capacity violation falls from
+    ~12 to the tolerance while the dual objective stops rising -- and the
+    converged plan keeps every capacity to 1e-3, conserves each commodity's
+    mass at every time, and is complementary-slack (a state whose capacity
+    scaling is below 1 is at its capacity)."""
+    inst = instances.road_grid_instance()
+    S = _solver()(inst, precision="fp32", domain="auto", tol=1e-3, check_every=10)
+    st = S.solve(3000)
+    assert st["domain"] == 2
+    assert st["converged"] == 1, st
+    assert st["cap_viol"] <= 1e-3 and st["src_resid"] <= 1e-3
+    assert st["mass_drift"] <= 1e-4
+    g1 = st["dual_obj"]
+    st2 = S.iterate(50, stats=True)
+    assert st2["dual_obj"] >= g1 - 1e-7 * abs(g1)            # ascent (to FP32 round-off)
+    assert st2["dual_obj"] - g1 <= 1e-5 * abs(g1)            # ... and it has levelled off
+    occ = S.occupancy().cpu().numpy()
+    lc = S.log_duals()[2].cpu().numpy()                      # log u_t, (T-1) x n
+    S.close()
+    mass = inst.src.sum()
+    assert np.abs(occ.sum(axis=1) - mass).max() <= 1e-4 * mass
+    cap = np.broadcast_to(inst.cap_full(), (inst.T - 1, inst.n))
+    fin = np.isfinite(cap)
+    inner = occ[1:-1]
+    assert (inner[fin] <= cap[fin] * (1 + 2e-3)).all()
+    tight = fin & (lc < -1e-2)                               # u_t < 0.99
+    assert tight.any()
+    assert (inner[tight] >= cap[tight] * (1 - 1e-2)).all()
+
+
+@pytest.fixture(scope="module")
+def dense_full_states():
+    inst = instances.dense_blob_instance(n=4096, L=64, T=12, seed=3)
+    p = to_oracle(inst)
+    ost = alg2.iterate(p, alg2.initial_state(p), 100)
+    return inst, alg2.projections(p, ost)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_dense_full_states_against_the_oracle(dense_full_states, precision):
+    """The dense workload's state count (n = 4096, complete graph truncated at
+    distance^2 0.25) with fewer commodities and times (L = 64, T = 12), run to
+    its fixed point (the FP64 oracle is at machine precision after 100
+    iterations): FP32 products for 100 iterations, or BF16 products for 80 and
+    an FP32 polish of 20.  Occupancy and per-commodity marginals against the
+    exact-input oracle to 1e-5 (FP32) and 1e-4 (BF16 + polish); source residual
+    and capacity violation below 1e-6 after the polish."""
+    inst, ref = dense_full_states
+    S = _solver()(inst, precision=precision, domain="auto")
+    if precision == "bf16":
+        S.iterate(80)
+        S.set_precision("fp32")
+        st = S.iterate(20, stats=True)
+        tol = 1e-4
+    else:
+        st = S.iterate(100, stats=True)
+        tol = 1e-5
+    occ, pc = S.occupancy(per_commodity=True)
+    occ, pc = occ.cpu().numpy(), pc.cpu().numpy()
+    S.close()
+    assert rel_l1(occ, ref["Pt"]) <= tol, rel_l1(occ, ref["Pt"])
+    assert rel_l1(pc, ref["P0t"]) <= tol, rel_l1(pc, ref["P0t"])
+    for l in range(inst.L):
+        assert rel_l1(pc[:, l, :], ref["P0t"][:, l, :]) <= 2 * tol, l
+    assert st["src_resid"] <= 1e-6 and st["cap_viol"] <= 1e-6, st
+
+
 # ---------------------------------------------------------------------------
 # edge-state lifts: flow on edges, per-commodity edge costs as state costs
 # ---------------------------------------------------------------------------

@@ -119,3 +119,75 @@ def test_extension_requests_same_in_pool_and_plain():
         assert np.array_equal(mixed[k][1], plain[1]), f"request {k}: pool differs from plain solver"
         assert mixed[k][0]["iters"] == plain[0]["iters"]
         assert mixed[k][0]["dual_obj"] == plain[0]["dual_obj"]
+
+
+def test_more_requests_than_tick_slots():
+    """80 small requests at once: a tick runs at most 64 requests' items, so the
+    others wait for later ticks; every request still runs its whole recorded
+    schedule in order, and its result is bitwise the plain solver's."""
+    insts = [instances.rgg_instance(n=200 + 10 * (k % 7), L=1 + k % 5, T=6 + k % 4, seed=100 + k,
+                                    cap_lo=1.0, cap_hi=2.0) for k in range(80)]
+    mixed = _pooled(insts, 30)
+    for k in (0, 1, 13, 63, 64, 65, 79):
+        plain = _plain(insts[k], 30)
+        assert np.array_equal(mixed[k][1], plain[1]), f"request {k}: pool differs from plain solver"
+        assert mixed[k][0]["iters"] == plain[0]["iters"]
+        assert mixed[k][0]["dual_obj"] == plain[0]["dual_obj"]
+
+
+def test_workspace_exactly_the_queried_size():
+    """The pool carves each request's program area from the caller's workspace:
+    the queried size is enough, one byte less is ENOMEM."""
+    import ctypes
+    from paper_2106_14485_amd import _lib
+    from paper_2106_14485_amd.serve import Pool
+    from paper_2106_14485_amd.solver import _ptr, device_problem
+    inst = _mix()[1]
+    pool = Pool(1 << 34)
+    nbytes = pool.workspace_bytes(inst)
+    p, keep = device_problem(inst, pool.device)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=pool.device)
+    t = ctypes.c_uint64(0)
+    L = _lib.lib()
+    assert L.mmot_pool_submit(pool._h, ctypes.byref(p), ctypes.byref(pool.opts), _ptr(ws), nbytes - 1, 20,
+                              ctypes.byref(t)) == _lib.MMOT_ENOMEM
+    assert L.mmot_pool_submit(pool._h, ctypes.byref(p), ctypes.byref(pool.opts), _ptr(ws), nbytes, 20,
+                              ctypes.byref(t)) == _lib.MMOT_OK
+    while pool.run(64) > 0:
+        pass
+    state, status, st = pool.poll(t.value)
+    assert state == 1 and status == 0
+    occ = pool.occupancy(t.value).cpu().numpy()
+    torch.cuda.synchronize()
+    pool.release(t.value)
+    pool.close()
+    plain = _plain(inst, 20)
+    assert np.array_equal(occ, plain[1])
+    del keep
+
+
+def test_served_result_matches_the_oracle():
+    """A served request against the FP64 oracle directly (not only against the
+    plain solver): the same schedule -- chunks of ten iterations, each ended by
+    the check pass -- to a fixed iteration count, occupancy and per-commodity
+    marginals to 1e-5."""
+    from oracle import alg2
+    from paper_2106_14485_amd.serve import Pool
+    from tests.helpers import rel_l1, to_oracle
+    inst = _mix()[0]
+    pool = Pool(1 << 34, check_every=10, tol=1e-30)         # runs to max_iter
+    t = pool.submit(inst, max_iter=30)
+    while pool.run(64) > 0:
+        pass
+    state, status, st = pool.poll(t)
+    assert state == 1 and status == 0 and st["iters"] == 30 and st["domain"] == 1
+    occ, pc = pool.occupancy(t, per_commodity=True)
+    occ, pc = occ.cpu().numpy(), pc.cpu().numpy()
+    pool.release(t)
+    pool.close()
+    p = to_oracle(inst)
+    ost = alg2.iterate(p, alg2.initial_state(p), 30)
+    ref = alg2.projections(p, ost, want_flows=False)
+    assert rel_l1(occ, ref["Pt"]) <= 1e-5
+    assert rel_l1(pc, ref["P0t"]) <= 1e-5
+    assert abs(st["dual_obj"] - ost.g[-1]) <= 1e-5 * abs(ost.g[-1])

@@ -7,7 +7,7 @@ import scipy.sparse as sp
 
 from oracle import alg2, closed_forms
 from paper_2106_14485_amd import instances
-from tests.helpers import rel_l1, to_oracle
+from tests.helpers import dense_flow, rel_l1, to_oracle
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -60,7 +60,7 @@ def test_two_marginal_limit_is_diagonal_scaling():
     p = alg2.make_problem(C, 0.3, 1, a, b, np.zeros((0, n)))
     st = alg2.iterate(p, alg2.initial_state(p), 3000)
     out = alg2.projections(p, st)
-    M = out["flows"][0].toarray()
+    M = dense_flow(out["flows"][0])
     assert np.allclose(M.sum(1), a[0], rtol=1e-9, atol=0)
     assert np.allclose(M.sum(0), b[0], rtol=1e-12, atol=0)
     assert closed_forms.rank_one_residual(M, alg2.gibbs(p), None, None) < 1e-10

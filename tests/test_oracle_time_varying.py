@@ -16,7 +16,7 @@ import pytest
 import scipy.sparse as sp
 
 from oracle import alg2, bruteforce, lp_check
-from tests.helpers import random_tiny, rel_l1
+from tests.helpers import dense_flow, random_tiny, rel_l1
 
 
 def _per_step(p, seed, close_frac=0.15):
@@ -55,9 +55,9 @@ def test_time_varying_projections_match_full_tensor(seed):
     for tau in range(p.T + 1):
         assert rel_l1(out["P0t"][tau], P0t[tau]) < 1e-13
     for tau in range(p.T):
-        assert rel_l1(out["flows"][tau].toarray(), pairs[tau]) < 1e-13
+        assert rel_l1(dense_flow(out["flows"][tau]), pairs[tau]) < 1e-13
         closed = ~np.isfinite(p.C[tau].toarray()) & (p.C[tau].toarray() != 0)
-        assert np.all(out["flows"][tau].toarray()[closed] == 0.0)
+        assert np.all(dense_flow(out["flows"][tau])[closed] == 0.0)
     Cf = [np.where(K > 0, c.toarray(), 0.0) for K, c in zip(Ks, p.C)]
     brute = sum((Cf[tau] * pairs[tau]).sum() for tau in range(p.T))
     brute += sum((p.state_cost * P0t[tau]).sum() for tau in range(1, p.T))
