@@ -157,8 +157,10 @@ def test_workspace_exactly_the_queried_size():
         pass
     state, status, st = pool.poll(t.value)
     assert state == 1 and status == 0
-    occ = pool.occupancy(t.value).cpu().numpy()
-    torch.cuda.synchronize()
+    s = L.mmot_pool_solver(pool._h, ctypes.c_uint64(t.value))
+    occ_d = torch.empty((inst.T + 1, inst.n), dtype=torch.float64, device=pool.device)
+    assert L.mmot_occupancy(ctypes.c_void_p(s), _ptr(occ_d), None) == _lib.MMOT_OK
+    occ = occ_d.cpu().numpy()
     pool.release(t.value)
     pool.close()
     plain = _plain(inst, 20)
