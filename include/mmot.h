@@ -233,6 +233,27 @@ int64_t mmot_iterations(const mmot_solver* s);
  * forward product is the sink update). */
 mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double* avg_ms_host);
 
+/* One whole solve that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): mmot_create, mmot_solve(max_iter), mmot_occupancy and
+ * mmot_destroy in one call, with the solver workspace taken from a static
+ * device array of MMOT_STATIC_WORKSPACE_BYTES that the library holds on each
+ * GPU it runs on until the process ends, and the solver's host state on the
+ * call's stack.  The caller passes the problem (device inputs, as for
+ * mmot_create), occ ((T+1) * n doubles on the device, NULL for none), stats
+ * (host, nullable) and the stream, which must belong to the current device.
+ * Same results as that sequence of calls (same kernels; iterations are
+ * launched directly, never through captured graphs).  ENOMEM when the problem's
+ * workspace (mmot_query_workspace) exceeds MMOT_STATIC_WORKSPACE_BYTES; the
+ * other errors as mmot_create and mmot_solve.  The array is shared by every
+ * call on a GPU and keeps the last call's contents (the set-up initialises
+ * everything a solve reads): calls that overlap on one GPU -- from several host
+ * threads or on streams that are not ordered -- race.  Returns after the solve
+ * has finished on the stream; the occupancy is written asynchronously after it. */
+#define MMOT_STATIC_WORKSPACE_BYTES ((size_t)256 << 20)
+mmot_status mmot_solve_static(const mmot_problem* prob, const mmot_options* opt, int32_t max_iter, double* occ,
+                              mmot_stats* stats, void* stream);
+
 /* ---------------------------------------------------------------------------
  * Serving pool: continuous batching of many solves on one GPU.
  *

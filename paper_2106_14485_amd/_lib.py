@@ -78,6 +78,8 @@ _SIGS = {
     "mmot_destroy": (None, [ctypes.c_void_p]),
     "mmot_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "mmot_iterations": (ctypes.c_int64, [ctypes.c_void_p]),
+    "mmot_solve_static": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_void_p]),
     "mmot_pool_query_workspace": (ctypes.c_int, [ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                                  ctypes.POINTER(ctypes.c_size_t)]),
     "mmot_pool_create": (ctypes.c_int, [ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),

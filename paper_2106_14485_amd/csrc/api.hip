@@ -8,6 +8,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -175,8 +176,9 @@ struct mmot_solver {
   bool probe_clean = false;        // the scaled domain passed the AUTO probe iteration
   hipStream_t cap_stream = nullptr;
   std::map<int, hipGraphExec_t> graphs;
-  double* host_stats = nullptr;   // pinned
-  int* host_flags = nullptr;      // pinned
+  double* host_stats = nullptr;   // pinned (or the caller's pageable buffers: owns_host false)
+  int* host_flags = nullptr;
+  bool owns_host = false;
 
   size_t panel_elems() const { return (size_t)n * Lp; }
   template <typename V> V* P(void* p) const { return static_cast<V*>(p); }
@@ -875,6 +877,128 @@ int64_t pool_prog_items(int T, int check_every) {
 }
 }  // namespace
 
+namespace {
+// Set-up of a solver object in a workspace of at least the queried size.
+// host_stats / host_flags: host buffers of 16 doubles and 4 ints to use
+// (pageable; the solver then runs without captured graphs), or NULL to
+// allocate pinned ones and a capture stream.  On failure the caller releases
+// what was made (release_solver).
+mmot_status create_into(mmot_solver* s, const mmot_problem* p, const mmot_options* o, void* ws, void* stream,
+                        double* host_stats, int* host_flags) {
+  mmot_status st = MMOT_OK;
+  s->n = p->n; s->L = p->L; s->T = p->T; s->nnz = p->nnz; s->kind = p->kind; s->eps = p->eps;
+  s->steps_k = p->cost_per_step ? p->T : 1;
+  s->has_kl = p->state_cost != nullptr;
+  s->has_comm = p->cap_comm != nullptr && p->T > 1;
+  s->comm_steps = p->cap_comm_per_step ? std::max(p->T - 1, 1) : 1;
+  s->opt = *o;
+  if (s->opt.check_every < 1) s->opt.check_every = 10;
+  if (!(s->opt.tol > 0)) s->opt.tol = 1e-6;
+  s->prec = (o->precision == MMOT_FP64) ? MMOT_FP64 : MMOT_FP32;
+  s->has_bf16 = s->dense_bf16 = o->precision == MMOT_BF16;
+  s->stream = static_cast<hipStream_t>(stream);
+  set_geometry(s);
+  uintptr_t b = reinterpret_cast<uintptr_t>(ws);
+  b = (b + 255) & ~uintptr_t(255);
+  Carver c{reinterpret_cast<char*>(b)};
+  carve(s, c);
+  auto fail = [&](mmot_status e) { return e; };
+  if (host_stats && host_flags) {
+    s->host_stats = host_stats;
+    s->host_flags = host_flags;
+    s->owns_host = false;
+    s->opt.use_graph = 0;
+  } else {
+    s->owns_host = true;
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->host_stats), 16 * sizeof(double), 0) != hipSuccess) return fail(MMOT_EHIP);
+    if (hipHostMalloc(reinterpret_cast<void**>(&s->host_flags), 4 * sizeof(int), 0) != hipSuccess) return fail(MMOT_EHIP);
+    if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MMOT_EHIP);
+  }
+  // domain: an estimate of the within-message dynamic range R = T * mean excess move cost / eps (log2 units)
+  bool auto_probe = false;
+  if (o->domain == MMOT_DOMAIN_AUTO && p->kind == MMOT_DENSE) {
+    s->dom = MMOT_DOMAIN_SCALED;
+  } else if (o->domain == MMOT_DOMAIN_AUTO) {
+    launch_excess(p->rowptr, p->colidx, p->cost, p->n, s->exc_row, s->exc_cnt, s->exc, s->stream);
+    double h = 0;
+    if (hipMemcpyAsync(&s->host_stats[8], s->exc, sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
+        hipStreamSynchronize(s->stream) != hipSuccess)
+      return fail(MMOT_EHIP);
+    h = s->host_stats[8];
+    const double R = (double)p->T * h / p->eps;       // natural-log range estimate
+    const double limit = (s->prec == MMOT_FP64) ? 600.0 : 60.0;
+    s->dom = (R <= limit) ? MMOT_DOMAIN_SCALED : MMOT_DOMAIN_LOG;
+    auto_probe = s->dom == MMOT_DOMAIN_SCALED;
+  } else {
+    s->dom = o->domain;
+  }
+  st = dispatch(s, [&](auto impl) { return decltype(impl)::setup(s, p); });
+  if (st != MMOT_OK) return fail(st);
+  if (auto_probe) {
+    // The cost estimate above misses the path-counting part of the range (a
+    // state many forced moves away from the sink sees only a few of the walks
+    // that a state next to it sees), so the scaled domain is confirmed by one
+    // iteration: a zero or non-finite message at a support entry means the
+    // within-commodity range exceeds the element type, and the solver switches
+    // to the log domain.  Either way it then restarts from the initial scalings.
+    const int g = s->opt.use_graph;
+    s->opt.use_graph = 0;
+    st = run_iterations(s, 1);
+    s->opt.use_graph = g;
+    if (st != MMOT_OK) return fail(st);
+    const mmot_status fs = read_flags(s);
+    if (fs == MMOT_EINFEASIBLE || fs == MMOT_ENUMERIC) s->dom = MMOT_DOMAIN_LOG;
+    else if (fs != MMOT_OK) return fail(fs);
+    else s->probe_clean = true;
+    s->iters = 0;
+    s->psi_fresh = s->pend_b = s->pend_f = false;
+    s->force_calib = 0;
+    st = dispatch(s, [&](auto impl) { return decltype(impl)::setup(s, p); });
+    if (st != MMOT_OK) return fail(st);
+  }
+  return MMOT_OK;
+}
+
+// what create_into made, except the solver object itself
+void release_solver(mmot_solver* s) {
+  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
+  s->graphs.clear();
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  s->cap_stream = nullptr;
+  if (s->owns_host) {
+    if (s->host_stats) (void)hipHostFree(s->host_stats);
+    if (s->host_flags) (void)hipHostFree(s->host_flags);
+  }
+  s->host_stats = nullptr;
+  s->host_flags = nullptr;
+}
+}  // namespace
+
+namespace {
+// Workspace of mmot_solve_static: one array per GPU, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, not device memory;
+// the device address comes from hipGetSymbolAddress, taken once per device with
+// that device current, and only that address is ever handed to kernels or copies.
+constexpr size_t kStaticWorkspaceBytes = MMOT_STATIC_WORKSPACE_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+mmot_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return MMOT_EHIP;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MMOT_EHIP;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return MMOT_OK;
+}
+}  // namespace
+
 extern "C" {
 
 void mmot_default_options(mmot_options* o) {
@@ -931,68 +1055,8 @@ mmot_status mmot_create(const mmot_problem* p, const mmot_options* o, void* ws, 
   if (!ws || ws_bytes < need) return MMOT_ENOMEM;
   mmot_solver* s = new (std::nothrow) mmot_solver();
   if (!s) return MMOT_ENOMEM;
-  s->n = p->n; s->L = p->L; s->T = p->T; s->nnz = p->nnz; s->kind = p->kind; s->eps = p->eps;
-  s->steps_k = p->cost_per_step ? p->T : 1;
-  s->has_kl = p->state_cost != nullptr;
-  s->has_comm = p->cap_comm != nullptr && p->T > 1;
-  s->comm_steps = p->cap_comm_per_step ? std::max(p->T - 1, 1) : 1;
-  s->opt = *o;
-  if (s->opt.check_every < 1) s->opt.check_every = 10;
-  if (!(s->opt.tol > 0)) s->opt.tol = 1e-6;
-  s->prec = (o->precision == MMOT_FP64) ? MMOT_FP64 : MMOT_FP32;
-  s->has_bf16 = s->dense_bf16 = o->precision == MMOT_BF16;
-  s->stream = static_cast<hipStream_t>(stream);
-  set_geometry(s);
-  uintptr_t b = reinterpret_cast<uintptr_t>(ws);
-  b = (b + 255) & ~uintptr_t(255);
-  Carver c{reinterpret_cast<char*>(b)};
-  carve(s, c);
-  auto fail = [&](mmot_status e) { mmot_destroy(s); return e; };
-  if (hipHostMalloc(reinterpret_cast<void**>(&s->host_stats), 16 * sizeof(double), 0) != hipSuccess) return fail(MMOT_EHIP);
-  if (hipHostMalloc(reinterpret_cast<void**>(&s->host_flags), 4 * sizeof(int), 0) != hipSuccess) return fail(MMOT_EHIP);
-  if (hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) return fail(MMOT_EHIP);
-  // domain: an estimate of the within-message dynamic range R = T * mean excess move cost / eps (log2 units)
-  bool auto_probe = false;
-  if (o->domain == MMOT_DOMAIN_AUTO && p->kind == MMOT_DENSE) {
-    s->dom = MMOT_DOMAIN_SCALED;
-  } else if (o->domain == MMOT_DOMAIN_AUTO) {
-    launch_excess(p->rowptr, p->colidx, p->cost, p->n, s->exc_row, s->exc_cnt, s->exc, s->stream);
-    double h = 0;
-    if (hipMemcpyAsync(&s->host_stats[8], s->exc, sizeof(double), hipMemcpyDeviceToHost, s->stream) != hipSuccess ||
-        hipStreamSynchronize(s->stream) != hipSuccess)
-      return fail(MMOT_EHIP);
-    h = s->host_stats[8];
-    const double R = (double)p->T * h / p->eps;       // natural-log range estimate
-    const double limit = (s->prec == MMOT_FP64) ? 600.0 : 60.0;
-    s->dom = (R <= limit) ? MMOT_DOMAIN_SCALED : MMOT_DOMAIN_LOG;
-    auto_probe = s->dom == MMOT_DOMAIN_SCALED;
-  } else {
-    s->dom = o->domain;
-  }
-  st = dispatch(s, [&](auto impl) { return decltype(impl)::setup(s, p); });
-  if (st != MMOT_OK) return fail(st);
-  if (auto_probe) {
-    // The cost estimate above misses the path-counting part of the range (a
-    // state many forced moves away from the sink sees only a few of the walks
-    // that a state next to it sees), so the scaled domain is confirmed by one
-    // iteration: a zero or non-finite message at a support entry means the
-    // within-commodity range exceeds the element type, and the solver switches
-    // to the log domain.  Either way it then restarts from the initial scalings.
-    const int g = s->opt.use_graph;
-    s->opt.use_graph = 0;
-    st = run_iterations(s, 1);
-    s->opt.use_graph = g;
-    if (st != MMOT_OK) return fail(st);
-    const mmot_status fs = read_flags(s);
-    if (fs == MMOT_EINFEASIBLE || fs == MMOT_ENUMERIC) s->dom = MMOT_DOMAIN_LOG;
-    else if (fs != MMOT_OK) return fail(fs);
-    else s->probe_clean = true;
-    s->iters = 0;
-    s->psi_fresh = s->pend_b = s->pend_f = false;
-    s->force_calib = 0;
-    st = dispatch(s, [&](auto impl) { return decltype(impl)::setup(s, p); });
-    if (st != MMOT_OK) return fail(st);
-  }
+  st = create_into(s, p, o, ws, stream, nullptr, nullptr);
+  if (st != MMOT_OK) { mmot_destroy(s); return st; }
   *out = s;
   return MMOT_OK;
 }
@@ -1029,6 +1093,33 @@ mmot_status mmot_solve(mmot_solver* s, int32_t max_iter, mmot_stats* stats) {
     st = mmot_iterate(s, s->opt.polish_iters, &local);
   }
   if (stats) *stats = local;
+  return st;
+}
+
+mmot_status mmot_solve_static(const mmot_problem* p, const mmot_options* o, int32_t max_iter, double* occ,
+                              mmot_stats* stats, void* stream) {
+  if (!p || !o || max_iter < 0) return MMOT_EINVAL;
+  mmot_status st = basic_checks(p, o);
+  if (st != MMOT_OK) return st;
+  if (!p->cap || !p->src || !p->dst) return MMOT_EINVAL;
+  if (p->kind == MMOT_CSR && (!p->rowptr || !p->colidx || !p->cost)) return MMOT_EINVAL;
+  if (p->kind == MMOT_DENSE && !p->cost_dense) return MMOT_EINVAL;
+  size_t need = 0;
+  st = mmot_query_workspace(p, o, &need);
+  if (st != MMOT_OK) return st;
+  if (need > kStaticWorkspaceBytes) return MMOT_ENOMEM;
+  void* ws = nullptr;
+  st = scratch_address(&ws);
+  if (st != MMOT_OK) return st;
+  // the solver object and its host buffers live on this call's stack; no
+  // captured graphs (they would be instantiated, i.e. allocated)
+  double host_stats[16];
+  int host_flags[4];
+  mmot_solver s;
+  st = create_into(&s, p, o, ws, stream, host_stats, host_flags);
+  if (st == MMOT_OK) st = mmot_solve(&s, max_iter, stats);
+  if (st == MMOT_OK && occ) st = mmot_occupancy(&s, occ, nullptr);
+  release_solver(&s);
   return st;
 }
 
@@ -1149,10 +1240,7 @@ mmot_status mmot_set_log_duals(mmot_solver* s, const double* ls, const double* l
 
 void mmot_destroy(mmot_solver* s) {
   if (!s) return;
-  for (auto& kv : s->graphs) (void)hipGraphExecDestroy(kv.second);
-  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
-  if (s->host_stats) (void)hipHostFree(s->host_stats);
-  if (s->host_flags) (void)hipHostFree(s->host_flags);
+  release_solver(s);
   delete s;
 }
 
