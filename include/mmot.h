@@ -182,11 +182,12 @@ mmot_status mmot_occupancy_window(mmot_solver* s, double* occ, double* per_comm,
                                   int32_t comm_count);
 
 /* Aggregate edge flows (bi-marginal projections P_{t,t+1} summed over
- * commodities, eq. proj_discrete_bi): flow[t * nnz + e] = mass moving along
- * CSR entry e between times t and t+1, t = 0..T-1.  CSR problems only
- * (EUNSUPPORTED for dense ones).  cost_host (nullable): transport cost
- * <C, M> = move costs + interior state costs (eq. cost_multicommodity);
- * synchronises. */
+ * commodities, eq. proj_discrete_bi), t = 0..T-1.  CSR problems:
+ * flow[t * nnz + e] = mass moving along CSR entry e between times t and t+1.
+ * Dense problems: flow[(t * n + i) * n + j] = mass moving from state i to
+ * state j (T * n * n doubles, zero where C_ij = +INF), the commodity sum of
+ * each time one MFMA product.  cost_host (nullable): transport cost <C, M> =
+ * move costs + interior state costs (eq. cost_multicommodity); synchronises. */
 mmot_status mmot_edge_flows(mmot_solver* s, double* flow, double* cost_host);
 
 /* Natural-log dual scalings of the current iterate: log_src, log_dst (L x n,

@@ -71,6 +71,10 @@ void launch_dense_gibbs(const double*, int, int, double, float*, float*, void*, 
 void launch_dense_operand(int, int, const float*, const float*, uint16_t*, hipStream_t);
 void launch_dense_operand32(int, int, int, const float*, const float*, float*, hipStream_t);
 void launch_dense_rowsum_max(const float*, int, int, uint32_t*, hipStream_t);
+void launch_dense_flows(int, int, int, int, const float*, const float*, const float*, const float*, const double*,
+                        const double*, float*, const float*, double, double*, double*, int, hipStream_t);
+void launch_dense_state_cost(int, int, int, const float*, const float*, const float*, const float*, const double*,
+                             const double*, double, double*, int, hipStream_t);
 void launch_pool_tick(const TickArgs&, bool, hipStream_t);
 bool pool_item_is_light(const PoolItem&);
 
@@ -634,6 +638,37 @@ struct Impl {
     const size_t Lp = s->Lp, pstride = (size_t)s->nblk_s * kNSt;
     launch_prep_fwd<V, LOG>(T, s->Lp, 1, s->cf, s->sigf, s->sigb, static_cast<V*>(s->facf),
                             static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, s->lvl0, s->slotsS, s->nslot, st);
+    if (s->kind == MMOT_DENSE) {
+      // Dense network: F_t = K (.) (A_t B_{t+1}^T) per time on MFMA, A_t from the
+      // update-free forward recursion; flows as n x n per time, the move and state
+      // costs as block partials (field 0 and ST_SCOST of part_flow)
+      const int n = s->n, nt = (n + 127) / 128;
+      const int nb = std::min(nt * nt, s->nblk_s);
+      const float* ones = static_cast<const float*>(s->ones);
+      float* fab = s->levf;   // [2][Lp] commodity factors (calibration scratch, free outside sweeps)
+      if (s->dense_bf16)
+        launch_dense_operand(n, s->Lp, static_cast<const float*>(s->U01), nullptr, bbuf(s, 0), st);
+      else
+        launch_dense_operand32(n, s->n8, s->Lp, static_cast<const float*>(s->U01), nullptr, b32(s, 0), st);
+      for (int t = 0; t < T; ++t) {
+        const int tb = t + 1;
+        const float* A = reinterpret_cast<const float*>(t == 0 ? static_cast<V*>(s->U01) : zh(s, t));
+        const float* ua = t == 0 ? ones : reinterpret_cast<const float*>(uat(s, t));
+        const float* B = reinterpret_cast<const float*>(tb == T ? static_cast<V*>(s->U0T) : psi(s, tb));
+        const float* ub = tb == T ? ones : reinterpret_cast<const float*>(uat(s, tb));
+        launch_dense_flows(n, s->L, s->Lp, s->lda, A, ua, B, ub, s->sigf + (size_t)t * Lp, s->sigb + (size_t)tb * Lp,
+                           fab, s->Kd, s->eps, flow + (size_t)t * n * n, s->part_flow + (size_t)t * pstride, nb, st);
+        if (s->has_kl && t >= 1)
+          launch_dense_state_cost(n, s->L, s->Lp, reinterpret_cast<const float*>(zh(s, t)),
+                                  reinterpret_cast<const float*>(psi(s, t)), static_cast<const float*>(s->KL),
+                                  reinterpret_cast<const float*>(uat(s, t)), s->sigf + (size_t)t * Lp,
+                                  s->sigb + (size_t)t * Lp, s->eps, s->part_flow + (size_t)t * pstride, nb, st);
+        if (tb < T) dense_fwd(s, t, 1, false, nullptr, nullptr, st);
+      }
+      launch_reduce_cost(s->part_flow, s->part_flow, nb, nb, s->nblk_s, T, s->tpart_flow, s->tpart,
+                         s->stats_dev + 7, st);
+      return;
+    }
     for (int t = 0; t < T; ++t) {
       const V* xin = (t == 0) ? static_cast<const V*>(s->U01) : zh(s, t);
       const int tb = t + 1;
@@ -1153,7 +1188,6 @@ mmot_status mmot_occupancy(mmot_solver* s, double* occ, double* per_comm) {
 
 mmot_status mmot_edge_flows(mmot_solver* s, double* flow, double* cost_host) {
   if (!s || !flow) return MMOT_EINVAL;
-  if (s->kind != MMOT_CSR) return MMOT_EUNSUPPORTED;
   ensure_fresh(s);
   dispatch(s, [&](auto impl) { decltype(impl)::flows_pass(s, flow, s->stream); return 0; });
   if (hipGetLastError() != hipSuccess) return MMOT_EHIP;

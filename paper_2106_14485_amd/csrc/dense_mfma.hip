@@ -666,4 +666,154 @@ void launch_dense_rowsum_max(const float* K, int n, int lda, uint32_t* out, hipS
   hipLaunchKernelGGL(k_dense_rowsum_max, dim3(n), dim3(256), 0, s, K, n, lda, out);
 }
 
+// ---------------------------------------------------------------------------
+// outputs of a dense network: edge flows and transport cost
+// ---------------------------------------------------------------------------
+// Commodity factors of the flows at one time: the offsets of the two panels
+// (sa of A_t, sb of B_{t+1}, log2 units, FP64) split into two powers of two,
+// one per operand, so that neither factor leaves the FP32 range alone; zero for
+// the padding commodities l >= L.
+__global__ void k_flow_factors(const double* __restrict__ sa, const double* __restrict__ sb, int L, int Lp,
+                               float* __restrict__ fa, float* __restrict__ fb) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= Lp) return;
+  if (l >= L) { fa[l] = 0.f; fb[l] = 0.f; return; }
+  const double sg = sa[l] + sb[l];
+  const double ha = floor(0.5 * sg);
+  fa[l] = (float)exp2(ha);
+  fb[l] = (float)exp2(sg - ha);
+}
+
+// Edge flows of one time step (Theorem 5, eq. proj_discrete_bi) on a dense
+// network: F[i][j] = K_ij ua[i] ub[j] sum_l A[i][l] B[j][l] fa[l] fb[l], the
+// sum over commodities on MFMA (v_mfma_f32_32x32x2f32).  Both panels are
+// state-major ([n][Lp], commodities contiguous), so the product is A B^T with
+// the commodity as the contraction index; the two halves of a wave take the
+// first and the second four of every eight commodities (the order of the sum is
+// free), so each 16-byte load feeds four MFMA steps.  A block of four waves
+// owns 128 x 128 tiles of F (a wave 64 x 64: 2 x 2 MFMA tiles), taking tiles
+// b, b + nblk, ...; it writes F as doubles (row-major n x n, zero where K_ij = 0)
+// and its share of the move costs sum_ij C_ij F_ij (C_ij = -eps ln K_ij) into
+// field 0 of its stats partial.
+__global__ __launch_bounds__(256) void k_dense_flows(int n, int Lp, int lda, const float* __restrict__ A,
+                                                      const float* __restrict__ ua, const float* __restrict__ B,
+                                                      const float* __restrict__ ub, const float* __restrict__ fa,
+                                                      const float* __restrict__ fb, const float* __restrict__ K,
+                                                      double eps, double* __restrict__ flow, double* __restrict__ part) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1, lr = lane & 31, lh = lane >> 5;
+  const int nt = (n + 127) >> 7;
+  double cost = 0.0;
+  for (int tile = blockIdx.x; tile < nt * nt; tile += gridDim.x) {
+    const int i0 = (tile / nt) * 128 + wm * 64, j0 = (tile % nt) * 128 + wn * 64;
+    int ra[2], rb[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      ra[q] = min(i0 + q * 32 + lr, n - 1);
+      rb[q] = min(j0 + q * 32 + lr, n - 1);
+    }
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int p = 0; p < 2; ++p)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[q][p][r] = 0.f;
+    for (int l0 = 0; l0 < Lp; l0 += 8) {
+      const int lc = l0 + 4 * lh;
+      const bool lok = lc < Lp;           // Lp is a multiple of 4, not always of 8
+      const int lcc = lok ? lc : 0;
+      const float4 f4a = *reinterpret_cast<const float4*>(fa + lcc);
+      const float4 f4b = *reinterpret_cast<const float4*>(fb + lcc);
+      float4 av[2], bv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[q] = *reinterpret_cast<const float4*>(A + (size_t)ra[q] * Lp + lcc);
+        bv[q] = *reinterpret_cast<const float4*>(B + (size_t)rb[q] * Lp + lcc);
+      }
+      const float m = lok ? 1.f : 0.f;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[q].x *= f4a.x * m; av[q].y *= f4a.y * m; av[q].z *= f4a.z * m; av[q].w *= f4a.w * m;
+        bv[q].x *= f4b.x; bv[q].y *= f4b.y; bv[q].z *= f4b.z; bv[q].w *= f4b.w;
+      }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            const float x = s == 0 ? av[q].x : s == 1 ? av[q].y : s == 2 ? av[q].z : av[q].w;
+            const float y = s == 0 ? bv[p].x : s == 1 ? bv[p].y : s == 2 ? bv[p].z : bv[p].w;
+            acc[q][p] = __builtin_amdgcn_mfma_f32_32x32x2f32(x, y, acc[q][p], 0, 0, 0);
+          }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int j = j0 + p * 32 + lr;
+        const bool jok = j < n;
+        const double ubj = jok ? (double)ub[j] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = i0 + q * 32 + 8 * (r >> 2) + 4 * lh + (r & 3);
+          if (!jok || i >= n) continue;
+          const float kij = K[(size_t)i * lda + ipos32(j)];
+          const double F = (double)kij * (double)ua[i] * ubj * (double)acc[q][p][r];
+          flow[(size_t)i * n + j] = F;
+          if (F > 0.0) cost += -eps * log((double)kij) * F;
+        }
+      }
+  }
+  // block partial of the move costs (waves in order)
+  __shared__ double red[4];
+  for (int m = 32; m > 0; m >>= 1) cost += __shfl_xor(cost, m, 64);
+  if (lane == 0) red[wave] = cost;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[(size_t)blockIdx.x * kNSt] = ((red[0] + red[1]) + red[2]) + red[3];
+    part[(size_t)blockIdx.x * kNSt + ST_SCOST] = 0.0;   // (the state-cost kernel, where it runs, follows)
+  }
+}
+
+// State costs of one interior time on a dense network: sum_{i,l} C_L[i][l]
+// P_{0,t}[l][i], P_{0,t} = hatPsi_t (.) Psi_t (.) K_L (.) u_t (eq. proj_0t) with
+// zh = hatPsi_t (.) K_L and psi = Psi_t (.) K_L as stored and C_L = -eps ln K_L,
+// into field ST_SCOST of the block partials (nblk blocks, grid-stride, fixed order).
+__global__ __launch_bounds__(256) void k_dense_state_cost(int n, int L, int Lp, const float* __restrict__ zh,
+                                                           const float* __restrict__ psi, const float* __restrict__ kl,
+                                                           const float* __restrict__ u, const double* __restrict__ sa,
+                                                           const double* __restrict__ sb, double eps,
+                                                           double* __restrict__ part) {
+  double c = 0.0;
+  const size_t total = (size_t)n * Lp;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / Lp), l = (int)(e % Lp);
+    if (l >= L) continue;
+    const double k = (double)kl[e];
+    if (!(k > 0.0)) continue;
+    const double P = (double)zh[e] * (double)psi[e] / k * (double)u[i] * exp2(sa[l] + sb[l]);
+    if (P > 0.0) c += -eps * log(k) * P;
+  }
+  __shared__ double red[4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int m = 32; m > 0; m >>= 1) c += __shfl_xor(c, m, 64);
+  if (lane == 0) red[wave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNSt + ST_SCOST] = ((red[0] + red[1]) + red[2]) + red[3];
+}
+
+void launch_dense_flows(int n, int L, int Lp, int lda, const float* A, const float* ua, const float* B,
+                        const float* ub, const double* sa, const double* sb, float* fab, const float* K, double eps,
+                        double* flow, double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_flow_factors, dim3((Lp + 255) / 256), dim3(256), 0, s, sa, sb, L, Lp, fab, fab + Lp);
+  hipLaunchKernelGGL(k_dense_flows, dim3(nblk), dim3(256), 0, s, n, Lp, lda, A, ua, B, ub, fab, fab + Lp, K, eps,
+                     flow, part);
+}
+void launch_dense_state_cost(int n, int L, int Lp, const float* zh, const float* psi, const float* kl, const float* u,
+                             const double* sa, const double* sb, double eps, double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_state_cost, dim3(nblk), dim3(256), 0, s, n, L, Lp, zh, psi, kl, u, sa, sb, eps, part);
+}
+
 }  // namespace mmot

@@ -131,7 +131,9 @@ class Solver:
         return occ, pc
 
     def edge_flows(self):
-        flow = torch.empty((self.T, self.nnz), dtype=torch.float64, device=self.device)
+        """Flows (T x nnz for a sparse network, T x n x n for a dense one) and the transport cost."""
+        shape = (self.T, self.nnz) if self.inst.kind == "csr" else (self.T, self.n, self.n)
+        flow = torch.empty(shape, dtype=torch.float64, device=self.device)
         cost = ctypes.c_double(0.0)
         check(_lib.lib().mmot_edge_flows(self._h, _ptr(flow), ctypes.byref(cost)), "mmot_edge_flows")
         return flow, cost.value

@@ -318,6 +318,38 @@ def test_dense_fp32_iterates(n, L, T):
     assert abs(g["stats"]["dual_obj"] - o["g"][-1]) <= 1e-5 * abs(o["g"][-1])
 
 
+@pytest.mark.parametrize("state_costs", [False, True])
+def test_dense_edge_flows_and_cost(state_costs):
+    """Edge flows of a dense network, F_t[i, j] = K_ij sum_l A_t[l, i] B_{t+1}[l, j]
+    (Theorem 5, eq. proj_discrete_bi; an MFMA product per time), and the
+    transport cost with and without per-commodity state costs, iterate for
+    iterate against the oracle (FP32-rounded marginals, as the FP32 solver
+    represents them) to 1e-5.  n = 200 and L = 30 leave ragged tiles of the
+    128 x 128 flow tiles and of the eight-commodity steps."""
+    import dataclasses
+    inst = instances.dense_blob_instance(n=200, L=30, T=6, seed=17)
+    if state_costs:
+        rng = np.random.default_rng(4)
+        inst = dataclasses.replace(inst, state_cost=rng.uniform(0.0, 0.05, (inst.L, inst.n)))
+    p = to_oracle(inst)
+    p = alg2.make_problem(p.C, p.eps, p.T, inst.src.astype(np.float32).astype(np.float64),
+                          inst.dst.astype(np.float32).astype(np.float64), p.cap, p.state_cost)
+    ost = alg2.iterate(p, alg2.initial_state(p), 15)
+    ref = alg2.projections(p, ost)
+    S = _solver()(inst, precision="fp32", domain="auto")
+    S.iterate(15)
+    flows, cost = S.edge_flows()
+    flows = flows.cpu().numpy()
+    S.close()
+    assert flows.shape == (inst.T, inst.n, inst.n)
+    closed = ~np.isfinite(inst.cost_dense)
+    assert np.all(flows[:, closed] == 0.0)
+    for t in range(inst.T):
+        assert rel_l1(flows[t], ref["flows"][t]) <= 1e-5, (t, rel_l1(flows[t], ref["flows"][t]))
+    assert rel_l1(flows, np.stack(ref["flows"])) <= 1e-5
+    assert abs(cost - ref["cost"]) <= 1e-5 * abs(ref["cost"]), (cost, ref["cost"])
+
+
 def test_dense_fp32_against_exact_inputs_after_convergence():
     inst = instances.dense_blob_instance(n=300, L=40, T=8, seed=340)
     o = dense_oracle(inst, 100)
@@ -551,12 +583,18 @@ def test_dense_full_states_against_the_oracle(dense_full_states, precision):
         tol = 1e-5
     occ, pc = S.occupancy(per_commodity=True)
     occ, pc = occ.cpu().numpy(), pc.cpu().numpy()
+    flows, cost = S.edge_flows()
+    flows = flows.cpu().numpy()
     S.close()
     assert rel_l1(occ, ref["Pt"]) <= tol, rel_l1(occ, ref["Pt"])
     assert rel_l1(pc, ref["P0t"]) <= tol, rel_l1(pc, ref["P0t"])
     for l in range(inst.L):
         assert rel_l1(pc[:, l, :], ref["P0t"][:, l, :]) <= 2 * tol, l
     assert st["src_resid"] <= 1e-6 and st["cap_viol"] <= 1e-6, st
+    # edge flows F_t = K (.) (A_t^T B_{t+1}) and the transport cost
+    for t in range(inst.T):
+        assert rel_l1(flows[t], ref["flows"][t]) <= tol, (t, rel_l1(flows[t], ref["flows"][t]))
+    assert abs(cost - ref["cost"]) <= tol * abs(ref["cost"]), (cost, ref["cost"])
 
 
 # ---------------------------------------------------------------------------
