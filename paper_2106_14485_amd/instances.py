@@ -331,7 +331,8 @@ def road_grid_instance(side: int = 100, L: int = 2000, T: int = 120, eps: float 
     pairs further than T in Manhattan distance are redrawn.  Masses are
     lognormal(0, 0.5).  Origin/destination nodes are uncapacitated; relay nodes
     get base_cap_factor * mean mass, a seeded weak_frac of them weak_factor
-    times that.
+    times that.  States are labelled in Morton order of their grid position
+    (meta["grid_of"][k] = row-major grid id r * side + c of state k).
     """
     rng = np.random.default_rng(seed)
     n = side * side
@@ -348,7 +349,6 @@ def road_grid_instance(side: int = 100, L: int = 2000, T: int = 120, eps: float 
                 j = i + side
                 rows += [i, j]; cols += [j, i]; vals += [w, w]
     rows += list(range(n)); cols += list(range(n)); vals += [wait_cost] * n
-    rowptr, colidx, cost = _csr_from_pairs(n, np.array(rows), np.array(cols), np.array(vals))
     perm = rng.permutation(n)
     w = 1.0 / np.arange(1, n + 1) ** zipf_s
     p = w / w.sum()
@@ -371,9 +371,17 @@ def road_grid_instance(side: int = 100, L: int = 2000, T: int = 120, eps: float 
     weak = rng.choice(relay, size=int(round(weak_frac * len(relay))), replace=False)
     capv[weak] *= weak_factor
     capv[np.union1d(o, z)] = np.inf
+    # States relabelled in Morton (Z) order of their grid position (the draws above
+    # use row-major ids): the five rows a sweep step gathers for a state then lie
+    # close together in the panels.  A relabelling does not change the problem.
+    grid = np.arange(n)
+    order = _morton_order(np.stack([(grid % side + 0.5) / side, (grid // side + 0.5) / side], axis=1))
+    lab = np.empty(n, dtype=np.int64)
+    lab[order] = np.arange(n)
+    rowptr, colidx, cost = _csr_from_pairs(n, lab[np.array(rows)], lab[np.array(cols)], np.array(vals))
     return Instance(name=f"road{side}x{side}", n=n, L=L, T=T, eps=eps, kind="csr",
-                    src=src, dst=dst, cap=capv, rowptr=rowptr, colidx=colidx, cost=cost,
-                    meta=dict(seed=seed, origins=o, destinations=z, weak=weak))
+                    src=src[:, order], dst=dst[:, order], cap=capv[order], rowptr=rowptr, colidx=colidx, cost=cost,
+                    meta=dict(seed=seed, origins=lab[o], destinations=lab[z], weak=lab[weak], grid_of=order))
 
 
 # ----------------------------------------------------------------------------
