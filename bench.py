@@ -121,10 +121,11 @@ def cpu_baseline(inst, log_domain, budget_s=20.0):
                       f"sizing run (FP64 numpy/scipy log-sum-exp, single-threaded); {_host_cpu()}"}
 
 
-def serving_compare(requests, load, max_iter, budget_gb, nmax, lmax):
+def serving_compare(requests, load, max_iter, budget_gb, nmax, lmax, capacity=0.0, progress=0):
     """Served (continuous batching, the pool) vs plain one-at-a-time on the same
     seeded Poisson trace of the serving workload.  The plain solver's capacity is
-    measured first (everything queued at t = 0), the arrival rate is load x that."""
+    measured first (everything queued at t = 0) unless given; the arrival rate is
+    load x that."""
     import numpy as np
     from paper_2106_14485_amd import instances as I
     from paper_2106_14485_amd.serve import latency_summary, serve, serve_plain
@@ -132,12 +133,16 @@ def serving_compare(requests, load, max_iter, budget_gb, nmax, lmax):
     insts = [I.instance_from_request(r) for r in reqs]
     zero = np.zeros(len(insts))
     serve_plain(insts[:2], zero[:2], max_iter=max_iter)          # warm-up
-    res0, t_plain0 = serve_plain(insts, zero, max_iter=max_iter)
-    cap = len(insts) / t_plain0
+    if capacity > 0:
+        cap = capacity
+    else:
+        res0, t_plain0 = serve_plain(insts, zero, max_iter=max_iter, progress=progress)
+        cap = len(insts) / t_plain0
     gaps = np.random.default_rng(1).exponential(1.0 / (load * cap), size=len(insts))
     arrivals = np.cumsum(gaps) - gaps[0]
-    res_p, tp = serve_plain(insts, arrivals, max_iter=max_iter)
-    res_s, ts = serve(insts, arrivals, budget_bytes=int(budget_gb * (1 << 30)), max_iter=max_iter)
+    res_p, tp = serve_plain(insts, arrivals, max_iter=max_iter, progress=progress)
+    res_s, ts = serve(insts, arrivals, budget_bytes=int(budget_gb * (1 << 30)), max_iter=max_iter,
+                      progress=progress)
     sp, ss = latency_summary(res_p, tp), latency_summary(res_s, ts)
     def outcome(r):
         return (r["status"], r["stats"]["iters"] if r["status"] == 0 else None)
@@ -150,7 +155,8 @@ def serving_compare(requests, load, max_iter, budget_gb, nmax, lmax):
 
 
 def serving(args):
-    s = serving_compare(args.requests, args.load, args.max_iter, args.budget_gb, args.serve_nmax, args.serve_lmax)
+    s = serving_compare(args.requests, args.load, args.max_iter, args.budget_gb, args.serve_nmax, args.serve_lmax,
+                        capacity=args.plain_capacity, progress=100 if args.requests >= 200 else 0)
     out = {"metric": "p50/p99 solve latency, served vs plain", "value": s["served"]["p99_s"],
            "unit": "s (p99 latency)", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
            "config": {"workload": s["workload"], "offered_load": s["offered_load"],
@@ -210,6 +216,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=48,
                     help="requests of the bounded serving comparison added to a solver line (0: none)")
     ap.add_argument("--serve-load", type=float, default=1.5)
+    ap.add_argument("--plain-capacity", type=float, default=0.0,
+                    help="solves/s of the plain solver on the trace (serve workload; measured when 0)")
     ap.add_argument("--load", type=float, default=0.8)
     ap.add_argument("--max-iter", type=int, default=500)
     ap.add_argument("--budget-gb", type=float, default=96.0)

@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import collections
 import ctypes
+import sys
 import time
 
 import numpy as np
@@ -112,8 +113,14 @@ def _problem_sizes(inst):
     return p, marker
 
 
-def serve(instances, arrivals, budget_bytes, max_iter=500, ticks_per_round=32, check_every=10, tol=1e-6):
-    """Serve a trace with the pool.  Returns per-request dicts (latency, stats)."""
+def _progress(tag, done, total, t0):
+    print(f"[{tag}] {done}/{total} requests done after {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+
+def serve(instances, arrivals, budget_bytes, max_iter=500, ticks_per_round=32, check_every=10, tol=1e-6,
+          progress=0):
+    """Serve a trace with the pool.  Returns per-request dicts (latency, stats).
+    progress > 0: a line on stderr every `progress` finished requests."""
     order = np.argsort(arrivals, kind="stable")
     pending = collections.deque(int(i) for i in order)
     pool = Pool(budget_bytes, check_every=check_every, tol=tol)
@@ -143,6 +150,8 @@ def serve(instances, arrivals, budget_bytes, max_iter=500, ticks_per_round=32, c
                     i = active.pop(tk)
                     done[i] = dict(latency=time.perf_counter() - t0 - arrivals[i], stats=st, status=status)
                     pool.release(tk)
+                    if progress and len(done) % progress == 0:
+                        _progress("served", len(done), len(instances), t0)
         elif pending:
             wait = arrivals[pending[0]] - (time.perf_counter() - t0)
             if wait > 0:
@@ -152,7 +161,7 @@ def serve(instances, arrivals, budget_bytes, max_iter=500, ticks_per_round=32, c
     return [done[i] for i in range(len(instances))], total
 
 
-def serve_plain(instances, arrivals, max_iter=500, check_every=10, tol=1e-6):
+def serve_plain(instances, arrivals, max_iter=500, check_every=10, tol=1e-6, progress=0):
     """One solve at a time, in arrival order, with the plain solver."""
     order = np.argsort(arrivals, kind="stable")
     out = [None] * len(instances)
@@ -172,6 +181,9 @@ def serve_plain(instances, arrivals, max_iter=500, check_every=10, tol=1e-6):
         except MmotError as e:              # the request fails; the service goes on
             status = e.status
         out[i] = dict(latency=time.perf_counter() - t0 - arrivals[i], stats=st, status=status)
+        ndone = sum(1 for r in out if r is not None)
+        if progress and ndone % progress == 0:
+            _progress("plain", ndone, len(instances), t0)
     return out, time.perf_counter() - t0
 
 
