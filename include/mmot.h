@@ -81,10 +81,12 @@ typedef struct mmot_problem {
   const double* src;
   const double* dst;
   /* 1: a time-varying network (Section 3.3, one cost matrix C_tau per move
-   * tau -> tau+1): cost holds T x nnz values, row tau for the moves from time
-   * tau to tau+1, all with the pattern of rowptr/colidx; an entry may be +INF
-   * to close that move at that step.  CSR only (EUNSUPPORTED for dense).
-   * 0: cost holds nnz values used at every step (finite). */
+   * tau -> tau+1).  CSR: cost holds T x nnz values, row tau for the moves from
+   * time tau to tau+1, all with the pattern of rowptr/colidx; an entry may be
+   * +INF to close that move at that step.  Dense: cost_dense holds T x n x n
+   * values (matrix tau for the move tau -> tau+1; the workspace then holds T
+   * copies of K and K^T).  0: cost holds nnz values used at every step
+   * (finite), cost_dense one n x n matrix. */
   int32_t cost_per_step;
   /* Commodity-dependent capacities (the extension at the end of Section 3):
    * P_{0,t}[l, i] <= D_t[l, i] at the interior times, D >= 0, +INF = no bound,

@@ -292,7 +292,7 @@ void carve(mmot_solver* s, Carver& c) {
   s->ell_kv_b = takev(ell);
   s->ell_kv_f = takev(ell);
   if (dense) {
-    const size_t nn = n * (size_t)s->lda;
+    const size_t nn = ks * n * (size_t)s->lda;   // one K (and K^T) per move for a time-varying network
     s->Kd = c.take<float>(nn);
     s->Ktd = c.take<float>(nn);
     s->Kb = s->has_bf16 ? static_cast<void*>(c.take<uint16_t>(nn)) : nullptr;
@@ -317,7 +317,6 @@ mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
   if (p->cap_comm_per_step != 0 && p->cap_comm_per_step != 1) return MMOT_EINVAL;
   if (p->cap_comm && p->kind == MMOT_DENSE) return MMOT_EUNSUPPORTED;   // commodity capacities: sparse path
   if (p->kind == MMOT_DENSE) {
-    if (p->cost_per_step) return MMOT_EUNSUPPORTED;   // per-step dense costs: not built
     // dense products run on MFMA in the scaled domain, FP32 or BF16 (+ FP32 polish)
     if (o->precision != MMOT_FP32 && o->precision != MMOT_BF16) return MMOT_EUNSUPPORTED;
     if (o->domain == MMOT_DOMAIN_LOG) return MMOT_EUNSUPPORTED;
@@ -374,12 +373,17 @@ struct Impl {
     return a;
   }
 
-  static GemmArgs gemm_base(mmot_solver* s, bool forward_op) {
+  // K (and K^T) of the move t -> t+1: one of T for a time-varying network
+  static size_t kofs(mmot_solver* s, int t) {
+    return (s->steps_k > 1 ? (size_t)t : 0) * (size_t)s->n * s->lda;
+  }
+  static GemmArgs gemm_base(mmot_solver* s, bool forward_op, int t) {
     GemmArgs g;
     std::memset(&g, 0, sizeof(g));
     g.n = s->n; g.Lp = s->Lp; g.L = s->L; g.lda = s->lda; g.n8 = s->n8;
-    if (s->dense_bf16) g.A = forward_op ? s->Ktb : s->Kb;
-    else g.A = forward_op ? static_cast<const void*>(s->Ktd) : static_cast<const void*>(s->Kd);
+    const size_t o = kofs(s, t);
+    if (s->dense_bf16) g.A = static_cast<const uint16_t*>(forward_op ? s->Ktb : s->Kb) + o;
+    else g.A = (forward_op ? s->Ktd : s->Kd) + o;
     g.nslot = s->nslot;
     return g;
   }
@@ -393,7 +397,7 @@ struct Impl {
   static uint16_t* bbuf(mmot_solver* s, int t) { return s->Bbuf[t & 1]; }
   static float* b32(mmot_solver* s, int t) { return s->B32buf[t & 1]; }
   static void dense_bwd(mmot_solver* s, int t, bool calib, hipStream_t st) {
-    GemmArgs g = gemm_base(s, false);
+    GemmArgs g = gemm_base(s, false, t);
     if (s->dense_bf16) {
       g.Bb = bbuf(s, t + 1);
       if (t >= 1) { g.bout = bbuf(s, t); g.uo = reinterpret_cast<const float*>(uat(s, t)); }
@@ -414,7 +418,7 @@ struct Impl {
   static void dense_fwd(mmot_solver* s, int t, int mode, bool calib, double* occ, double* pcomm, hipStream_t st) {
     const int T = s->T, to = t + 1;
     const size_t Lp = s->Lp, pstride = (size_t)s->nblk_s * kNSt;
-    GemmArgs g = gemm_base(s, true);
+    GemmArgs g = gemm_base(s, true, t);
     if (s->dense_bf16) g.Bb = bbuf(s, t);
     else g.B32 = b32(s, t);
     g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facf) + (size_t)to * Lp);
@@ -601,7 +605,7 @@ struct Impl {
     HIPCK(hipEventCreate(&e1));
     auto launch_at = [&](int t) {
       if (s->kind == MMOT_DENSE) {
-        GemmArgs g = gemm_base(s, fwd != 0);
+        GemmArgs g = gemm_base(s, fwd != 0, t);
         if (s->dense_bf16) g.Bb = bbuf(s, t + 1);   // the operand form of the sweep's products
         else g.B32 = b32(s, t + 1);
         g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
@@ -657,7 +661,8 @@ struct Impl {
         const float* B = reinterpret_cast<const float*>(tb == T ? static_cast<V*>(s->U0T) : psi(s, tb));
         const float* ub = tb == T ? ones : reinterpret_cast<const float*>(uat(s, tb));
         launch_dense_flows(n, s->L, s->Lp, s->lda, A, ua, B, ub, s->sigf + (size_t)t * Lp, s->sigb + (size_t)tb * Lp,
-                           fab, s->Kd, s->eps, flow + (size_t)t * n * n, s->part_flow + (size_t)t * pstride, nb, st);
+                           fab, s->Kd + kofs(s, t), s->eps, flow + (size_t)t * n * n,
+                           s->part_flow + (size_t)t * pstride, nb, st);
         if (s->has_kl && t >= 1)
           launch_dense_state_cost(n, s->L, s->Lp, reinterpret_cast<const float*>(zh(s, t)),
                                   reinterpret_cast<const float*>(psi(s, t)), static_cast<const float*>(s->KL),
@@ -692,7 +697,7 @@ struct Impl {
     launch_validate_vals(p->cap, p->cap_per_step ? Tm1 * n : n, 1, 1, 0, s->flags, st);
     const bool dense = s->kind == MMOT_DENSE;
     if (!dense) launch_validate_vals(p->cost, (size_t)s->steps_k * nnz, s->steps_k > 1 ? 1 : 0, 0, 1, s->flags, st);
-    else launch_validate_vals(p->cost_dense, n * n, 1, 0, 1, s->flags, st);
+    else launch_validate_vals(p->cost_dense, (size_t)s->steps_k * n * n, 1, 0, 1, s->flags, st);
     if (p->state_cost) launch_validate_vals(p->state_cost, n * L, 0, 0, 1, s->flags, st);
     if (p->cap_comm) launch_validate_vals(p->cap_comm, (size_t)s->comm_steps * L * n, 1, 0, 0, s->flags, st);
     if (!dense) launch_validate_csr(p->rowptr, p->colidx, s->n, s->nnz, s->flags, st);
@@ -702,10 +707,16 @@ struct Impl {
     if (*s->host_flags) return MMOT_EINVAL;
     launch_fill<uint32_t>(s->rho, 2, 0u, st);
     if (dense) {
-      // K = exp(-C/eps) (+inf -> 0) and K^T, FP32 and optionally BF16
-      launch_dense_gibbs(p->cost_dense, s->n, s->lda, s->eps, s->Kd, s->Ktd, s->Kb, s->Ktb, st);
-      launch_dense_rowsum_max(s->Kd, s->n, s->lda, s->rho, st);
-      launch_dense_rowsum_max(s->Ktd, s->n, s->lda, s->rho + 1, st);
+      // K = exp(-C/eps) (+inf -> 0) and K^T, FP32 and optionally BF16; one per move
+      // for a time-varying network (Section 3.3)
+      for (int k = 0; k < s->steps_k; ++k) {
+        const size_t o = kofs(s, k);
+        launch_dense_gibbs(p->cost_dense + (size_t)k * n * n, s->n, s->lda, s->eps, s->Kd + o, s->Ktd + o,
+                           s->Kb ? static_cast<void*>(static_cast<uint16_t*>(s->Kb) + o) : nullptr,
+                           s->Ktb ? static_cast<void*>(static_cast<uint16_t*>(s->Ktb) + o) : nullptr, st);
+        launch_dense_rowsum_max(s->Kd + o, s->n, s->lda, s->rho, st);
+        launch_dense_rowsum_max(s->Ktd + o, s->n, s->lda, s->rho + 1, st);
+      }
     } else {
       // operators: backward = rows of K (input order), forward = rows of K^T
       HIPCK(hipMemcpyAsync(s->rp_b, p->rowptr, (n + 1) * sizeof(int), hipMemcpyDeviceToDevice, st));

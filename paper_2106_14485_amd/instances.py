@@ -534,7 +534,11 @@ def time_varying_instance(base: Instance, seed: int = 0, peak: float = 1.5, clos
     smooth rush-hour profile rush(tau) = sin^2(pi tau / T) (waiting keeps its
     cost); a seeded closed_frac of the state pairs have both directions closed
     (+inf) during one window of closed_span * T consecutive steps at a seeded
-    start.  The source/sink draws of the base instance are kept."""
+    start.  The source/sink draws of the base instance are kept.  A dense
+    instance gets the same profile on its finite moves, its costs of shape
+    (T, n, n)."""
+    if base.kind == "dense":
+        return _time_varying_dense(base, seed, peak, closed_frac, closed_span)
     assert base.kind == "csr"
     rng = np.random.default_rng(seed)
     T = base.T
@@ -554,6 +558,26 @@ def time_varying_instance(base: Instance, seed: int = 0, peak: float = 1.5, clos
         t0 = int(rng.integers(0, max(1, T - span + 1)))
         cost[t0:t0 + span, pair_id == pid] = np.inf
     return dataclasses.replace(base, name=base.name + "-tv", cost=cost, meta={**base.meta, "closed_pairs": shut})
+
+
+def _time_varying_dense(base: Instance, seed, peak, closed_frac, closed_span) -> Instance:
+    rng = np.random.default_rng(seed)
+    T, n = base.T, base.n
+    C0 = base.cost_dense
+    move = np.isfinite(C0) & ~np.eye(n, dtype=bool)
+    rush = np.sin(np.pi * np.arange(T) / max(T, 1)) ** 2
+    cost = np.repeat(C0[None, :, :], T, axis=0)
+    for t in range(T):
+        cost[t][move] *= 1.0 + peak * rush[t]
+    iu, ju = np.nonzero(np.triu(move, 1))
+    shut = rng.choice(len(iu), size=int(round(closed_frac * len(iu))), replace=False)
+    span = max(1, int(round(closed_span * T)))
+    for q in shut:
+        t0 = int(rng.integers(0, max(1, T - span + 1)))
+        cost[t0:t0 + span, iu[q], ju[q]] = np.inf
+        cost[t0:t0 + span, ju[q], iu[q]] = np.inf
+    return dataclasses.replace(base, name=base.name + "-tv", cost_dense=cost,
+                               meta={**base.meta, "closed_pairs": np.stack([iu[shut], ju[shut]], axis=1)})
 
 
 def staggered_instance(base: Instance, enter: np.ndarray, leave: np.ndarray) -> Instance:

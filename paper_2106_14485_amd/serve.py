@@ -103,7 +103,7 @@ def _problem_sizes(inst):
     p.n, p.L, p.T, p.eps = inst.n, inst.L, inst.T, float(inst.eps)
     p.kind = _lib.MMOT_CSR if inst.kind == "csr" else _lib.MMOT_DENSE
     p.nnz = inst.nnz
-    p.cost_per_step = 1 if inst.kind == "csr" and np.ndim(inst.cost) == 2 else 0
+    p.cost_per_step = 1 if (np.ndim(inst.cost) == 2 if inst.kind == "csr" else np.ndim(inst.cost_dense) == 3) else 0
     marker = np.zeros(1)
     if inst.state_cost is not None:
         p.state_cost = marker.ctypes.data

@@ -59,6 +59,7 @@ def device_problem(inst, device="cuda"):
         keep.append(cd)
         p.cost_dense = _ptr(cd)
         p.nnz = int(np.isfinite(inst.cost_dense).sum())
+        p.cost_per_step = 1 if np.ndim(inst.cost_dense) == 3 else 0   # (T, n, n): time-varying network
     cap = dt(inst.cap, torch.float64)
     p.cap_per_step = 1 if inst.cap.ndim == 2 else 0
     src, dst = dt(inst.src, torch.float64), dt(inst.dst, torch.float64)

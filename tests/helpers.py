@@ -7,7 +7,10 @@ from paper_2106_14485_amd.instances import Instance
 
 
 def to_oracle(inst: Instance) -> alg2.Problem:
-    C = inst.cost_csr() if inst.kind == "csr" else inst.cost_dense
+    if inst.kind == "csr":
+        C = inst.cost_csr()
+    else:   # a time-varying dense network: one cost matrix per move
+        C = list(inst.cost_dense) if np.ndim(inst.cost_dense) == 3 else inst.cost_dense
     return alg2.make_problem(C, inst.eps, inst.T, inst.src, inst.dst, inst.cap, inst.state_cost, inst.cap_comm)
 
 

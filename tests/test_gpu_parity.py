@@ -350,6 +350,38 @@ def test_dense_edge_flows_and_cost(state_costs):
     assert abs(cost - ref["cost"]) <= 1e-5 * abs(ref["cost"]), (cost, ref["cost"])
 
 
+def test_dense_time_varying_network():
+    """A dense network with one cost matrix per move (Section 3.3: rush-hour
+    costs, some moves closed for a window of steps): T copies of K and K^T on the
+    device, each product with its step's matrix; iterate for iterate against the
+    oracle with the list of per-step matrices (FP32-rounded marginals), occupancy,
+    per-commodity marginals, flows and cost to 1e-5."""
+    base = instances.dense_blob_instance(n=200, L=30, T=6, seed=19)
+    inst = instances.time_varying_instance(base, seed=2, closed_frac=0.05)
+    assert inst.cost_dense.shape == (6, 200, 200)
+    p = to_oracle(inst)
+    p = alg2.make_problem(p.C, p.eps, p.T, inst.src.astype(np.float32).astype(np.float64),
+                          inst.dst.astype(np.float32).astype(np.float64), p.cap)
+    ost = alg2.iterate(p, alg2.initial_state(p), 15)
+    ref = alg2.projections(p, ost)
+    S = _solver()(inst, precision="fp32", domain="auto")
+    S.iterate(15)
+    occ, pc = S.occupancy(per_commodity=True)
+    occ, pc = occ.cpu().numpy(), pc.cpu().numpy()
+    flows, cost = S.edge_flows()
+    flows = flows.cpu().numpy()
+    S.close()
+    assert rel_l1(occ, ref["Pt"]) <= 1e-5
+    assert rel_l1(pc, ref["P0t"]) <= 1e-5
+    for t in range(inst.T):
+        assert rel_l1(flows[t], ref["flows"][t]) <= 1e-5, t
+        assert np.all(flows[t][~np.isfinite(inst.cost_dense[t])] == 0.0)
+    assert abs(cost - ref["cost"]) <= 1e-5 * abs(ref["cost"])
+    # the per-step matrices matter: the first step's network alone gives other marginals
+    fixed = alg2.make_problem(p.C[0], p.eps, p.T, p.src, p.dst, p.cap)
+    assert rel_l1(alg2.projections(fixed, ost, want_flows=False)["P0t"], ref["P0t"]) > 1e-3
+
+
 def test_dense_fp32_against_exact_inputs_after_convergence():
     inst = instances.dense_blob_instance(n=300, L=40, T=8, seed=340)
     o = dense_oracle(inst, 100)

@@ -67,6 +67,38 @@ def test_time_varying_projections_match_full_tensor(seed):
     assert rel_l1(alg2.projections(fixed, st)["P0t"], out["P0t"]) > 1e-3
 
 
+@pytest.mark.parametrize("seed", [0, 1])
+def test_time_varying_dense_projections_match_full_tensor(seed):
+    """The same pin with dense per-step cost matrices (+inf closing a move at a
+    step): message passing, per-commodity marginals, flows (dense K_tau times a
+    matrix product) and the transport cost against the explicit tensor."""
+    p0, C0 = random_tiny(n=4, T=4, L=3, seed=seed, kind="dense")
+    rng = np.random.default_rng(300 + seed)
+    Cs = []
+    for tau in range(p0.T):
+        c = np.where(np.isfinite(C0), rng.uniform(0.0, 1.0, C0.shape), np.inf)
+        shut = (rng.random(C0.shape) < 0.15) & ~np.eye(p0.n, dtype=bool)
+        c[shut] = np.inf
+        Cs.append(c)
+    p = alg2.make_problem(Cs, p0.eps, p0.T, p0.src, p0.dst, p0.cap, p0.state_cost)
+    st = alg2.initial_state(p)
+    st.U01 = rng.uniform(0.2, 2.0, (p.L, p.n)) * (p.src > 0)
+    st.U0T = rng.uniform(0.2, 2.0, (p.L, p.n)) * (p.dst > 0)
+    st.u = rng.uniform(0.1, 1.0, st.u.shape)
+    out = alg2.projections(p, st)
+    Ks = alg2.gibbs(p)
+    M = bruteforce.full_tensor(Ks, alg2.gibbs_state(p), st.U01, st.U0T, st.u, p.T)
+    P0t, Pt, pairs = bruteforce.tensor_projections(M, p.T)
+    for tau in range(p.T + 1):
+        assert rel_l1(out["P0t"][tau], P0t[tau]) < 1e-13
+    for tau in range(p.T):
+        assert rel_l1(dense_flow(out["flows"][tau]), pairs[tau]) < 1e-13
+        assert np.all(dense_flow(out["flows"][tau])[~np.isfinite(Cs[tau])] == 0.0)
+    brute = sum((np.where(Ks[tau] > 0, Cs[tau], 0.0) * pairs[tau]).sum() for tau in range(p.T))
+    brute += sum((p.state_cost * P0t[tau]).sum() for tau in range(1, p.T))
+    assert abs(out["cost"] - brute) <= 1e-12 * abs(brute)
+
+
 @pytest.mark.parametrize("seed,T", [(0, 3), (3, 4)])
 def test_time_varying_iterates_match_tensor_sinkhorn(seed, T):
     p0, _ = random_tiny(n=4, T=T, L=2, seed=seed, cap_scale=0.35, state_cost=False)
