@@ -38,6 +38,9 @@ TRAFFIC = {
     "road100": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
                 "sha256": "282773a11b63e797f7e589abce81adea26efd989a4614ea7d087df1768842907",
                 "fetch_kib": 98622.525, "write_kib": 79550.804, "fetch_scale": 2.0, "write_scale": 1.0},
+    "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
+                "sha256": "282773a11b63e797f7e589abce81adea26efd989a4614ea7d087df1768842907",
+                "fetch_kib": 2402.094, "write_kib": 2007.938, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
