@@ -270,7 +270,10 @@ mmot_status mmot_solve_static(const mmot_problem* prob, const mmot_options* opt,
  *  - dedicated lane (steps that fill the GPU alone): such requests run one at
  *    a time, in admission order, with their own captured iteration graphs on
  *    a pool-owned stream, next to the batched lane (two of them together would
- *    only stretch both).
+ *    only stretch both);
+ *  - express lanes (two): a small request admitted while fewer than two
+ *    requests run in the batched lane replays its own graphs on a pool-owned
+ *    stream instead (alone, that finishes sooner than one kernel per tick).
  * Either way a request's schedule is exactly the one mmot_solve would run
  * (check_every iterations, then a convergence check, until converged or
  * max_iter), so its result is bitwise the same alone, in any mix, and as a

@@ -1312,11 +1312,15 @@ struct mmot_pool {
   size_t budget = 0, used = 0;
   hipStream_t stream = nullptr;       // batched lane: the tick launches
   hipStream_t setup = nullptr;        // admission work (validation, operators, probe)
-  static constexpr int kLanes = 3;    // dedicated lanes: solves whose steps fill the GPU alone
+  // Dedicated lanes (a solve's own captured graphs on a pool stream): lane 0 for
+  // solves whose steps fill the GPU alone -- one at a time, in arrival order,
+  // beside the batched lane (two together would only stretch both) -- and
+  // express lanes 1..kLanes-1 for small solves admitted while the batched lane
+  // is nearly idle: alone, a small solve finishes sooner replaying its own
+  // graphs than advancing one kernel per tick; under load it joins the ticks.
+  static constexpr int kLanes = 3;
+  static constexpr int kExpressBelow = 2;   // batched requests running, at most, to use an express lane
   hipStream_t lanes[kLanes] = {nullptr, nullptr, nullptr};
-  // Large solves run one at a time, in arrival order, beside the batched lane:
-  // each already fills the GPU, so running two together only stretches both.
-  static constexpr int kLaneActive = 1;
   std::deque<uint64_t> lane_queue;    // admitted large solves waiting for a lane
   uint64_t next_ticket = 1;
   struct Req {
@@ -1497,9 +1501,26 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
   if (hipEventCreateWithFlags(&r->up_ev, hipEventDisableTiming) != hipSuccess) {
     mmot_destroy(s); (void)hipEventDestroy(r->ev); delete r; return MMOT_EHIP;
   }
+  int express = -1;
+  if (s->nblk < kFillBlocks) {
+    int batched = 0;
+    bool used[mmot_pool::kLanes] = {};
+    for (auto& kv : P->reqs) {
+      const mmot_pool::Req* q = kv.second;
+      if (q->state != 0) continue;
+      if (q->lane == -1) ++batched;
+      else if (q->lane > 0) used[q->lane] = true;
+    }
+    for (int i = 1; i < mmot_pool::kLanes && express < 0 && batched < mmot_pool::kExpressBelow; ++i)
+      if (!used[i]) express = i;
+  }
   if (s->nblk >= kFillBlocks) {
-    r->lane = -2;                      // started by mmot_pool_run when a lane is free
+    r->lane = -2;                      // started by mmot_pool_run when lane 0 is free
     P->lane_queue.push_back(r->ticket);
+  } else if (express > 0) {
+    r->lane = express;
+    s->stream = P->lanes[express];
+    st = lane_chunk(r);
   } else {
     s->stream = P->stream;
     st = pool_program(P, r);
@@ -1519,26 +1540,26 @@ mmot_status mmot_pool_run(mmot_pool* P, int32_t max_ticks, int32_t* n_running) {
   if (!P || max_ticks < 0) return MMOT_EINVAL;
   for (int tk = 0; tk < max_ticks; ++tk) {
     // chunks whose statistics have landed: decide and schedule the next chunk
-    int lanes_busy = 0;
+    bool large_busy = false;
     for (auto& kv : P->reqs) {
       mmot_pool::Req* r = kv.second;
       if (r->state == 0 && r->awaiting && hipEventQuery(r->ev) == hipSuccess) {
         const mmot_status st = pool_finish_chunk(P, r);
         if (st != MMOT_OK) { r->state = 2; r->status = st; }
       }
-      lanes_busy += (r->state == 0 && r->lane >= 0);
+      large_busy = large_busy || (r->state == 0 && r->lane == 0);
     }
-    // start waiting large solves, oldest first, while lanes are free
-    while (lanes_busy < mmot_pool::kLaneActive && !P->lane_queue.empty()) {
+    // start the oldest waiting large solve when lane 0 is free
+    while (!large_busy && !P->lane_queue.empty()) {
       auto it = P->reqs.find(P->lane_queue.front());
       P->lane_queue.pop_front();
       if (it == P->reqs.end() || it->second->state != 0) continue;
       mmot_pool::Req* r = it->second;
-      r->lane = lanes_busy;
-      r->s->stream = P->lanes[r->lane];
+      r->lane = 0;
+      r->s->stream = P->lanes[0];
       const mmot_status st = lane_chunk(r);
       if (st != MMOT_OK) { r->state = 2; r->status = st; r->s->stream = P->stream; continue; }
-      ++lanes_busy;
+      large_busy = true;
     }
     // one tick of the batched lane: the next item of up to kTickSlots batched
     // requests, taken round-robin among those with an item ready; a request
