@@ -92,7 +92,8 @@ typedef struct mmot_problem {
    * P_{0,t}[l, i] <= D_t[l, i] at the interior times, D >= 0, +INF = no bound,
    * 0 closes state i to commodity l.  L x n values used at every interior
    * time (cap_comm_per_step = 0) or (T-1) x L x n (index ((t-1)*L + l)*n + i,
-   * cap_comm_per_step = 1).  NULL = none.  CSR only (EUNSUPPORTED for dense).
+   * cap_comm_per_step = 1).  NULL = none.  Sparse and dense networks (dense:
+   * w_t is applied in the epilogue of the forward and backward products).
    * Each adds one dual scaling w_t (L x n, in [0, 1]) per interior time; see
    * mmot_get_comm_duals. */
   const double* cap_comm;

@@ -62,8 +62,7 @@ void launch_reduce_cost(const double*, const double*, int, int, int, int, double
 void launch_gemm(const GemmArgs&, bool, hipStream_t);
 int gemm_col_tiles(int);
 void launch_dense_rows(int, int, const float*, const float*, float*, int, double*, double*, const float*, uint16_t*,
-                       float*, int, int,
-                       int, hipStream_t);
+                       float*, int, int, int, const double*, int, hipStream_t);
 void launch_dense_sink(int, int, int, const float*, const float*, float*, int, const double*, const double*,
                        uint32_t*, int, uint32_t*, size_t, int*, double*, double*, double*, int, int, int,
                        hipStream_t);
@@ -73,8 +72,10 @@ void launch_dense_operand32(int, int, int, const float*, const float*, float*, h
 void launch_dense_rowsum_max(const float*, int, int, uint32_t*, hipStream_t);
 void launch_dense_flows(int, int, int, int, const float*, const float*, const float*, const float*, const double*,
                         const double*, float*, const float*, double, double*, double*, int, hipStream_t);
-void launch_dense_state_cost(int, int, int, const float*, const float*, const float*, const float*, const double*,
-                             const double*, double, double*, int, hipStream_t);
+void launch_dense_state_cost(int, int, int, const float*, const float*, const float*, const float*, const float*,
+                             const double*, const double*, double, double*, int, hipStream_t);
+void launch_dense_comm_stats(int, int, int, const float*, const float*, const float*, const float*, const float*,
+                             const float*, const double*, const double*, double*, int, hipStream_t);
 void launch_pool_tick(const TickArgs&, bool, hipStream_t);
 bool pool_item_is_light(const PoolItem&);
 
@@ -154,6 +155,7 @@ struct mmot_solver {
   float *levb = nullptr, *levf = nullptr;
   double *part = nullptr, *tpart = nullptr, *stats_dev = nullptr, *masses = nullptr;
   double *part_flow = nullptr, *tpart_flow = nullptr;
+  double* part_cc = nullptr;   // dense check pass: commodity-capacity partials of the product's blocks
   double *exc_row = nullptr, *exc = nullptr;
   int* exc_cnt = nullptr;
   int* flags = nullptr;
@@ -192,7 +194,8 @@ namespace {
 
 int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
 constexpr int64_t kStepWaves = 2048;    // a sweep step of fewer waves (two per SIMD) splits its rows
-constexpr int kEllMax = 16;    // widest ELL row (one gather batch); wider graphs use CSR
+constexpr int kEllMax = 16;
+constexpr int kDenseCommBlocks = 256;   // blocks of a dense check pass's commodity-capacity statistics    // widest ELL row (one gather batch); wider graphs use CSR
 
 void set_geometry(mmot_solver* s) {
   s->vsize = (s->prec == MMOT_FP64) ? 8 : 4;
@@ -298,6 +301,8 @@ void carve(mmot_solver* s, Carver& c) {
     s->Kb = s->has_bf16 ? static_cast<void*>(c.take<uint16_t>(nn)) : nullptr;
     s->Ktb = s->has_bf16 ? static_cast<void*>(c.take<uint16_t>(nn)) : nullptr;
     s->part_s = c.take<float>((size_t)s->ntn * n);
+    // commodity-capacity terms of a check-pass product, one partial per product block
+    s->part_cc = s->has_comm ? c.take<double>((size_t)kDenseCommBlocks * kNSt) : nullptr;
     s->n8 = (int)((n + 63) / 64 * 64);
     for (int i = 0; i < 2; ++i)
       s->Bbuf[i] = s->has_bf16 ? c.take<uint16_t>((size_t)s->n8 * Lp) : nullptr;
@@ -315,7 +320,6 @@ mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
   if (p->kind != MMOT_CSR && p->kind != MMOT_DENSE) return MMOT_EINVAL;
   if (p->cost_per_step != 0 && p->cost_per_step != 1) return MMOT_EINVAL;
   if (p->cap_comm_per_step != 0 && p->cap_comm_per_step != 1) return MMOT_EINVAL;
-  if (p->cap_comm && p->kind == MMOT_DENSE) return MMOT_EUNSUPPORTED;   // commodity capacities: sparse path
   if (p->kind == MMOT_DENSE) {
     // dense products run on MFMA in the scaled domain, FP32 or BF16 (+ FP32 polish)
     if (o->precision != MMOT_FP32 && o->precision != MMOT_BF16) return MMOT_EUNSUPPORTED;
@@ -407,6 +411,7 @@ struct Impl {
     g.fac = reinterpret_cast<const float*>(static_cast<V*>(s->facb) + (size_t)t * s->Lp);
     g.out = reinterpret_cast<float*>(psi(s, t));
     g.kl = (s->has_kl && t >= 1) ? static_cast<const float*>(s->KL) : nullptr;
+    g.cw = reinterpret_cast<const float*>(wat(s, t));
     g.slots = calib ? s->slots_b + (size_t)t * s->Lp : nullptr;
     g.slot_stride = (size_t)(s->T + 1) * s->Lp;
     launch_gemm(g, s->dense_bf16, st);
@@ -437,14 +442,31 @@ struct Impl {
         g.pc_lo = s->pc_lo;
         g.pc_cnt = s->pc_cnt;
       }
+      if (s->has_comm) {
+        // commodity capacities: w_to multiplied in; the update projects it with the u_to
+        // of the last sweep (still in place: the row kernel after the product updates u)
+        g.cw = reinterpret_cast<const float*>(wat(s, to));
+        g.dc = reinterpret_cast<const float*>(dat(s, to));
+        g.ucur = reinterpret_cast<const float*>(uat(s, to));
+        if (mode == 0) {
+          g.cc_update = 1;
+          g.cwo = reinterpret_cast<float*>(wat(s, to));
+        }
+      }
       launch_gemm(g, s->dense_bf16, st);
+      const bool comm_stats = s->has_comm && mode == 1;
+      if (comm_stats)
+        launch_dense_comm_stats(s->n, s->L, s->Lp, reinterpret_cast<const float*>(zh(s, to)),
+                                reinterpret_cast<const float*>(psi(s, to)),
+                                s->has_kl ? static_cast<const float*>(s->KL) : nullptr, g.cw, g.dc, g.ucur,
+                                s->sigf + (size_t)to * Lp, s->sigb + (size_t)to * Lp, s->part_cc, kDenseCommBlocks, st);
       launch_dense_rows(s->n, s->ntn, s->part_s, reinterpret_cast<const float*>(static_cast<V*>(s->cap) + (size_t)(to - 1) * s->n),
                         reinterpret_cast<float*>(uat(s, to)), mode == 0 ? 1 : 0,
                         mode == 1 ? s->part + (size_t)to * pstride : nullptr,
                         (mode == 1 && occ) ? occ + (size_t)to * s->n : nullptr,
                         reinterpret_cast<const float*>(zh(s, to)), s->dense_bf16 ? bbuf(s, to) : nullptr,
                         s->dense_bf16 ? nullptr : b32(s, to), s->n8, s->Lp,
-                        s->nblk, st);
+                        s->nblk, comm_stats ? s->part_cc : nullptr, kDenseCommBlocks, st);
     } else {
       launch_gemm(g, s->dense_bf16, st);   // hatPsi_T into the rolling buffer
       launch_dense_sink(s->n, s->Lp, s->L, g.out, reinterpret_cast<const float*>(s->R0T),
@@ -666,7 +688,7 @@ struct Impl {
         if (s->has_kl && t >= 1)
           launch_dense_state_cost(n, s->L, s->Lp, reinterpret_cast<const float*>(zh(s, t)),
                                   reinterpret_cast<const float*>(psi(s, t)), static_cast<const float*>(s->KL),
-                                  reinterpret_cast<const float*>(uat(s, t)), s->sigf + (size_t)t * Lp,
+                                  reinterpret_cast<const float*>(wat(s, t)), reinterpret_cast<const float*>(uat(s, t)), s->sigf + (size_t)t * Lp,
                                   s->sigb + (size_t)t * Lp, s->eps, s->part_flow + (size_t)t * pstride, nb, st);
         if (tb < T) dense_fwd(s, t, 1, false, nullptr, nullptr, st);
       }

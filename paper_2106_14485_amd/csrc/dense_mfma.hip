@@ -45,6 +45,9 @@ __host__ __device__ __forceinline__ int ipos32(int k) { return (k & ~31) | ((k &
 // j = g of its wave's 64 x 64 quadrant.  smem: LDS that no wave reads any more
 // (the operand ring), 2 * 256 + 2 * GBN floats.
 constexpr int kWaveGroups = 2;
+// CM: commodity-dependent capacities (see GemmArgs): 0 none, 1 w_t applied, 2 w_t
+// projected (forward update) and applied
+template <int CM>
 __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2][2], int row0, int col0, int bn,
                                               int logical, float* smem) {
   // red[g][wm][wn][64]: capacity partial sums across the column waves (and groups)
@@ -89,10 +92,34 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2
         const bool ok = cok && gr < a.n;
         const size_t off = (size_t)gr * a.Lp + gc;
         const float o = acc[i][j][r] * f;
-        const float z = a.kl ? o * klv[r] : o;
+        float z = a.kl ? o * klv[r] : o;
+        if constexpr (CM) {
+          // w_t multiplied into the stored output; at a forward update first projected
+          // (before u_t, with the u_t of the last sweep): w = min(D / (P_{0,t} u_t), 1),
+          // 0 where D = 0, in the multiplicative form w_old D / (P_{0,t} u_t) with
+          // P_{0,t} taken with w_old (folded into the stored backward panel)
+          const int grc = gr < a.n ? gr : a.n - 1;
+          const size_t offc = (size_t)grc * a.Lp + gcc;
+          const float cw = a.cw[offc];
+          float wn = cw;
+          if (CM == 2 && capc) {
+            const float dc = a.dc[offc];
+            const float q = o * wv[r] * g;
+            const float qu = q * a.ucur[grc], lim = cw * dc;
+            wn = (dc == 0.f) ? 0.f : ((qu <= lim) ? 1.f : lim / qu);
+            if (ok) {
+              a.cwo[off] = wn;
+              rsum[i][r] += (cw > 0.f) ? q * (wn / cw) : 0.f;
+            }
+          } else if (ok && capc) {
+            rsum[i][r] = fmaf(o * wv[r], g, rsum[i][r]);
+          }
+          z *= wn;
+        } else {
+          if (ok && capc) rsum[i][r] = fmaf(o * wv[r], g, rsum[i][r]);
+        }
         if (ok) a.out[off] = z;
         if (ok && z > 0.f) colmax[j] = fmaxf(colmax[j], z);
-        if (ok && capc) rsum[i][r] = fmaf(o * wv[r], g, rsum[i][r]);
         if (a.pcomm && ok && capc && (unsigned)(gc - a.pc_lo) < (unsigned)a.pc_cnt) {
           const double P = (double)o * (double)wv[r] * (double)g * (double)a.ucur[gr];
           a.pcomm[(size_t)(gc - a.pc_lo) * a.n + gr] = P;
@@ -111,7 +138,11 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs& a, f32x16 (&acc)[2
             const int r = 4 * q + e;
             const int gr = g0 + 4 * lh + e;
             const float o = acc[i][j][r] * f;
-            const float z = a.kl ? o * klv[r] : o;
+            float z = a.kl ? o * klv[r] : o;
+            if constexpr (CM) {   // (backward products only: w_t as stored)
+              const int grc = gr < a.n ? gr : a.n - 1;
+              z *= a.cw[(size_t)grc * a.Lp + gc];
+            }
             p[e] = (__bf16)(gr < a.n ? z * uov[r] : 0.f);
           }
           *reinterpret_cast<bf16x4*>(a.bout + ((size_t)(g0 >> 3) * a.Lp + gc) * 8 + 4 * lh) = p;
@@ -213,7 +244,7 @@ __device__ __forceinline__ void wait_vm() {
 // of four waves took 53.2 us per BF16 product, two take 50.3 us).  At the end
 // each group posts the 32-column half that the other group stores, adds the half
 // it keeps, and the two groups share the epilogue.
-template <bool F32>
+template <bool F32, int CM>
 __global__ __launch_bounds__(512) void k_gemm_lds(GemmArgs a) {
   constexpr int KS = F32 ? 32 : 64;          // k per stage
   constexpr int ES = F32 ? 4 : 2;            // element bytes
@@ -361,7 +392,7 @@ __global__ __launch_bounds__(512) void k_gemm_lds(GemmArgs a) {
   if (grp == 0) take(std::integral_constant<int, 0>{});
   else take(std::integral_constant<int, 1>{});
   __syncthreads();
-  gemm_epilogue(a, acc, row0, col0, bn, logical, reinterpret_cast<float*>(&lds[0][0][0]));
+  gemm_epilogue<CM>(a, acc, row0, col0, bn, logical, reinterpret_cast<float*>(&lds[0][0][0]));
 }
 
 // ---------------------------------------------------------------------------
@@ -394,8 +425,17 @@ __device__ __forceinline__ void block_partials(const double (&st)[kNSt], double*
 // sums: s_j = sum_p part_s[p][j]; update: u_j = 1 if s_j <= d_j else d_j / s_j;
 // check: occupancy u_j s_j and the capacity / dual / gap statistics.
 __global__ void k_dense_rows(int n, int ntn, const float* __restrict__ part_s, const float* __restrict__ cap,
-                             float* __restrict__ u, int update, double* part, double* occ) {
+                             float* __restrict__ u, int update, double* part, double* occ,
+                             const double* __restrict__ cc, int ncc) {
   double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (cc && blockIdx.x == 0) {
+    // the commodity-capacity terms of the product's blocks (check pass), folded into block 0
+    for (int b = threadIdx.x; b < ncc; b += blockDim.x) {
+      st[ST_CAP_VIOL] = fmax(st[ST_CAP_VIOL], cc[(size_t)b * kNSt + ST_CAP_VIOL]);
+      st[ST_DUAL] += cc[(size_t)b * kNSt + ST_DUAL];
+      st[ST_GAP] += cc[(size_t)b * kNSt + ST_GAP];
+    }
+  }
   const int per = (n + gridDim.x - 1) / gridDim.x;
   const int r0 = blockIdx.x * per, r1 = min(n, r0 + per);
   for (int j = r0 + threadIdx.x; j < r1; j += blockDim.x) {
@@ -581,8 +621,18 @@ void launch_dense_operand(int n, int Lp, const float* x, const float* u, uint16_
 void launch_dense_operand32(int n, int n8, int Lp, const float* x, const float* u, float* bout, hipStream_t s);
 void launch_gemm(const GemmArgs& a, bool bf16, hipStream_t s) {
   dim3 grid((a.n + GBM - 1) / GBM, (a.Lp + GBN - 1) / GBN);
-  if (bf16) hipLaunchKernelGGL(k_gemm_lds<false>, grid, dim3(512), 0, s, a);
-  else hipLaunchKernelGGL(k_gemm_lds<true>, grid, dim3(512), 0, s, a);
+  // (one variant per commodity-capacity mode: the projection's loads and division
+  // in the one kernel that needs them keep the others' registers)
+  if (a.cw && a.cc_update) {
+    if (bf16) hipLaunchKernelGGL((k_gemm_lds<false, 2>), grid, dim3(512), 0, s, a);
+    else hipLaunchKernelGGL((k_gemm_lds<true, 2>), grid, dim3(512), 0, s, a);
+  } else if (a.cw) {
+    if (bf16) hipLaunchKernelGGL((k_gemm_lds<false, 1>), grid, dim3(512), 0, s, a);
+    else hipLaunchKernelGGL((k_gemm_lds<true, 1>), grid, dim3(512), 0, s, a);
+  } else {
+    if (bf16) hipLaunchKernelGGL((k_gemm_lds<false, 0>), grid, dim3(512), 0, s, a);
+    else hipLaunchKernelGGL((k_gemm_lds<true, 0>), grid, dim3(512), 0, s, a);
+  }
 }
 int gemm_col_tiles(int Lp) { return (Lp + GBN - 1) / GBN; }
 __global__ void k_dense_operand32(int n, int Lp, const float* __restrict__ x, const float* __restrict__ u,
@@ -590,7 +640,7 @@ __global__ void k_dense_operand32(int n, int Lp, const float* __restrict__ x, co
                                   const float* __restrict__ cap, float* __restrict__ uw);
 void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, float* u, int update, double* part,
                        double* occ, const float* x, uint16_t* bout, float* bout32, int n8, int Lp, int nblk,
-                       hipStream_t s) {
+                       const double* cc, int ncc, hipStream_t s) {
   // an update that feeds a next product is done by the operand kernel itself (one
   // launch); statistics come as one partial per block of the check pass's fixed
   // grid, and an update alone needs one thread per state
@@ -604,7 +654,7 @@ void launch_dense_rows(int n, int ntn, const float* part_s, const float* cap, fl
     return;
   }
   const int g = part ? nblk : (n + 255) / 256;
-  hipLaunchKernelGGL(k_dense_rows, dim3(g), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ);
+  hipLaunchKernelGGL(k_dense_rows, dim3(g), dim3(256), 0, s, n, ntn, part_s, cap, u, update, part, occ, cc, ncc);
   // the next product's operand, u_j x_j in BF16 or FP32, once u is final
   if (bout) launch_dense_operand(n, Lp, x, u, bout, s);
   if (bout32) launch_dense_operand32(n, n8, Lp, x, u, bout32, s);
@@ -778,11 +828,13 @@ __global__ __launch_bounds__(256) void k_dense_flows(int n, int Lp, int lda, con
 }
 
 // State costs of one interior time on a dense network: sum_{i,l} C_L[i][l]
-// P_{0,t}[l][i], P_{0,t} = hatPsi_t (.) Psi_t (.) K_L (.) u_t (eq. proj_0t) with
-// zh = hatPsi_t (.) K_L and psi = Psi_t (.) K_L as stored and C_L = -eps ln K_L,
-// into field ST_SCOST of the block partials (nblk blocks, grid-stride, fixed order).
+// P_{0,t}[l][i], P_{0,t} = hatPsi_t (.) Psi_t (.) K_L (.) w_t (.) u_t (eq. proj_0t) with
+// zh = hatPsi_t (.) K_L (.) w_t and psi = Psi_t (.) K_L (.) w_t as stored (w_t the
+// commodity-capacity scaling, cw == nullptr: none) and C_L = -eps ln K_L, into field
+// ST_SCOST of the block partials (nblk blocks, grid-stride, fixed order).
 __global__ __launch_bounds__(256) void k_dense_state_cost(int n, int L, int Lp, const float* __restrict__ zh,
                                                            const float* __restrict__ psi, const float* __restrict__ kl,
+                                                           const float* __restrict__ cw,
                                                            const float* __restrict__ u, const double* __restrict__ sa,
                                                            const double* __restrict__ sb, double eps,
                                                            double* __restrict__ part) {
@@ -791,9 +843,9 @@ __global__ __launch_bounds__(256) void k_dense_state_cost(int n, int L, int Lp, 
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / Lp), l = (int)(e % Lp);
     if (l >= L) continue;
-    const double k = (double)kl[e];
-    if (!(k > 0.0)) continue;
-    const double P = (double)zh[e] * (double)psi[e] / k * (double)u[i] * exp2(sa[l] + sb[l]);
+    const double k = (double)kl[e], w = cw ? (double)cw[e] : 1.0;
+    if (!(k > 0.0) || !(w > 0.0)) continue;
+    const double P = (double)zh[e] * (double)psi[e] / (k * w) * (double)u[i] * exp2(sa[l] + sb[l]);
     if (P > 0.0) c += -eps * log(k) * P;
   }
   __shared__ double red[4];
@@ -804,6 +856,56 @@ __global__ __launch_bounds__(256) void k_dense_state_cost(int n, int L, int Lp, 
   if (threadIdx.x == 0) part[(size_t)blockIdx.x * kNSt + ST_SCOST] = ((red[0] + red[1]) + red[2]) + red[3];
 }
 
+// Commodity-capacity statistics of one interior time on a dense network (check
+// pass): P_{0,t} = hatPsi_t (.) Psi_t (.) K_L (.) w_t (.) u_t (eq. proj_0t) from the
+// stored panels zh = hatPsi_t (.) K_L (.) w_t and psi = Psi_t (.) K_L (.) w_t (kl ==
+// nullptr: K_L = 1), and over the bounds D_t[l][i] that are finite and positive the
+// relative violation max(P - D, 0) / D (maximised), the dual term D ln w_t and the
+// gap term ln w_t (P - D) (summed), into fields ST_CAP_VIOL, ST_DUAL and ST_GAP of
+// part[block] (nblk blocks, grid-stride, fixed order; the row kernel of the same
+// time folds them into its statistics).
+__global__ __launch_bounds__(256) void k_dense_comm_stats(int n, int L, int Lp, const float* __restrict__ zh,
+                                                           const float* __restrict__ psi, const float* __restrict__ kl,
+                                                           const float* __restrict__ cw, const float* __restrict__ dc,
+                                                           const float* __restrict__ u, const double* __restrict__ sa,
+                                                           const double* __restrict__ sb, double* __restrict__ part) {
+  double v = 0.0, du = 0.0, ga = 0.0;
+  const size_t total = (size_t)n * Lp;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e / Lp), l = (int)(e % Lp);
+    if (l >= L) continue;
+    const double D = (double)dc[e];
+    if (!(D > 0.0) || !isfinite(D)) continue;
+    const double w = (double)cw[e], k = kl ? (double)kl[e] : 1.0;
+    const double P = (w > 0.0 && k > 0.0) ? (double)zh[e] * (double)psi[e] / (k * w) * (double)u[i] * exp2(sa[l] + sb[l])
+                                          : 0.0;
+    const double lnw = log(w);
+    v = fmax(v, fmax(P - D, 0.0) / D);
+    du += D * lnw;
+    ga += lnw * (P - D);
+  }
+  __shared__ double red[4][3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int m = 32; m > 0; m >>= 1) {
+    v = fmax(v, __shfl_xor(v, m, 64));
+    du += __shfl_xor(du, m, 64);
+    ga += __shfl_xor(ga, m, 64);
+  }
+  if (lane == 0) { red[wave][0] = v; red[wave][1] = du; red[wave][2] = ga; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double* o = part + (size_t)blockIdx.x * kNSt;
+    o[ST_CAP_VIOL] = fmax(fmax(red[0][0], red[1][0]), fmax(red[2][0], red[3][0]));
+    o[ST_DUAL] = ((red[0][1] + red[1][1]) + red[2][1]) + red[3][1];
+    o[ST_GAP] = ((red[0][2] + red[1][2]) + red[2][2]) + red[3][2];
+  }
+}
+
+void launch_dense_comm_stats(int n, int L, int Lp, const float* zh, const float* psi, const float* kl, const float* cw,
+                             const float* dc, const float* u, const double* sa, const double* sb, double* part,
+                             int nblk, hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_comm_stats, dim3(nblk), dim3(256), 0, s, n, L, Lp, zh, psi, kl, cw, dc, u, sa, sb, part);
+}
 void launch_dense_flows(int n, int L, int Lp, int lda, const float* A, const float* ua, const float* B,
                         const float* ub, const double* sa, const double* sb, float* fab, const float* K, double eps,
                         double* flow, double* part, int nblk, hipStream_t s) {
@@ -811,9 +913,10 @@ void launch_dense_flows(int n, int L, int Lp, int lda, const float* A, const flo
   hipLaunchKernelGGL(k_dense_flows, dim3(nblk), dim3(256), 0, s, n, Lp, lda, A, ua, B, ub, fab, fab + Lp, K, eps,
                      flow, part);
 }
-void launch_dense_state_cost(int n, int L, int Lp, const float* zh, const float* psi, const float* kl, const float* u,
-                             const double* sa, const double* sb, double eps, double* part, int nblk, hipStream_t s) {
-  hipLaunchKernelGGL(k_dense_state_cost, dim3(nblk), dim3(256), 0, s, n, L, Lp, zh, psi, kl, u, sa, sb, eps, part);
+void launch_dense_state_cost(int n, int L, int Lp, const float* zh, const float* psi, const float* kl, const float* cw,
+                             const float* u, const double* sa, const double* sb, double eps, double* part, int nblk,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_state_cost, dim3(nblk), dim3(256), 0, s, n, L, Lp, zh, psi, kl, cw, u, sa, sb, eps, part);
 }
 
 }  // namespace mmot

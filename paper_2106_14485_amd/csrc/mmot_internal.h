@@ -202,6 +202,14 @@ struct GemmArgs {
   uint32_t* slots;      // column levels of the stored output, nullptr = off
   int nslot;
   size_t slot_stride;
+  // commodity-dependent capacities (kernel variant CM, nullptr = none): cw = w_t
+  // [n][Lp] multiplied into the stored output; forward update (cc_update): w_t
+  // projected before u_t with ucur (the u_t of the last sweep) against dc = D_t,
+  // written to cwo
+  const float* cw;
+  float* cwo;
+  const float* dc;
+  int cc_update;
 };
 
 // Work items of the serving pool: one recorded kernel launch of one solve.

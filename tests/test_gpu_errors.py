@@ -63,7 +63,6 @@ def test_unsupported_combinations():
     d = instances.dense_blob_instance(n=64, L=8, T=4, seed=1)
     _expect(d, _lib.MMOT_EUNSUPPORTED, precision="fp64")                             # dense products: FP32/BF16
     _expect(d, _lib.MMOT_EUNSUPPORTED, domain="log")                                 # dense: scaled domain only
-    _expect(dataclasses.replace(d, cap_comm=np.full((d.L, d.n), np.inf)), _lib.MMOT_EUNSUPPORTED)
 
 
 def test_workspace_too_small():

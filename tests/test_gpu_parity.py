@@ -382,6 +382,100 @@ def test_dense_time_varying_network():
     assert rel_l1(alg2.projections(fixed, ost, want_flows=False)["P0t"], ref["P0t"]) > 1e-3
 
 
+@pytest.mark.parametrize("per_step,state_costs", [(True, True), (False, False)])
+def test_dense_commodity_capacities(per_step, state_costs):
+    """Commodity-dependent capacities on a dense network (the extension at the end
+    of Section 3): w_t applied in the epilogue of every product and projected in
+    the forward products' epilogue.  Iterate for iterate against the oracle
+    (FP32-rounded marginals, as the FP32 solver represents them): occupancy,
+    per-commodity marginals, flows and cost (with state costs: C_L weighted by
+    P_{0,t}, which w_t scales once) to 1e-5, the dual objective to 1e-5, log w_t
+    to 1e-4 with the same closed entries, and the capacity violation (commodity
+    bounds and state capacities) to 1e-5.  n = 200 and L = 30 leave ragged
+    product tiles."""
+    import dataclasses
+    base = instances.dense_blob_instance(n=200, L=30, T=6, seed=23)
+    if state_costs:
+        rng = np.random.default_rng(5)
+        base = dataclasses.replace(base, state_cost=rng.uniform(0.0, 0.05, (base.L, base.n)))
+    inst = _with_comm_caps(base, 12, per_step=per_step, zero_frac=0.0)
+    # every state is a source and a sink of every commodity here (blobs of full
+    # support), and the complete graph leaves a closed state in one move: close
+    # 1% of the entries outright
+    D = inst.cap_comm.copy()
+    D[np.random.default_rng(6).random(D.shape) < 0.01] = 0.0
+    inst = dataclasses.replace(inst, cap_comm=D)
+    p = to_oracle(inst)
+    r32 = lambda a: a.astype(np.float32).astype(np.float64)
+    p = alg2.make_problem(p.C, p.eps, p.T, r32(inst.src), r32(inst.dst), p.cap, p.state_cost, p.cap_comm)
+    ost = alg2.iterate(p, alg2.initial_state(p), 15)
+    assert np.sum((ost.w < 1.0) & (ost.w > 0.0)) > 30 and np.sum(ost.w == 0.0) > 100
+    ref = alg2.projections(p, ost)
+    S = _solver()(inst, precision="fp32", domain="auto")
+    S.iterate(15)
+    st = S.stats()
+    occ, pc = S.occupancy(per_commodity=True)
+    occ, pc = occ.cpu().numpy(), pc.cpu().numpy()
+    flows, cost = S.edge_flows()
+    flows = flows.cpu().numpy()
+    lw = S.comm_duals().cpu().numpy()
+    S.close()
+    assert rel_l1(occ, ref["Pt"]) <= 1e-5, rel_l1(occ, ref["Pt"])
+    assert rel_l1(pc, ref["P0t"]) <= 1e-5, rel_l1(pc, ref["P0t"])
+    for l in range(inst.L):
+        assert rel_l1(pc[:, l], ref["P0t"][:, l]) <= 1e-5, l
+    for t in range(inst.T):
+        assert rel_l1(flows[t], ref["flows"][t]) <= 1e-5, (t, rel_l1(flows[t], ref["flows"][t]))
+    assert abs(cost - ref["cost"]) <= 1e-5 * abs(ref["cost"]), (cost, ref["cost"])
+    assert abs(st["dual_obj"] - ost.g[-1]) <= 1e-5 * abs(ost.g[-1]), (st["dual_obj"], ost.g[-1])
+    with np.errstate(divide="ignore"):
+        lw_o = np.log(ost.w)
+    assert np.array_equal(np.isfinite(lw), np.isfinite(lw_o))
+    fin = np.isfinite(lw_o)
+    assert np.abs(lw[fin] - lw_o[fin]).max() <= 1e-4
+    # the violation the check pass reports: commodity bounds and state capacities
+    P = ref["P0t"][1:-1]
+    D = np.broadcast_to(inst.cap_comm, P.shape)
+    m = np.isfinite(D) & (D > 0)
+    viol = np.max(np.maximum(P[m] - D[m], 0.0) / D[m])
+    d = np.broadcast_to(np.asarray(inst.cap, dtype=np.float64), ref["Pt"][1:-1].shape)
+    fd = np.isfinite(d)
+    viol = max(viol, np.max(np.maximum(ref["Pt"][1:-1][fd] - d[fd], 0.0) / d[fd]))
+    assert viol > 5e-4
+    assert abs(st["cap_viol"] - viol) <= 1e-5, (st["cap_viol"], viol)
+
+
+def _dense_comm_caps_instance(n, L, T, seed, per_step=True):
+    base = instances.dense_blob_instance(n=n, L=L, T=T, seed=seed)
+    inst = _with_comm_caps(base, seed + 1, per_step=per_step, zero_frac=0.0)
+    D = inst.cap_comm.copy()
+    D[np.random.default_rng(seed + 2).random(D.shape) < 0.01] = 0.0
+    import dataclasses
+    return dataclasses.replace(inst, cap_comm=D)
+
+
+def test_dense_commodity_capacities_bf16_then_fp32_polish():
+    """BF16 products with commodity capacities (w_t also in the BF16 operand that
+    a backward product's epilogue writes).  After 15 iterations the per-commodity
+    marginals are within 3e-3 of the oracle's (BF16 rounds each operand to 2^-9;
+    7e-4 measured, with and without the capacities), where the capacities
+    themselves move the marginals by 2.7e-2 (so a product without w_t cannot pass);
+    then 360 BF16 + 40 FP32 iterations against 400 of the oracle to 1e-4."""
+    import dataclasses
+    inst = _dense_comm_caps_instance(300, 40, 8, 7)
+    o15 = dense_oracle(inst, 15)
+    free15 = dense_oracle(dataclasses.replace(inst, cap_comm=None), 15)
+    assert rel_l1(free15["P0t"], o15["P0t"]) > 2e-2
+    g16 = dense_outputs(inst, 15, "bf16")
+    assert g16["stats"]["precision"] == 2
+    assert rel_l1(g16["P0t"], o15["P0t"]) <= 3e-3, rel_l1(g16["P0t"], o15["P0t"])
+    o = dense_oracle(inst, 400)
+    g = dense_outputs(inst, 360, "bf16", polish=40)
+    assert g["stats"]["precision"] == 0
+    assert rel_l1(g["Pt"], o["Pt"]) <= 1e-4, rel_l1(g["Pt"], o["Pt"])
+    assert rel_l1(g["P0t"], o["P0t"]) <= 1e-4, rel_l1(g["P0t"], o["P0t"])
+
+
 def test_dense_fp32_against_exact_inputs_after_convergence():
     inst = instances.dense_blob_instance(n=300, L=40, T=8, seed=340)
     o = dense_oracle(inst, 100)
