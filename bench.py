@@ -281,7 +281,7 @@ def main():
         achieved = flops / (fwd_ms * 1e-3) / 1e12
         peak = 2500.0 if prec == "bf16" else 157.3
         roof = {"bound": "mfma", "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 5), "traffic": None, "kernel": "k_gemm_lds<false> forward (BF16)" if prec == "bf16" else "k_gemm_lds<true> forward (FP32)",
+                "frac": round(achieved / peak, 5), "traffic": None, "kernel": "k_gemm_lds<false, 0> forward (BF16)" if prec == "bf16" else "k_gemm_lds<true, 0> forward (FP32)",
                 "kernel_ms": round(fwd_ms, 5), "flops_per_launch": flops, "bwd_kernel_ms": round(bwd_ms, 5)}
     else:
         # algorithmic bytes of one forward step: read hatPsi_t, read Psi_{t+1}, write hatPsi_{t+1}
