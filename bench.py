@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "road100": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "282773a11b63e797f7e589abce81adea26efd989a4614ea7d087df1768842907",
-                "fetch_kib": 98622.525, "write_kib": 79550.804, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "2bef7482dbd1bfe24ef6297b168dd252ed10ed1790a3757b022a583afef5d0be",
+                "fetch_kib": 87600.233, "write_kib": 79431.677, "fetch_scale": 2.0, "write_scale": 1.0},
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "282773a11b63e797f7e589abce81adea26efd989a4614ea7d087df1768842907",
-                "fetch_kib": 2402.094, "write_kib": 2007.938, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "2bef7482dbd1bfe24ef6297b168dd252ed10ed1790a3757b022a583afef5d0be",
+                "fetch_kib": 2407.656, "write_kib": 2007.938, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
 
