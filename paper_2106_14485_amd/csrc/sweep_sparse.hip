@@ -686,6 +686,14 @@ __host__ __device__ __forceinline__ bool ell_fast(const StepArgs<V>& a) {
   return a.ellD > 0 && !a.cw && !a.kl && !a.slots && !a.slots_o && !a.cslots_b && !a.cslots_f && a.epi != 2 &&
          (a.epi == 0 || a.update) && !a.part && !a.occ && !a.pcomm && a.out;
 }
+// the update-free forward step of a check pass in the same form: no u update, the
+// occupancy and capacity statistics of each row into the block's partial (and the
+// occupancy output), no per-commodity output
+template <typename V>
+__host__ __device__ __forceinline__ bool ell_check(const StepArgs<V>& a) {
+  return a.ellD > 0 && !a.cw && !a.kl && !a.slots && !a.slots_o && !a.cslots_b && !a.cslots_f && a.epi == 1 &&
+         !a.update && a.part && !a.pcomm && a.out;
+}
 // every wave of the step has exactly one column chunk of its row
 template <typename V>
 __host__ __device__ __forceinline__ bool ell_one_chunk(const StepArgs<V>& a) {
@@ -699,8 +707,11 @@ __host__ __device__ __forceinline__ bool ell_one_chunk(const StepArgs<V>& a) {
 // for before any gather was issued, one more memory round trip per row (RGG
 // workload, with the wait below: forward step 5.10 -> 4.61 us, backward 4.10 ->
 // 3.69 us; on the road grid's rows of eight chunks the same order measured 3% slower).
-template <typename V, bool LOG, bool FWD, int KB, bool ONE>
+// CHK (forward only): the check pass's update-free step (ell_check), the row-end
+// statistics of step_body's check mode operation for operation.
+template <typename V, bool LOG, bool FWD, int KB, bool ONE, bool CHK = false>
 __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int nblk) {
+  static_assert(FWD || !CHK, "the check pass runs forward steps");
   constexpr int NV = VT<V>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = a.G;
@@ -849,15 +860,39 @@ __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int
       }
     }
     if (LOG) sv = (ls > V(0)) ? lm + llog2(ls) : ninf<V>();
-    if (valid && gl == 0 && sub == 0) {
-      const V d = a.cap[row];
-      a.uout[row] = !LOG ? ((sv <= d) ? V(1) : d / sv) : fmin(V(0), d - sv);
+    if constexpr (!CHK) {
+      if (valid && gl == 0 && sub == 0) {
+        const V d = a.cap[row];
+        a.uout[row] = !LOG ? ((sv <= d) ? V(1) : d / sv) : fmin(V(0), d - sv);
+      }
+    } else {
+      // occupancy u_t s_t of the row and its capacity terms (Corollary 1)
+      double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (valid && gl == 0 && sub == 0) {
+        const V d = a.cap[row];
+        const V u = a.uout[row];
+        double occ, dd, lnu;
+        if (!LOG) { occ = (double)u * (double)sv; dd = (double)d; lnu = log((double)u); }
+        else {
+          occ = (sv == ninf<V>()) ? 0.0 : exp2((double)u + (double)sv);
+          dd = exp2((double)d); lnu = (double)u * M_LN2;
+        }
+        st[ST_MASS] += occ;
+        if (isfinite(dd)) {
+          st[ST_CAP_VIOL] = fmax(st[ST_CAP_VIOL], fmax(occ - dd, 0.0) / dd);
+          st[ST_DUAL] += dd * lnu;
+          st[ST_GAP] += lnu * (occ - dd);
+        }
+        if (!isfinite(occ)) st[ST_NONFINITE] += 1.0;
+        if (a.occ) a.occ[row] = occ;
+      }
+      block_stats(st, a.part, bid);
     }
   }
 }
-template <typename V, bool LOG, bool FWD, int KB, bool ONE>
+template <typename V, bool LOG, bool FWD, int KB, bool ONE, bool CHK>
 __global__ __launch_bounds__(kBlock) void k_ell_step(StepArgs<V> a) {
-  ell_step_body<V, LOG, FWD, KB, ONE>(a, blockIdx.x, gridDim.x);
+  ell_step_body<V, LOG, FWD, KB, ONE, CHK>(a, blockIdx.x, gridDim.x);
 }
 
 // (at least two waves per SIMD: the wide CSR variants would otherwise take the
@@ -1391,23 +1426,25 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
     else if (fwd == 2) hipLaunchKernelGGL((k_step<V, LOG, true, true, E, K, C>), dim3(nblk), dim3(kBlock), 0, s, a); \
     else hipLaunchKernelGGL((k_step<V, LOG, false, false, E, K, C>), dim3(nblk), dim3(kBlock), 0, s, a);       \
   } while (0)
+#define MMOT_ELL_LAUNCH1(K, O)                                                                                      \
+  do {                                                                                                             \
+    if (fwd == 2) hipLaunchKernelGGL((k_ell_step<V, LOG, true, K, O, true>), dim3(nblk), dim3(kBlock), 0, s, a);    \
+    else if (fwd == 1) hipLaunchKernelGGL((k_ell_step<V, LOG, true, K, O, false>), dim3(nblk), dim3(kBlock), 0, s, a); \
+    else hipLaunchKernelGGL((k_ell_step<V, LOG, false, K, O, false>), dim3(nblk), dim3(kBlock), 0, s, a);          \
+  } while (0)
 #define MMOT_ELL_LAUNCH(K)                                                                                          \
   do {                                                                                                             \
-    if (one) {                                                                                                     \
-      if (fwd == 1) hipLaunchKernelGGL((k_ell_step<V, LOG, true, K, true>), dim3(nblk), dim3(kBlock), 0, s, a);     \
-      else hipLaunchKernelGGL((k_ell_step<V, LOG, false, K, true>), dim3(nblk), dim3(kBlock), 0, s, a);             \
-    } else {                                                                                                       \
-      if (fwd == 1) hipLaunchKernelGGL((k_ell_step<V, LOG, true, K, false>), dim3(nblk), dim3(kBlock), 0, s, a);    \
-      else hipLaunchKernelGGL((k_ell_step<V, LOG, false, K, false>), dim3(nblk), dim3(kBlock), 0, s, a);            \
-    }                                                                                                              \
+    if (one) MMOT_ELL_LAUNCH1(K, true);                                                                            \
+    else MMOT_ELL_LAUNCH1(K, false);                                                                               \
   } while (0)
-  if (fwd != 2 && ell_fast(a)) {
+  if (fwd != 2 ? ell_fast(a) : ell_check(a)) {
     const bool one = ell_one_chunk(a);
     if (a.ellD == 16) MMOT_ELL_LAUNCH(16);
     else if (a.ellD == 8) MMOT_ELL_LAUNCH(8);
     else if (a.ellD == 5) MMOT_ELL_LAUNCH(5);
     else MMOT_ELL_LAUNCH(4);
 #undef MMOT_ELL_LAUNCH
+#undef MMOT_ELL_LAUNCH1
     return;
   }
   if (a.cw) MMOT_STEP_LAUNCH(false, 16, true);
@@ -1516,24 +1553,33 @@ __device__ __forceinline__ void run_item(const PoolItem& it, int bid) {
     case IK_STEP_FWD:
     case IK_STEP_CHK: {
       const StepArgs<float>& sa = *static_cast<const StepArgs<float>*>(p);
-      if (it.kind != IK_STEP_CHK && ell_fast(sa)) {
+      // (a check-pass step is heavy: it reaches lean ticks only by a host error)
+      const bool chk = it.kind == IK_STEP_CHK;
+      if (chk ? (!LEAN && ell_check(sa)) : ell_fast(sa)) {
         const bool fw = it.kind == IK_STEP_FWD;
         const bool one = ell_one_chunk(sa);
+#define MMOT_ELL_ITEM1(K, O)                                                          \
+        do {                                                                          \
+          if constexpr (!LEAN) {                                                      \
+            if (chk) {                                                                \
+              ell_step_body<float, LOG, true, K, O, true>(sa, bid, it.nblk);          \
+              break;                                                                  \
+            }                                                                         \
+          }                                                                           \
+          if (fw) ell_step_body<float, LOG, true, K, O>(sa, bid, it.nblk);            \
+          else ell_step_body<float, LOG, false, K, O>(sa, bid, it.nblk);              \
+        } while (0)
 #define MMOT_ELL_ITEM(K)                                                              \
         do {                                                                          \
-          if (one) {                                                                  \
-            if (fw) ell_step_body<float, LOG, true, K, true>(sa, bid, it.nblk);       \
-            else ell_step_body<float, LOG, false, K, true>(sa, bid, it.nblk);         \
-          } else {                                                                    \
-            if (fw) ell_step_body<float, LOG, true, K, false>(sa, bid, it.nblk);      \
-            else ell_step_body<float, LOG, false, K, false>(sa, bid, it.nblk);        \
-          }                                                                           \
+          if (one) MMOT_ELL_ITEM1(K, true);                                           \
+          else MMOT_ELL_ITEM1(K, false);                                              \
         } while (0)
         if (sa.ellD == 16) MMOT_ELL_ITEM(16);
         else if (sa.ellD == 8) MMOT_ELL_ITEM(8);
         else if (sa.ellD == 5) MMOT_ELL_ITEM(5);
         else MMOT_ELL_ITEM(4);
 #undef MMOT_ELL_ITEM
+#undef MMOT_ELL_ITEM1
         break;
       }
       // 0: CSR, 1..4: ELL of width 8, 16, 5, 4, 5: CSR with commodity capacities
