@@ -694,6 +694,14 @@ __host__ __device__ __forceinline__ bool ell_check(const StepArgs<V>& a) {
   return a.ellD > 0 && !a.cw && !a.kl && !a.slots && !a.slots_o && !a.cslots_b && !a.cslots_f && a.epi == 1 &&
          !a.update && a.part && !a.pcomm && a.out;
 }
+// a step of a calibration sweep in the same form: the column levels of the stored
+// panel (scaled domain) or the calibration keys of the forward step (log domain)
+// recorded as step_body records them
+template <typename V>
+__host__ __device__ __forceinline__ bool ell_calib(const StepArgs<V>& a) {
+  return a.ellD > 0 && !a.cw && !a.kl && !a.slots_o && a.epi != 2 && (a.epi == 0 || a.update) && !a.part &&
+         !a.occ && !a.pcomm && a.out && (a.slots || a.cslots_b);
+}
 // every wave of the step has exactly one column chunk of its row
 template <typename V>
 __host__ __device__ __forceinline__ bool ell_one_chunk(const StepArgs<V>& a) {
@@ -708,10 +716,12 @@ __host__ __device__ __forceinline__ bool ell_one_chunk(const StepArgs<V>& a) {
 // workload, with the wait below: forward step 5.10 -> 4.61 us, backward 4.10 ->
 // 3.69 us; on the road grid's rows of eight chunks the same order measured 3% slower).
 // CHK (forward only): the check pass's update-free step (ell_check), the row-end
-// statistics of step_body's check mode operation for operation.
-template <typename V, bool LOG, bool FWD, int KB, bool ONE, bool CHK = false>
+// statistics of step_body's check mode operation for operation.  CAL: a step of a
+// calibration sweep (ell_calib), each chunk's levels or keys recorded after its store.
+template <typename V, bool LOG, bool FWD, int KB, bool ONE, bool CHK = false, bool CAL = false>
 __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int nblk) {
   static_assert(FWD || !CHK, "the check pass runs forward steps");
+  static_assert(!(CHK && CAL), "the check pass records no levels");
   constexpr int NV = VT<V>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int G = a.G;
@@ -833,6 +843,24 @@ __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int
       }
     }
     if (cv) vst(a.out + row * Lp + col, o);
+    if constexpr (CAL) {
+      // (every wave of the block runs the same chunks: the recordings hold barriers)
+      V z[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) z[v] = cv ? o[v] : (LOG ? ninf<V>() : V(0));
+      if (a.slots) calib_chunk<V, LOG>(z, G, it, lw, a.Lp, a.slots + (size_t)(bid % a.nslot) * a.nslot_stride);
+      if constexpr (LOG && FWD) {
+        if (a.cslots_b) {
+          // plan level at the output time: hatPsi + (Psi (.) K_L), up to per-column constants
+          V pl[NV];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) pl[v] = cv ? o[v] + w[v] : ninf<V>();
+          const size_t cs = (size_t)(bid % a.ncslot) * a.cslot_stride;
+          corr_chunk<V>(pl, w, G, it, lw, a.Lp, a.cslots_b + cs);
+          corr_chunk<V>(pl, z, G, it, lw, a.Lp, a.cslots_f + cs);
+        }
+      }
+    }
   }
 
   if (FWD) {
@@ -890,9 +918,9 @@ __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int
     }
   }
 }
-template <typename V, bool LOG, bool FWD, int KB, bool ONE, bool CHK>
+template <typename V, bool LOG, bool FWD, int KB, bool ONE, bool CHK, bool CAL = false>
 __global__ __launch_bounds__(kBlock) void k_ell_step(StepArgs<V> a) {
-  ell_step_body<V, LOG, FWD, KB, ONE, CHK>(a, blockIdx.x, gridDim.x);
+  ell_step_body<V, LOG, FWD, KB, ONE, CHK, CAL>(a, blockIdx.x, gridDim.x);
 }
 
 // (at least two waves per SIMD: the wide CSR variants would otherwise take the
@@ -1446,6 +1474,29 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
 #undef MMOT_ELL_LAUNCH
 #undef MMOT_ELL_LAUNCH1
     return;
+  }
+  if constexpr (std::is_same<V, float>::value) {
+    // calibration sweeps (FP32 solves)
+    if (fwd != 2 && ell_calib(a)) {
+      const bool one = ell_one_chunk(a);
+#define MMOT_CAL_LAUNCH1(K, O)                                                                                     \
+  do {                                                                                                             \
+    if (fwd == 1) hipLaunchKernelGGL((k_ell_step<V, LOG, true, K, O, false, true>), dim3(nblk), dim3(kBlock), 0, s, a); \
+    else hipLaunchKernelGGL((k_ell_step<V, LOG, false, K, O, false, true>), dim3(nblk), dim3(kBlock), 0, s, a);    \
+  } while (0)
+#define MMOT_CAL_LAUNCH(K)                                                                                         \
+  do {                                                                                                             \
+    if (one) MMOT_CAL_LAUNCH1(K, true);                                                                            \
+    else MMOT_CAL_LAUNCH1(K, false);                                                                               \
+  } while (0)
+      if (a.ellD == 16) MMOT_CAL_LAUNCH(16);
+      else if (a.ellD == 8) MMOT_CAL_LAUNCH(8);
+      else if (a.ellD == 5) MMOT_CAL_LAUNCH(5);
+      else MMOT_CAL_LAUNCH(4);
+#undef MMOT_CAL_LAUNCH
+#undef MMOT_CAL_LAUNCH1
+      return;
+    }
   }
   if (a.cw) MMOT_STEP_LAUNCH(false, 16, true);
   else if (a.ellD == 16) MMOT_STEP_LAUNCH(true, 16, false);
