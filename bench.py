@@ -36,10 +36,10 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "road100": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "2bef7482dbd1bfe24ef6297b168dd252ed10ed1790a3757b022a583afef5d0be",
-                "fetch_kib": 87600.233, "write_kib": 79431.677, "fetch_scale": 2.0, "write_scale": 1.0},
+                "sha256": "ebc25a421bbe5a97c138d48d76f38caa11a01b9f253bf9b746e7b7babc8994ed",
+                "fetch_kib": 87683.646, "write_kib": 79438.244, "fetch_scale": 2.0, "write_scale": 1.0},
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "2bef7482dbd1bfe24ef6297b168dd252ed10ed1790a3757b022a583afef5d0be",
+                "sha256": "ebc25a421bbe5a97c138d48d76f38caa11a01b9f253bf9b746e7b7babc8994ed",
                 "fetch_kib": 2407.656, "write_kib": 2007.938, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 
