@@ -308,7 +308,7 @@ def main():
         "config": {"workload": f"{inst.name}: n={n} states (nnz={nnz}), L={L} commodities, T={T}, "
                                f"eps={inst.eps}, {prec.upper()} {inst.kind.upper()}, "
                                f"domain={'log' if st['domain'] == 2 else 'scaled'}",
-                   "check_every": check_every},
+                   "check_every": check_every, "keep_forward": int(S.opts.keep_forward)},
         "roofline": roof,
         "stats": {k: st[k] for k in ("dual_obj", "src_resid", "cap_viol", "mass_drift")},
     }

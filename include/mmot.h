@@ -108,6 +108,14 @@ typedef struct mmot_options {
   int32_t polish_iters;  /* BF16: FP32 iterations appended by mmot_solve (default 20) */
   int32_t use_graph;     /* capture one iteration in a HIP graph (default 1) */
   double tol;            /* mmot_solve: stop when src_resid <= tol and cap_viol <= tol (default 1e-6) */
+  /* 1 (default): keep the forward messages of every time (T - 1 more n x L panels
+   * on sparse networks without state costs or commodity capacities), so that a
+   * convergence check after Sinkhorn sweeps takes its statistics from the fresh
+   * backward sweep it needs anyway (Corollary 1: P_t = u_t sum_l hatPsi_t Psi_t
+   * K_L), without an extra update-free forward sweep.  0: two rolling forward
+   * panels.  The serving pool runs 0 (mmot_pool_submit rejects 1 with
+   * MMOT_EUNSUPPORTED).  The two give the same statistics up to rounding order. */
+  int32_t keep_forward;
 } mmot_options;
 
 /* Convergence / dual statistics of the current iterate (FP64 reductions).
@@ -303,7 +311,8 @@ mmot_status mmot_pool_query_workspace(const mmot_problem* prob, const mmot_optio
  * mmot_pool_query_workspace, ENOMEM otherwise; the caller keeps it alive until
  * mmot_pool_release) and schedules it.  EAGAIN when admitting it would exceed
  * the budget (nothing is done; retry after a release); EUNSUPPORTED unless CSR
- * and MMOT_FP32, or if a recorded chunk would not fit its program area.
+ * and MMOT_FP32 with keep_forward = 0, or if a recorded chunk would not fit its
+ * program area.
  * *ticket identifies the request.  Synchronous with respect to its own set-up
  * only. */
 mmot_status mmot_pool_submit(mmot_pool* pool, const mmot_problem* prob, const mmot_options* opt, void* ws,

@@ -33,7 +33,7 @@ class Options(ctypes.Structure):
     _fields_ = [
         ("precision", ctypes.c_int32), ("domain", ctypes.c_int32), ("check_every", ctypes.c_int32),
         ("calib_every", ctypes.c_int32), ("polish_iters", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-        ("tol", ctypes.c_double),
+        ("tol", ctypes.c_double), ("keep_forward", ctypes.c_int32),
     ]
 
 

@@ -46,6 +46,9 @@ template <typename V, bool LOG>
 void launch_check0(int, int, int, int, int, const V*, const V*, const V*, const double*, const double*, double*,
                    double*, double*, int, int, int, hipStream_t);
 template <typename V, bool LOG>
+void launch_sink_check(int, int, int, int, int, const V*, const V*, const V*, const double*, const double*, double*,
+                       int, hipStream_t);
+template <typename V, bool LOG>
 void launch_flows(int, int, int, int, int, const int*, const int*, const V*, const double*, const V*, const V*,
                   const V*, const V*, const double*, const double*, double*, double*, int, hipStream_t);
 template <typename V, bool LOG>
@@ -156,6 +159,8 @@ struct mmot_solver {
   double *part = nullptr, *tpart = nullptr, *stats_dev = nullptr, *masses = nullptr;
   double *part_flow = nullptr, *tpart_flow = nullptr;
   double* part_cc = nullptr;   // dense check pass: commodity-capacity partials of the product's blocks
+  bool keep_fwd = false;       // forward messages of every time kept (see mmot_options::keep_forward)
+  bool hat_valid = false;      // the kept forward messages are those of the current scalings
   double *exc_row = nullptr, *exc = nullptr;
   int* exc_cnt = nullptr;
   int* flags = nullptr;
@@ -196,6 +201,13 @@ int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
 constexpr int64_t kStepWaves = 2048;    // a sweep step of fewer waves (two per SIMD) splits its rows
 constexpr int kEllMax = 16;
 constexpr int kDenseCommBlocks = 256;   // blocks of a dense check pass's commodity-capacity statistics    // widest ELL row (one gather batch); wider graphs use CSR
+
+// the kept forward messages serve the statistics of a fused check, which runs on
+// ELL operators of a fixed network without per-commodity epilogues
+bool keeps_forward(const mmot_problem* p, const mmot_options* o) {
+  return o->keep_forward != 0 && p->kind == MMOT_CSR && !p->cost_per_step && !p->state_cost && !p->cap_comm &&
+         p->T >= 2;
+}
 
 void set_geometry(mmot_solver* s) {
   s->vsize = (s->prec == MMOT_FP64) ? 8 : 4;
@@ -254,7 +266,7 @@ void carve(mmot_solver* s, Carver& c) {
   s->U01 = takev(n * Lp);
   s->U0T = takev(n * Lp);
   s->psi = takev(T * n * Lp);
-  s->zh = takev(2 * n * Lp);
+  s->zh = takev((s->keep_fwd ? T + 1 : 2) * n * Lp);
   s->u = takev(Tm1 * n);
   s->ones = takev(n);
   s->cb = c.take<double>((T + 1) * Lp);
@@ -320,6 +332,7 @@ mmot_status basic_checks(const mmot_problem* p, const mmot_options* o) {
   if (p->kind != MMOT_CSR && p->kind != MMOT_DENSE) return MMOT_EINVAL;
   if (p->cost_per_step != 0 && p->cost_per_step != 1) return MMOT_EINVAL;
   if (p->cap_comm_per_step != 0 && p->cap_comm_per_step != 1) return MMOT_EINVAL;
+  if (o->keep_forward != 0 && o->keep_forward != 1) return MMOT_EINVAL;
   if (p->kind == MMOT_DENSE) {
     // dense products run on MFMA in the scaled domain, FP32 or BF16 (+ FP32 polish)
     if (o->precision != MMOT_FP32 && o->precision != MMOT_BF16) return MMOT_EUNSUPPORTED;
@@ -348,7 +361,8 @@ struct Impl {
   static constexpr bool kLog = LOG;
   static V* pan(mmot_solver* s, void* base, size_t k) { return static_cast<V*>(base) + k * s->panel_elems(); }
   static V* psi(mmot_solver* s, int t) { return pan(s, s->psi, t); }
-  static V* zh(mmot_solver* s, int k) { return pan(s, s->zh, k & 1); }
+  // forward messages: panel k = time k when every time is kept, else two rolling panels
+  static V* zh(mmot_solver* s, int k) { return pan(s, s->zh, s->keep_fwd ? k : (k & 1)); }
   static V* uat(mmot_solver* s, int tau) {  // u at interior time tau (1..T-1)
     return (tau >= 1 && tau <= s->T - 1) ? static_cast<V*>(s->u) + (size_t)(tau - 1) * s->n : nullptr;
   }
@@ -502,8 +516,11 @@ struct Impl {
     return a;
   }
 
-  static void backward(mmot_solver* s, bool consume, bool calib, hipStream_t st) {
+  // check: a fused check (kept forward messages): the statistics of every time
+  // from this sweep's Psi_t and the kept hatPsi_t (Corollary 1), no forward pass
+  static void backward(mmot_solver* s, bool consume, bool calib, hipStream_t st, bool check = false) {
     const int T = s->T;
+    const size_t pstride = (size_t)s->nblk_s * kNSt;
     if (consume) {
       if (LOG && s->cslots_b)
         launch_levels64(s->cslots_b, s->slots_b, s->levb, T + 1, s->Lp, s->ncslot, s->nslot, st);
@@ -513,14 +530,39 @@ struct Impl {
     }
     launch_prep_bwd<V, LOG>(T, s->Lp, s->cb, s->sigb, static_cast<V*>(s->facb), s->gaugeT, s->lvlT, s->slotsE,
                             s->nslot, st);
+    if (check) {
+      // the weights 2^(sigma_hat_t + sigma_t) with this sweep's sigma (the kept panels
+      // carry the sigma_hat of their sweep, which the update-free preparation restores),
+      // then time T from the kept hatPsi_T and the current U0T
+      launch_prep_fwd<V, LOG>(T, s->Lp, 1, s->cf, s->sigf, s->sigb, static_cast<V*>(s->facf),
+                              static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, s->lvl0, s->slotsS, s->nslot, st);
+      launch_sink_check<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, zh(s, T), static_cast<const V*>(s->U0T),
+                                static_cast<const V*>(s->R0T), s->sigb + (size_t)T * s->Lp,
+                                s->sigf + (size_t)T * s->Lp, s->part + (size_t)T * pstride, s->nblk_s, st);
+    }
     if (s->kind == MMOT_DENSE && s->dense_bf16)
       launch_dense_operand(s->n, s->Lp, static_cast<const float*>(s->U0T), nullptr, bbuf(s, T), st);
     else if (s->kind == MMOT_DENSE)
       launch_dense_operand32(s->n, s->n8, s->Lp, static_cast<const float*>(s->U0T), nullptr, b32(s, T), st);
     for (int t = T - 1; t >= 0; --t) {
-      if (s->kind == MMOT_DENSE) dense_bwd(s, t, calib, st);
-      else launch_step<V, LOG>(bwd_args(s, t, calib), 0, s->nblk_s, st);
+      if (s->kind == MMOT_DENSE) {
+        dense_bwd(s, t, calib, st);
+        continue;
+      }
+      StepArgs<V> a = bwd_args(s, t, calib);
+      if (check && t >= 1) {
+        a.part = s->part + (size_t)t * pstride;
+        a.wpan = zh(s, t);
+        a.wgt = static_cast<const V*>(s->wgt) + (size_t)t * s->Lp;
+        a.uout = uat(s, t);
+        a.cap = static_cast<const V*>(s->cap) + (size_t)(t - 1) * s->n;
+      }
+      launch_step<V, LOG>(a, 0, s->nblk_s, st);
     }
+    if (check)
+      launch_check0<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, psi(s, 0), static_cast<const V*>(s->U01),
+                            static_cast<const V*>(s->R01), s->sigf, s->sigb, s->part, nullptr, nullptr, s->pc_lo,
+                            s->pc_cnt, s->nblk, st);
   }
 
   // forward product t -> t+1; mode 0 Sinkhorn update, mode 1 update-free pass
@@ -565,6 +607,7 @@ struct Impl {
       a.epi = 2;
       a.rdst = static_cast<const V*>(s->R0T);
       a.u0t = static_cast<V*>(s->U0T);
+      if (mode == 0 && s->keep_fwd) a.hatT = zh(s, T);
       a.sigT = s->sigb + (size_t)T * Lp;
       a.sighT = s->sigf + (size_t)T * Lp;
       if (mode == 0) {
@@ -798,7 +841,7 @@ struct Impl {
     launch_init_u0t<V, LOG>(static_cast<const V*>(s->R0T), n * Lp, static_cast<V*>(s->U0T), st);
     launch_fill<V>(static_cast<V*>(s->U01), n * Lp, zero, st);
     launch_fill<V>(static_cast<V*>(s->psi), T * n * Lp, zero, st);
-    launch_fill<V>(static_cast<V*>(s->zh), 2 * n * Lp, zero, st);
+    launch_fill<V>(static_cast<V*>(s->zh), (s->keep_fwd ? T + 1 : 2) * n * Lp, zero, st);
     for (int i = 0; i < 2; ++i)   // BF16 operand buffers: padding rows must stay zero
       if (s->Bbuf[i]) launch_fill<uint32_t>(reinterpret_cast<uint32_t*>(s->Bbuf[i]), (size_t)s->n8 * Lp / 2, 0u, st);
     for (int i = 0; i < 2; ++i)   // FP32 operand buffers: padding rows must stay zero
@@ -883,6 +926,7 @@ mmot_status run_iterations(mmot_solver* s, int n_iter) {
     s->pend_b = calib ? true : (cb ? false : s->pend_b);
     s->pend_f = calib;
     s->psi_fresh = false;
+    s->hat_valid = s->keep_fwd;
     if (s->force_calib > 0) --s->force_calib;
     ++s->iters;
   }
@@ -920,6 +964,15 @@ mmot_status collect_stats(mmot_solver* s, mmot_stats* out) {
 }
 
 mmot_status check_pass(mmot_solver* s, double* occ, double* pcomm, mmot_stats* out) {
+  if (out && !occ && !pcomm && s->keep_fwd && s->hat_valid && !s->psi_fresh && s->ellD > 0) {
+    // fused: the fresh backward sweep the check needs computes the statistics too
+    const bool cb = s->pend_b;
+    dispatch(s, [&](auto impl) { decltype(impl)::backward(s, cb, false, s->stream, true); return 0; });
+    s->pend_b = false;
+    s->psi_fresh = true;
+    if (hipGetLastError() != hipSuccess) return MMOT_EHIP;
+    return collect_stats(s, out);
+  }
   ensure_fresh(s);
   dispatch(s, [&](auto impl) { decltype(impl)::forward(s, 1, false, false, occ, pcomm, s->stream); return 0; });
   if (hipGetLastError() != hipSuccess) return MMOT_EHIP;
@@ -964,6 +1017,7 @@ mmot_status create_into(mmot_solver* s, const mmot_problem* p, const mmot_option
   if (!(s->opt.tol > 0)) s->opt.tol = 1e-6;
   s->prec = (o->precision == MMOT_FP64) ? MMOT_FP64 : MMOT_FP32;
   s->has_bf16 = s->dense_bf16 = o->precision == MMOT_BF16;
+  s->keep_fwd = keeps_forward(p, o);
   s->stream = static_cast<hipStream_t>(stream);
   set_geometry(s);
   uintptr_t b = reinterpret_cast<uintptr_t>(ws);
@@ -1019,7 +1073,7 @@ mmot_status create_into(mmot_solver* s, const mmot_problem* p, const mmot_option
     else if (fs != MMOT_OK) return fail(fs);
     else s->probe_clean = true;
     s->iters = 0;
-    s->psi_fresh = s->pend_b = s->pend_f = false;
+    s->psi_fresh = s->pend_b = s->pend_f = s->hat_valid = false;
     s->force_calib = 0;
     st = dispatch(s, [&](auto impl) { return decltype(impl)::setup(s, p); });
     if (st != MMOT_OK) return fail(st);
@@ -1078,6 +1132,7 @@ void mmot_default_options(mmot_options* o) {
   o->polish_iters = 20;
   o->use_graph = 1;
   o->tol = 1e-6;
+  o->keep_forward = 1;
 }
 
 mmot_status mmot_query_workspace(const mmot_problem* p, const mmot_options* o, size_t* bytes) {
@@ -1092,6 +1147,7 @@ mmot_status mmot_query_workspace(const mmot_problem* p, const mmot_options* o, s
   tmp.comm_steps = p->cap_comm_per_step ? std::max(p->T - 1, 1) : 1;
   tmp.prec = (o->precision == MMOT_FP64) ? MMOT_FP64 : MMOT_FP32;
   tmp.has_bf16 = o->precision == MMOT_BF16;
+  tmp.keep_fwd = keeps_forward(p, o);
   set_geometry(&tmp);
   Carver c{nullptr};
   carve(&tmp, c);
@@ -1275,7 +1331,7 @@ mmot_status mmot_set_comm_duals(mmot_solver* s, const double* log_w) {
                                   static_cast<V*>(s->wcomm), s->stream);
     return 0;
   });
-  s->psi_fresh = false;
+  s->psi_fresh = s->hat_valid = false;
   return hipGetLastError() == hipSuccess ? MMOT_OK : MMOT_EHIP;
 }
 
@@ -1300,7 +1356,7 @@ mmot_status mmot_set_log_duals(mmot_solver* s, const double* ls, const double* l
   launch_fill<uint32_t>(s->slotsS, (size_t)s->nslot * s->Lp, 0u, s->stream);
   launch_fill<double>(s->lvlT, s->Lp, 0.0, s->stream);
   launch_fill<double>(s->lvl0, s->Lp, 0.0, s->stream);
-  s->psi_fresh = false;
+  s->psi_fresh = s->hat_valid = false;
   s->force_calib = 2;
   return hipGetLastError() == hipSuccess ? MMOT_OK : MMOT_EHIP;
 }
@@ -1497,6 +1553,7 @@ mmot_status mmot_pool_submit(mmot_pool* P, const mmot_problem* prob, const mmot_
                              size_t ws_bytes, int32_t max_iter, uint64_t* ticket) {
   if (!P || !prob || !opt || !ticket || max_iter < 1) return MMOT_EINVAL;
   if (prob->kind != MMOT_CSR || opt->precision != MMOT_FP32) return MMOT_EUNSUPPORTED;
+  if (opt->keep_forward) return MMOT_EUNSUPPORTED;   // the pool keeps two forward panels per request
   size_t need = 0, solver_need = 0;
   mmot_status st = mmot_pool_query_workspace(prob, opt, &need);
   if (st != MMOT_OK) return st;
@@ -1692,7 +1749,7 @@ void mmot_pool_destroy(mmot_pool* P) {
 mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double* avg_ms) {
   if (!s || reps < 1 || !avg_ms) return MMOT_EINVAL;
   mmot_status st = dispatch(s, [&](auto impl) { return decltype(impl)::time_step(s, forward ? 1 : 0, reps, avg_ms); });
-  s->psi_fresh = false;   // the timed launches overwrite scratch message buffers
+  s->psi_fresh = s->hat_valid = false;   // the timed launches overwrite message buffers
   return st;
 }
 

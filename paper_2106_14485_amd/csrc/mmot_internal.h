@@ -66,6 +66,7 @@ struct StepArgs {
   V* uout;              // [n] u at the output time
   const V* rdst;        // sink: R0T panel (log2 in the log domain)
   V* u0t;               // sink: U0T panel (written when update)
+  V* hatT;              // sink update: hatPsi_T stored here as well (kept forward messages), nullptr = not
   const double* sigT;   // sink/check: [Lp] sigma of U0T (log2 units), sigma_hat of hatPsi_T
   const double* sighT;
   // column-level recording (log2 column maxima, encoded, slot p at base + p*nslot_stride)

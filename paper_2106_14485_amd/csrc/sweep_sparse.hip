@@ -426,6 +426,7 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
       if (cv) {
         V r[NV], cur[NV];
         vld(a.rdst + row * Lp + col, r);
+        if (!CHK && a.hatT) vst(a.hatT + row * Lp + col, o);
         if (LOG) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) plT[v] = r[v];
@@ -702,6 +703,13 @@ __host__ __device__ __forceinline__ bool ell_calib(const StepArgs<V>& a) {
   return a.ellD > 0 && !a.cw && !a.kl && !a.slots_o && a.epi != 2 && (a.epi == 0 || a.update) && !a.part &&
          !a.occ && !a.pcomm && a.out && (a.slots || a.cslots_b);
 }
+// a backward step of a fused check: the statistics of P_t from the fresh Psi_t and
+// the kept hatPsi_t (wpan), weights wgt, u_t (uout) and d_t (cap)
+template <typename V>
+__host__ __device__ __forceinline__ bool ell_bcheck(const StepArgs<V>& a) {
+  return a.ellD > 0 && !a.cw && !a.kl && !a.slots && !a.slots_o && !a.cslots_b && !a.cslots_f && a.epi == 0 &&
+         a.part && !a.pcomm && !a.occ && a.out && a.wpan && a.wgt && a.uout && a.cap;
+}
 // every wave of the step has exactly one column chunk of its row
 template <typename V>
 __host__ __device__ __forceinline__ bool ell_one_chunk(const StepArgs<V>& a) {
@@ -715,12 +723,14 @@ __host__ __device__ __forceinline__ bool ell_one_chunk(const StepArgs<V>& a) {
 // for before any gather was issued, one more memory round trip per row (RGG
 // workload, with the wait below: forward step 5.10 -> 4.61 us, backward 4.10 ->
 // 3.69 us; on the road grid's rows of eight chunks the same order measured 3% slower).
-// CHK (forward only): the check pass's update-free step (ell_check), the row-end
-// statistics of step_body's check mode operation for operation.  CAL: a step of a
+// CHK: the check pass's update-free forward step (ell_check), the row-end
+// statistics of step_body's check mode operation for operation; on a backward step
+// (ell_bcheck) the same statistics with the roles of the panels exchanged: the
+// product is Psi_t, the row read at its side the kept forward message hatPsi_t
+// (K_L = 1), the weights 2^(sigma_hat_t + sigma_t) (a fused check).  CAL: a step of a
 // calibration sweep (ell_calib), each chunk's levels or keys recorded after its store.
 template <typename V, bool LOG, bool FWD, int KB, bool ONE, bool CHK = false, bool CAL = false>
 __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int nblk) {
-  static_assert(FWD || !CHK, "the check pass runs forward steps");
   static_assert(!(CHK && CAL), "the check pass records no levels");
   constexpr int NV = VT<V>::N;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -778,7 +788,7 @@ __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int
     }
     V f[NV], w[NV], g[NV];
     vld(a.fac + colc, f);
-    if (FWD) {
+    if (FWD || CHK) {
       vld(a.wpan + rowc * Lp + colc, w);
       vld(a.wgt + colc, g);
     }
@@ -820,7 +830,7 @@ __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int
     }
     // (ONE: computed on every lane and kept where cv, so that the loads of w and g,
     // used on every path, are not sunk below the wait for the gathers)
-    if (FWD && (ONE || cv)) {
+    if ((FWD || CHK) && (ONE || cv)) {
       if (!LOG) {
         V t = ssum;
 #pragma unroll
@@ -863,7 +873,7 @@ __device__ __forceinline__ void ell_step_body(const StepArgs<V>& a, int bid, int
     }
   }
 
-  if (FWD) {
+  if (FWD || CHK) {
     V sv;
     if (!LOG) sv = group_sum(ssum, G);
     else group_lse(lm, ls, G);
@@ -1442,6 +1452,62 @@ __global__ void k_reduce_cost(const double* __restrict__ tflow, const double* __
 // host-side launchers (explicit instantiations)
 // ---------------------------------------------------------------------------
 // fwd: 0 backward product, 1 forward Sinkhorn step, 2 forward update-free (check / output) step
+// Time-T statistics of a fused check: P_{0,T} = U0T (.) hatPsi_T from the kept
+// hatPsi_T of the last Sinkhorn sweep (the forward message the sink update divided
+// R0T by), as the sink step's check mode computes them (mass, <R0T, log U0T>, gap);
+// partials of nblk blocks (rows grid-stride), one per block.
+template <typename V, bool LOG>
+__global__ __launch_bounds__(kBlock) void k_sink_check(int n, int Lp, int L, int G, int nchunk,
+                                                       const V* __restrict__ hat, const V* __restrict__ u0t,
+                                                       const V* __restrict__ rdst, const double* __restrict__ sigT,
+                                                       const double* __restrict__ sighT, double* part) {
+  constexpr int NV = VT<V>::N;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int grp = lane / G, gl = lane & (G - 1), rpw = 64 / G;
+  double st[kNSt] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int r0 = (blockIdx.x * kWaves + wave) * rpw; r0 < n; r0 += gridDim.x * kWaves * rpw) {
+    const int row = r0 + grp;
+    if (row >= n) continue;
+    for (int ch = 0; ch < nchunk; ++ch) {
+      const int col = (ch * G + gl) * NV;
+      if (col >= Lp) continue;
+      V z[NV], o[NV], r[NV];
+      vld(u0t + (size_t)row * Lp + col, z);
+      vld(hat + (size_t)row * Lp + col, o);
+      vld(rdst + (size_t)row * Lp + col, r);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const int l = col + v;
+        if (l >= L) continue;
+        const double sg = sigT[l] + sighT[l];
+        double P, lnU, R;
+        if (!LOG) {
+          P = (double)z[v] * (double)o[v] * exp2(sg);
+          lnU = (z[v] > V(0)) ? (log2((double)z[v]) + sigT[l]) * M_LN2 : 0.0;
+          R = (double)r[v];
+        } else {
+          P = (z[v] == ninf<V>() || o[v] == ninf<V>()) ? 0.0 : exp2((double)z[v] + (double)o[v] + sg);
+          lnU = (z[v] != ninf<V>()) ? ((double)z[v] + sigT[l]) * M_LN2 : 0.0;
+          R = (r[v] == ninf<V>()) ? 0.0 : exp2((double)r[v]);
+        }
+        st[ST_MASS] += P;
+        st[ST_DUAL] += R * lnU;
+        st[ST_GAP] += lnU * (P - R);
+      }
+    }
+  }
+  block_stats(st, part, blockIdx.x);
+}
+template <typename V, bool LOG>
+void launch_sink_check(int n, int Lp, int L, int G, int nchunk, const V* hat, const V* u0t, const V* rdst,
+                       const double* sigT, const double* sighT, double* part, int nblk, hipStream_t s) {
+  hipLaunchKernelGGL((k_sink_check<V, LOG>), dim3(nblk), dim3(kBlock), 0, s, n, Lp, L, G, nchunk, hat, u0t, rdst,
+                     sigT, sighT, part);
+}
+
+__global__ void k_or_flag(int* flags, int v) {
+  if (threadIdx.x == 0) atomicOr(flags, v);
+}
 template <typename V, bool LOG>
 void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
   if (record_item(fwd == 0 ? IK_STEP_BWD : (fwd == 1 ? IK_STEP_FWD : IK_STEP_CHK), LOG, nblk, &a, sizeof(a))) return;
@@ -1458,6 +1524,7 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
   do {                                                                                                             \
     if (fwd == 2) hipLaunchKernelGGL((k_ell_step<V, LOG, true, K, O, true>), dim3(nblk), dim3(kBlock), 0, s, a);    \
     else if (fwd == 1) hipLaunchKernelGGL((k_ell_step<V, LOG, true, K, O, false>), dim3(nblk), dim3(kBlock), 0, s, a); \
+    else if (a.part) hipLaunchKernelGGL((k_ell_step<V, LOG, false, K, O, true>), dim3(nblk), dim3(kBlock), 0, s, a); \
     else hipLaunchKernelGGL((k_ell_step<V, LOG, false, K, O, false>), dim3(nblk), dim3(kBlock), 0, s, a);          \
   } while (0)
 #define MMOT_ELL_LAUNCH(K)                                                                                          \
@@ -1465,7 +1532,13 @@ void launch_step(const StepArgs<V>& a, int fwd, int nblk, hipStream_t s) {
     if (one) MMOT_ELL_LAUNCH1(K, true);                                                                            \
     else MMOT_ELL_LAUNCH1(K, false);                                                                               \
   } while (0)
-  if (fwd != 2 ? ell_fast(a) : ell_check(a)) {
+  if (fwd == 0 && a.part && !ell_bcheck(a)) {
+    // a backward step computes statistics only in that form (the caller checks):
+    // anything else is a host error, reported through the flags, never run half-done
+    hipLaunchKernelGGL(k_or_flag, dim3(1), dim3(64), 0, s, a.flags, (int)FLAG_BADINPUT);
+    return;
+  }
+  if (fwd == 2 ? ell_check(a) : (a.part ? ell_bcheck(a) : ell_fast(a))) {
     const bool one = ell_one_chunk(a);
     if (a.ellD == 16) MMOT_ELL_LAUNCH(16);
     else if (a.ellD == 8) MMOT_ELL_LAUNCH(8);
@@ -1714,6 +1787,8 @@ bool pool_item_is_light(const PoolItem& it) {
 
 #define MMOT_INST(V, LOG)                                                                                         \
   template void launch_step<V, LOG>(const StepArgs<V>&, int, int, hipStream_t);                                       \
+  template void launch_sink_check<V, LOG>(int, int, int, int, int, const V*, const V*, const V*, const double*,    \
+                                          const double*, double*, int, hipStream_t);                                 \
   template void launch_source<V, LOG>(int, int, int, int, const V*, const V*, V*, uint32_t*, int, size_t, int*,   \
                                       unsigned long long*, int, size_t, int, hipStream_t);                        \
   template void launch_check0<V, LOG>(int, int, int, int, int, const V*, const V*, const V*, const double*,      \

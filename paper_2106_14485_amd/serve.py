@@ -28,7 +28,9 @@ class Pool:
     def __init__(self, hbm_budget_bytes: int, device="cuda", stream=None, check_every=10, tol=1e-6):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self.opts = default_options(precision="fp32", domain="auto", check_every=check_every, tol=tol)
+        # (the pool keeps two forward panels per request: a smaller workspace per solve)
+        self.opts = default_options(precision="fp32", domain="auto", check_every=check_every, tol=tol,
+                                    keep_forward=0)
         h = ctypes.c_void_p(0)
         check(_lib.lib().mmot_pool_create(int(hbm_budget_bytes), ctypes.c_void_p(self.stream.cuda_stream),
                                           ctypes.byref(h)), "mmot_pool_create")
@@ -173,7 +175,8 @@ def serve_plain(instances, arrivals, max_iter=500, check_every=10, tol=1e-6, pro
             time.sleep(arrivals[i] - now)
         st, status = None, 0
         try:
-            S = Solver(instances[i], precision="fp32", domain="auto", check_every=check_every, tol=tol)
+            S = Solver(instances[i], precision="fp32", domain="auto", check_every=check_every, tol=tol,
+                       keep_forward=0)   # the pool's options: the same iterates and checks
             try:
                 st = S.solve(max_iter)
             finally:

@@ -42,9 +42,20 @@ def test_host_only_entry_points():
     p = _lib.Problem()
     p.n, p.L, p.T, p.eps, p.kind, p.nnz = 2000, 256, 50, 0.05, _lib.MMOT_CSR, 18430
     nb = ctypes.c_size_t(0)
+    assert o.keep_forward == 1
     assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_OK
-    # 50 stored message panels of 2000 x 256 floats dominate the footprint
-    assert 50 * 2000 * 256 * 4 < nb.value < 2 * 50 * 2000 * 256 * 4
+    # 50 stored backward and 51 kept forward message panels of 2000 x 256 floats
+    # dominate the footprint; without kept forward messages, two rolling ones
+    panel = 2000 * 256 * 4
+    keep = nb.value
+    assert 101 * panel < keep < 2 * 101 * panel
+    o.keep_forward = 0
+    assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_OK
+    assert keep - nb.value == 49 * panel
+    assert 52 * panel < nb.value < 2 * 52 * panel
+    o.keep_forward = 2
+    assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_EINVAL
+    o.keep_forward = 1
     p.eps = -1.0
     assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_EINVAL
     p.eps = 0.05

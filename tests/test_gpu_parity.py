@@ -229,6 +229,44 @@ def test_bench_schedule_matches_oracle():
     assert abs(g["stats"]["dual_obj"] - o["g"][-1]) <= 1e-5 * abs(o["g"][-1])
 
 
+@pytest.mark.parametrize("kind,prec,dom", [("rgg", "fp32", "scaled"), ("rgg", "fp64", "scaled"),
+                                           ("rgg", "fp64", "log"), ("road", "fp32", "log"),
+                                           ("rgg_narrow", "fp32", "log")])
+def test_fused_check_matches_the_forward_check(kind, prec, dom):
+    """With kept forward messages a check takes its statistics from the fresh
+    backward sweep (P_t = u_t sum_l hatPsi_t Psi_t K_L, Corollary 1, the products
+    with the roles of the panels exchanged) instead of an update-free forward
+    sweep: the same statistics up to rounding order (FP64 1e-12, FP32 1e-6
+    relative; the source residual, from the same time-0 kernel, bitwise), and the
+    iterations after the check are bitwise the same.  The road grid's rows take
+    eight column chunks per wave, the RGG rows one (L = 256) or a fraction of a
+    wave (L = 24)."""
+    if kind == "road":
+        inst = instances.road_grid_instance(side=12, L=600, T=16, eps=0.1, seed=41)
+    elif kind == "rgg_narrow":
+        inst = instances.rgg_instance(n=500, L=24, T=14, seed=42)
+    else:
+        inst = instances.rgg_instance(n=700, L=256, T=12, seed=43)
+    out = []
+    for keep in (1, 0):
+        S = _solver()(inst, precision=prec, domain=dom, keep_forward=keep)
+        S.iterate(12)
+        st = S.stats()
+        S.iterate(5)
+        duals = [d.cpu().numpy() for d in S.log_duals()]
+        assert S.opts.keep_forward == keep
+        S.close()
+        out.append((st, duals))
+    (a, da), (b, db) = out
+    tol = 1e-12 if prec == "fp64" else 1e-6
+    assert a["src_resid"] == b["src_resid"]
+    for k in ("dual_obj", "cap_viol", "mass", "dual_gap"):
+        assert abs(a[k] - b[k]) <= tol * max(1.0, abs(b[k])), (k, a[k], b[k])
+    assert abs(a["mass_drift"] - b["mass_drift"]) <= (1e-12 if prec == "fp64" else 1e-5)
+    for x, y in zip(da, db):
+        assert np.array_equal(x, y)
+
+
 def test_deterministic_repeat():
     inst = instances.rgg_instance(n=400, L=64, T=10, seed=5)
     a = gpu_outputs(inst, 15, "fp32", "auto")

@@ -22,7 +22,8 @@ def _mix():
 
 def _plain(inst, max_iter):
     from paper_2106_14485_amd.solver import Solver
-    S = Solver(inst, precision="fp32", domain="auto", check_every=10, tol=1e-6)
+    # (the pool's options: two forward panels, checks by an update-free forward pass)
+    S = Solver(inst, precision="fp32", domain="auto", check_every=10, tol=1e-6, keep_forward=0)
     st = S.solve(max_iter)
     occ = S.occupancy().cpu().numpy()
     S.close()
@@ -155,6 +156,12 @@ def test_workspace_exactly_the_queried_size():
                               ctypes.byref(t)) == _lib.MMOT_OK
     while pool.run(64) > 0:
         pass
+    # (a request asking for kept forward messages is refused before anything is done)
+    o1 = _lib.Options.from_buffer_copy(pool.opts)
+    o1.keep_forward = 1
+    t1 = ctypes.c_uint64(0)
+    assert L.mmot_pool_submit(pool._h, ctypes.byref(p), ctypes.byref(o1), _ptr(ws), nbytes, 20,
+                              ctypes.byref(t1)) == _lib.MMOT_EUNSUPPORTED
     state, status, st = pool.poll(t.value)
     assert state == 1 and status == 0
     s = L.mmot_pool_solver(pool._h, ctypes.c_uint64(t.value))
