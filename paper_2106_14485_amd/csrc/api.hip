@@ -161,6 +161,7 @@ struct mmot_solver {
   double* part_cc = nullptr;   // dense check pass: commodity-capacity partials of the product's blocks
   bool keep_fwd = false;       // forward messages of every time kept (see mmot_options::keep_forward)
   bool hat_valid = false;      // the kept forward messages are those of the current scalings
+  bool keep_now = false;       // the forward sweep being recorded keeps every time's message
   double *exc_row = nullptr, *exc = nullptr;
   int* exc_cnt = nullptr;
   int* flags = nullptr;
@@ -361,8 +362,10 @@ struct Impl {
   static constexpr bool kLog = LOG;
   static V* pan(mmot_solver* s, void* base, size_t k) { return static_cast<V*>(base) + k * s->panel_elems(); }
   static V* psi(mmot_solver* s, int t) { return pan(s, s->psi, t); }
-  // forward messages: panel k = time k when every time is kept, else two rolling panels
-  static V* zh(mmot_solver* s, int k) { return pan(s, s->zh, s->keep_fwd ? k : (k & 1)); }
+  // forward messages: panel k = time k in a sweep that keeps them (the last Sinkhorn
+  // sweep before a check), else two rolling panels (0 and 1)
+  static V* zh(mmot_solver* s, int k) { return pan(s, s->zh, s->keep_now ? k : (k & 1)); }
+  static V* zh_kept(mmot_solver* s, int k) { return pan(s, s->zh, k); }
   static V* uat(mmot_solver* s, int tau) {  // u at interior time tau (1..T-1)
     return (tau >= 1 && tau <= s->T - 1) ? static_cast<V*>(s->u) + (size_t)(tau - 1) * s->n : nullptr;
   }
@@ -536,7 +539,7 @@ struct Impl {
       // then time T from the kept hatPsi_T and the current U0T
       launch_prep_fwd<V, LOG>(T, s->Lp, 1, s->cf, s->sigf, s->sigb, static_cast<V*>(s->facf),
                               static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, s->lvl0, s->slotsS, s->nslot, st);
-      launch_sink_check<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, zh(s, T), static_cast<const V*>(s->U0T),
+      launch_sink_check<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, zh_kept(s, T), static_cast<const V*>(s->U0T),
                                 static_cast<const V*>(s->R0T), s->sigb + (size_t)T * s->Lp,
                                 s->sigf + (size_t)T * s->Lp, s->part + (size_t)T * pstride, s->nblk_s, st);
     }
@@ -552,7 +555,7 @@ struct Impl {
       StepArgs<V> a = bwd_args(s, t, calib);
       if (check && t >= 1) {
         a.part = s->part + (size_t)t * pstride;
-        a.wpan = zh(s, t);
+        a.wpan = zh_kept(s, t);
         a.wgt = static_cast<const V*>(s->wgt) + (size_t)t * s->Lp;
         a.uout = uat(s, t);
         a.cap = static_cast<const V*>(s->cap) + (size_t)(t - 1) * s->n;
@@ -607,7 +610,7 @@ struct Impl {
       a.epi = 2;
       a.rdst = static_cast<const V*>(s->R0T);
       a.u0t = static_cast<V*>(s->U0T);
-      if (mode == 0 && s->keep_fwd) a.hatT = zh(s, T);
+      if (mode == 0 && s->keep_now) a.hatT = zh_kept(s, T);
       a.sigT = s->sigb + (size_t)T * Lp;
       a.sighT = s->sigf + (size_t)T * Lp;
       if (mode == 0) {
@@ -903,7 +906,11 @@ mmot_status run_iterations(mmot_solver* s, int n_iter) {
                         (s->opt.calib_every > 0 && s->iters % s->opt.calib_every == 0));
     const bool runB = !s->psi_fresh;
     const bool cb = runB && s->pend_b, cf = s->pend_f;
-    const int key = (runB ? 1 : 0) | (cb ? 2 : 0) | (calib ? 4 : 0) | (cf ? 8 : 0) | (s->dense_bf16 ? 16 : 0);
+    // the last sweep of the call keeps every forward message (for a fused check);
+    // the others write two rolling panels, which stay resident in the last-level cache
+    s->keep_now = s->keep_fwd && k == n_iter - 1;
+    const int key = (runB ? 1 : 0) | (cb ? 2 : 0) | (calib ? 4 : 0) | (cf ? 8 : 0) | (s->dense_bf16 ? 16 : 0) |
+                    (s->keep_now ? 32 : 0);
     if (s->opt.use_graph) {
       auto it = s->graphs.find(key);
       if (it == s->graphs.end()) {
@@ -926,7 +933,8 @@ mmot_status run_iterations(mmot_solver* s, int n_iter) {
     s->pend_b = calib ? true : (cb ? false : s->pend_b);
     s->pend_f = calib;
     s->psi_fresh = false;
-    s->hat_valid = s->keep_fwd;
+    s->hat_valid = s->keep_now;
+    s->keep_now = false;
     if (s->force_calib > 0) --s->force_calib;
     ++s->iters;
   }
@@ -975,6 +983,7 @@ mmot_status check_pass(mmot_solver* s, double* occ, double* pcomm, mmot_stats* o
   }
   ensure_fresh(s);
   dispatch(s, [&](auto impl) { decltype(impl)::forward(s, 1, false, false, occ, pcomm, s->stream); return 0; });
+  s->hat_valid = false;   // (its rolling panels overlap the kept ones)
   if (hipGetLastError() != hipSuccess) return MMOT_EHIP;
   if (!out && !pcomm && !occ) return MMOT_OK;
   if (out) return collect_stats(s, out);
@@ -1279,6 +1288,7 @@ mmot_status mmot_edge_flows(mmot_solver* s, double* flow, double* cost_host) {
   if (!s || !flow) return MMOT_EINVAL;
   ensure_fresh(s);
   dispatch(s, [&](auto impl) { decltype(impl)::flows_pass(s, flow, s->stream); return 0; });
+  s->hat_valid = false;   // (its rolling panels overlap the kept ones)
   if (hipGetLastError() != hipSuccess) return MMOT_EHIP;
   if (cost_host) {
     if (hipMemcpyAsync(s->host_stats + 7, s->stats_dev + 7, sizeof(double), hipMemcpyDeviceToHost, s->stream) !=
