@@ -108,13 +108,15 @@ typedef struct mmot_options {
   int32_t polish_iters;  /* BF16: FP32 iterations appended by mmot_solve (default 20) */
   int32_t use_graph;     /* capture one iteration in a HIP graph (default 1) */
   double tol;            /* mmot_solve: stop when src_resid <= tol and cap_viol <= tol (default 1e-6) */
-  /* 1 (default): keep the forward messages of every time (T - 1 more n x L panels
-   * on sparse networks without state costs or commodity capacities), so that a
-   * convergence check after Sinkhorn sweeps takes its statistics from the fresh
+  /* 1 (default): room for the forward messages of every time (T - 1 more n x L
+   * panels on sparse networks without state costs or commodity capacities; the
+   * last Sinkhorn sweep of each mmot_iterate / mmot_solve chunk fills them), so
+   * that the convergence check after it takes its statistics from the fresh
    * backward sweep it needs anyway (Corollary 1: P_t = u_t sum_l hatPsi_t Psi_t
    * K_L), without an extra update-free forward sweep.  0: two rolling forward
    * panels.  The serving pool runs 0 (mmot_pool_submit rejects 1 with
-   * MMOT_EUNSUPPORTED).  The two give the same statistics up to rounding order. */
+   * MMOT_EUNSUPPORTED).  The two give the same statistics up to rounding order
+   * and the same iterates. */
   int32_t keep_forward;
 } mmot_options;
 
