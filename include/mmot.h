@@ -109,7 +109,8 @@ typedef struct mmot_options {
   int32_t use_graph;     /* capture one iteration in a HIP graph (default 1) */
   double tol;            /* mmot_solve: stop when src_resid <= tol and cap_viol <= tol (default 1e-6) */
   /* 1 (default): room for the forward messages of every time (T - 1 more n x L
-   * panels on sparse networks without state costs or commodity capacities; the
+   * panels without state costs or commodity capacities, on a fixed network when
+   * sparse; the
    * last Sinkhorn sweep of each mmot_iterate / mmot_solve chunk fills them), so
    * that the convergence check after it takes its statistics from the fresh
    * backward sweep it needs anyway (Corollary 1: P_t = u_t sum_l hatPsi_t Psi_t

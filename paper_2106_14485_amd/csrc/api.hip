@@ -206,7 +206,7 @@ constexpr int kDenseCommBlocks = 256;   // blocks of a dense check pass's commod
 // the kept forward messages serve the statistics of a fused check, which runs on
 // ELL operators of a fixed network without per-commodity epilogues
 bool keeps_forward(const mmot_problem* p, const mmot_options* o) {
-  return o->keep_forward != 0 && p->kind == MMOT_CSR && !p->cost_per_step && !p->state_cost && !p->cap_comm &&
+  return o->keep_forward != 0 && (p->kind == MMOT_DENSE || !p->cost_per_step) && !p->state_cost && !p->cap_comm &&
          p->T >= 2;
 }
 
@@ -417,7 +417,9 @@ struct Impl {
   // after each product and capacity update and at the start of each sweep
   static uint16_t* bbuf(mmot_solver* s, int t) { return s->Bbuf[t & 1]; }
   static float* b32(mmot_solver* s, int t) { return s->B32buf[t & 1]; }
-  static void dense_bwd(mmot_solver* s, int t, bool calib, hipStream_t st) {
+  // check: a fused check's product (t >= 1): the capacity partial sums of P_t with
+  // the kept hatPsi_t, then the row statistics of time t
+  static void dense_bwd(mmot_solver* s, int t, bool calib, hipStream_t st, bool check = false) {
     GemmArgs g = gemm_base(s, false, t);
     if (s->dense_bf16) {
       g.Bb = bbuf(s, t + 1);
@@ -431,7 +433,19 @@ struct Impl {
     g.cw = reinterpret_cast<const float*>(wat(s, t));
     g.slots = calib ? s->slots_b + (size_t)t * s->Lp : nullptr;
     g.slot_stride = (size_t)(s->T + 1) * s->Lp;
+    const bool chk = check && t >= 1;
+    if (chk) {
+      g.cap = 1;
+      g.wpan = reinterpret_cast<const float*>(zh_kept(s, t));
+      g.wgt = reinterpret_cast<const float*>(static_cast<V*>(s->wgt) + (size_t)t * s->Lp);
+      g.part_s = s->part_s;
+    }
     launch_gemm(g, s->dense_bf16, st);
+    if (chk)
+      launch_dense_rows(s->n, s->ntn, s->part_s,
+                        reinterpret_cast<const float*>(static_cast<V*>(s->cap) + (size_t)(t - 1) * s->n),
+                        reinterpret_cast<float*>(uat(s, t)), 0, s->part + (size_t)t * s->nblk_s * kNSt, nullptr,
+                        nullptr, nullptr, nullptr, s->n8, s->Lp, s->nblk, nullptr, 0, st);
     if (!s->dense_bf16 && t >= 1)
       launch_dense_operand32(s->n, s->n8, s->Lp, reinterpret_cast<const float*>(psi(s, t)),
                              reinterpret_cast<const float*>(uat(s, t)), b32(s, t), st);
@@ -539,9 +553,17 @@ struct Impl {
       // then time T from the kept hatPsi_T and the current U0T
       launch_prep_fwd<V, LOG>(T, s->Lp, 1, s->cf, s->sigf, s->sigb, static_cast<V*>(s->facf),
                               static_cast<V*>(s->wgt), s->gauge0, s->gaugeT, s->lvl0, s->slotsS, s->nslot, st);
-      launch_sink_check<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, zh_kept(s, T), static_cast<const V*>(s->U0T),
-                                static_cast<const V*>(s->R0T), s->sigb + (size_t)T * s->Lp,
-                                s->sigf + (size_t)T * s->Lp, s->part + (size_t)T * pstride, s->nblk_s, st);
+      if (s->kind == MMOT_DENSE)
+        launch_dense_sink(s->n, s->Lp, s->L, reinterpret_cast<const float*>(zh_kept(s, T)),
+                          reinterpret_cast<const float*>(s->R0T), reinterpret_cast<float*>(s->U0T), 0,
+                          s->sigb + (size_t)T * s->Lp, s->sigf + (size_t)T * s->Lp, s->slotsE, s->nslot, nullptr,
+                          (size_t)(T + 1) * s->Lp, s->flags, s->part + (size_t)T * pstride, nullptr, nullptr,
+                          s->pc_lo, s->pc_cnt, s->nblk, st);
+      else
+        launch_sink_check<V, LOG>(s->n, s->Lp, s->L, s->G, s->nchunk, zh_kept(s, T),
+                                  static_cast<const V*>(s->U0T), static_cast<const V*>(s->R0T),
+                                  s->sigb + (size_t)T * s->Lp, s->sigf + (size_t)T * s->Lp,
+                                  s->part + (size_t)T * pstride, s->nblk_s, st);
     }
     if (s->kind == MMOT_DENSE && s->dense_bf16)
       launch_dense_operand(s->n, s->Lp, static_cast<const float*>(s->U0T), nullptr, bbuf(s, T), st);
@@ -549,7 +571,7 @@ struct Impl {
       launch_dense_operand32(s->n, s->n8, s->Lp, static_cast<const float*>(s->U0T), nullptr, b32(s, T), st);
     for (int t = T - 1; t >= 0; --t) {
       if (s->kind == MMOT_DENSE) {
-        dense_bwd(s, t, calib, st);
+        dense_bwd(s, t, calib, st, check);
         continue;
       }
       StepArgs<V> a = bwd_args(s, t, calib);
@@ -972,7 +994,8 @@ mmot_status collect_stats(mmot_solver* s, mmot_stats* out) {
 }
 
 mmot_status check_pass(mmot_solver* s, double* occ, double* pcomm, mmot_stats* out) {
-  if (out && !occ && !pcomm && s->keep_fwd && s->hat_valid && !s->psi_fresh && s->ellD > 0) {
+  if (out && !occ && !pcomm && s->keep_fwd && s->hat_valid && !s->psi_fresh &&
+      (s->kind == MMOT_DENSE || s->ellD > 0)) {
     // fused: the fresh backward sweep the check needs computes the statistics too
     const bool cb = s->pend_b;
     dispatch(s, [&](auto impl) { decltype(impl)::backward(s, cb, false, s->stream, true); return 0; });
@@ -1267,6 +1290,7 @@ mmot_status mmot_set_precision(mmot_solver* s, int32_t precision) {
   } else {
     return MMOT_EUNSUPPORTED;
   }
+  s->hat_valid = false;   // (kept forward messages of the other precision)
   return MMOT_OK;
 }
 

@@ -231,7 +231,8 @@ def test_bench_schedule_matches_oracle():
 
 @pytest.mark.parametrize("kind,prec,dom", [("rgg", "fp32", "scaled"), ("rgg", "fp64", "scaled"),
                                            ("rgg", "fp64", "log"), ("road", "fp32", "log"),
-                                           ("rgg_narrow", "fp32", "log")])
+                                           ("rgg_narrow", "fp32", "log"), ("dense", "fp32", "auto"),
+                                           ("dense", "bf16", "auto")])
 def test_fused_check_matches_the_forward_check(kind, prec, dom):
     """With kept forward messages a check takes its statistics from the fresh
     backward sweep (P_t = u_t sum_l hatPsi_t Psi_t K_L, Corollary 1, the products
@@ -240,8 +241,11 @@ def test_fused_check_matches_the_forward_check(kind, prec, dom):
     relative; the source residual, from the same time-0 kernel, bitwise), and the
     iterations after the check are bitwise the same.  The road grid's rows take
     eight column chunks per wave, the RGG rows one (L = 256) or a fraction of a
-    wave (L = 24)."""
-    if kind == "road":
+    wave (L = 24); on a dense network the backward products of the check form the
+    capacity partial sums with the kept hatPsi_t (FP32 and BF16 products)."""
+    if kind == "dense":
+        inst = instances.dense_blob_instance(n=300, L=40, T=8, seed=44)
+    elif kind == "road":
         inst = instances.road_grid_instance(side=12, L=600, T=16, eps=0.1, seed=41)
     elif kind == "rgg_narrow":
         inst = instances.rgg_instance(n=500, L=24, T=14, seed=42)
