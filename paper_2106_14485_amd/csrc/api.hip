@@ -200,11 +200,13 @@ namespace {
 
 int next_pow2(int x) { int p = 1; while (p < x) p <<= 1; return p; }
 constexpr int64_t kStepWaves = 2048;    // a sweep step of fewer waves (two per SIMD) splits its rows
-constexpr int kEllMax = 16;
-constexpr int kDenseCommBlocks = 256;   // blocks of a dense check pass's commodity-capacity statistics    // widest ELL row (one gather batch); wider graphs use CSR
+constexpr int kEllMax = 16;    // widest ELL row (one gather batch); wider graphs use CSR
+constexpr int kDenseCommBlocks = 256;   // blocks of a dense check pass's commodity-capacity statistics
 
 // the kept forward messages serve the statistics of a fused check, which runs on
-// ELL operators of a fixed network without per-commodity epilogues
+// dense networks and on ELL operators of a fixed sparse network, without
+// per-commodity epilogues (a sparse network whose rows turn out wider than an ELL
+// row keeps the room unused and checks by a forward pass)
 bool keeps_forward(const mmot_problem* p, const mmot_options* o) {
   return o->keep_forward != 0 && (p->kind == MMOT_DENSE || !p->cost_per_step) && !p->state_cost && !p->cap_comm &&
          p->T >= 2;
