@@ -36,10 +36,10 @@ HBM_PEAK_GBS = 8000.0
 # one the counters were taken from.
 TRAFFIC = {
     "road100": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "a40af384219f06edd81703b5036028b70d16e5060c41312e69f8c0e7f66e5a80",
+                "sha256": "c7ba77027e13b362439b292c6ae2aa481d6d26ebb6e63bb3f1d84c34a4d1dcaf",
                 "fetch_kib": 87589.447, "write_kib": 79433.356, "fetch_scale": 2.0, "write_scale": 1.0},
     "rgg2000": {"source": "paper_2106_14485_amd/csrc/sweep_sparse.hip",
-                "sha256": "a40af384219f06edd81703b5036028b70d16e5060c41312e69f8c0e7f66e5a80",
+                "sha256": "c7ba77027e13b362439b292c6ae2aa481d6d26ebb6e63bb3f1d84c34a4d1dcaf",
                 "fetch_kib": 2407.656, "write_kib": 2007.938, "fetch_scale": 2.0, "write_scale": 1.0},
 }
 

@@ -675,8 +675,10 @@ __device__ __forceinline__ void step_body(const StepArgs<V>& a, int bid, int nbl
 // the steady-state ELL step
 // ---------------------------------------------------------------------------
 // Every step of a sweep on an ELL operator except the sink update: backward
-// products and forward products with the capacity update, outside calibration
-// sweeps and check passes, without state costs or commodity capacities.  The
+// products and forward products with the capacity update (ell_fast), and as
+// compile-time variants the steps of check passes (ell_check, ell_bcheck) and of
+// FP32 calibration sweeps (ell_calib), without state costs or commodity
+// capacities.  The
 // arithmetic is step_body's, operation for operation (the results are bitwise
 // the same); the difference is that nothing here is decided at run time, so
 // a chunk's loads -- the neighbour rows, the factor row and (forward) the
