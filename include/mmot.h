@@ -259,7 +259,8 @@ mmot_status mmot_time_step(mmot_solver* s, int32_t forward, int32_t reps, double
  * (host, nullable) and the stream, which must belong to the current device.
  * Same results as that sequence of calls (same kernels; iterations are
  * launched directly, never through captured graphs).  ENOMEM when the problem's
- * workspace (mmot_query_workspace) exceeds MMOT_STATIC_WORKSPACE_BYTES; the
+ * workspace (mmot_query_workspace, with the options given: keep_forward = 0
+ * needs T - 1 panels fewer) exceeds MMOT_STATIC_WORKSPACE_BYTES; the
  * other errors as mmot_create and mmot_solve.  The array is shared by every
  * call on a GPU and keeps the last call's contents (the set-up initialises
  * everything a solve reads): calls that overlap on one GPU -- from several host
