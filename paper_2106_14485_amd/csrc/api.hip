@@ -920,6 +920,8 @@ mmot_status read_flags(mmot_solver* s) {
   const int f = *s->host_flags;
   if (f & FLAG_INFEASIBLE) return zero_message_status(s);
   if (f & FLAG_NONFINITE) return MMOT_ENUMERIC;
+  // (after set-up, where it means invalid data: a step launched in a form the library does not run)
+  if (f & FLAG_BADINPUT) return MMOT_EUNSUPPORTED;
   return MMOT_OK;
 }
 
