@@ -1193,6 +1193,7 @@ mmot_status mmot_query_workspace(const mmot_problem* p, const mmot_options* o, s
 
 mmot_status mmot_pool_query_workspace(const mmot_problem* p, const mmot_options* o, size_t* bytes) {
   if (!bytes || !o) return MMOT_EINVAL;
+  if (o->keep_forward) return MMOT_EUNSUPPORTED;   // (as mmot_pool_submit)
   size_t need = 0;
   const mmot_status st = mmot_query_workspace(p, o, &need);
   if (st != MMOT_OK) return st;

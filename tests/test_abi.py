@@ -56,6 +56,11 @@ def test_host_only_entry_points():
     o.keep_forward = 2
     assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_EINVAL
     o.keep_forward = 1
+    # a pool request keeps no forward messages
+    assert L.mmot_pool_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_EUNSUPPORTED
+    o.keep_forward = 0
+    assert L.mmot_pool_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_OK
+    o.keep_forward = 1
     p.eps = -1.0
     assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_EINVAL
     p.eps = 0.05
