@@ -596,9 +596,8 @@ def test_road_grid_small_log_domain():
 @pytest.mark.parametrize("L,domain", [(600, "log"), (1000, "log"), (600, "scaled")])
 def test_road_grid_rows_of_several_chunks(L, domain):
     """More commodities than one wave covers (L > 256: rows of 3 or 4 column
-    chunks in FP32, 5 or 8 in FP64) on the 5-wide ELL operator of a road grid,
-    where each step issues the loads of two chunks before processing either;
-    odd chunk counts re-read their last chunk.  FP64 to 1e-12; FP32 to 1e-5, or
+    chunks in FP32, 5 or 8 in FP64, the last one ragged) on the 5-wide ELL
+    operator of a road grid, one wave per row.  FP64 to 1e-12; FP32 to 1e-5, or
     its log-domain floor where that is larger (eps = 1 keeps the scaled domain's
     range small)."""
     log = domain == "log"
@@ -607,6 +606,23 @@ def test_road_grid_rows_of_several_chunks(L, domain):
     g64 = gpu_outputs(inst, 8, "fp64", domain)
     compare(g64, o, 1e-12, duals_tol=1e-8)
     g = gpu_outputs(inst, 8, "fp32", domain)
+    compare(g, o, max(1e-5, o["floor"]))
+
+
+@pytest.mark.parametrize("domain", ["log", "scaled"])
+def test_road_grid_full_grid_rows_of_several_chunks(domain):
+    """The road grid's full 100 x 100 states (10^4 rows: more blocks of four
+    one-row waves than the GPU holds at once, so each step runs in a full round
+    of blocks and a partial one) with rows of two column chunks in FP32 and three
+    in FP64 (L = 260, the last chunk ragged), three iterations against the oracle
+    element by element: FP64 to 1e-12, FP32 to 1e-5 or its log-domain floor
+    where that is larger (eps = 1 keeps the scaled domain's range small)."""
+    log = domain == "log"
+    inst = instances.road_grid_instance(side=100, L=260, T=4, eps=0.1 if log else 1.0, seed=11)
+    o = oracle_outputs(inst, 3, log=log)
+    g64 = gpu_outputs(inst, 3, "fp64", domain)
+    compare(g64, o, 1e-12, duals_tol=1e-8)
+    g = gpu_outputs(inst, 3, "fp32", domain)
     compare(g, o, max(1e-5, o["floor"]))
 
 
