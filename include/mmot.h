@@ -306,10 +306,10 @@ typedef struct mmot_pool mmot_pool;
  * may have admitted at once. */
 mmot_status mmot_pool_create(size_t hbm_budget, void* stream, mmot_pool** out);
 
-/* Workspace bytes of one pool request: the solver's (mmot_query_workspace)
- * plus its program area, (check_every + 1) * (2 T + 8) + 8 work items of 368
- * bytes.  Same errors as mmot_query_workspace, and EUNSUPPORTED for
- * keep_forward = 1 (as mmot_pool_submit). */
+/* Workspace bytes of one pool request: the solver's (mmot_query_workspace),
+ * 256 bytes of alignment, and its program area of (check_every + 1) * (2 T + 8)
+ * + 8 work items of 368 bytes.  Same errors as mmot_query_workspace, and
+ * EUNSUPPORTED for keep_forward = 1 (as mmot_pool_submit). */
 mmot_status mmot_pool_query_workspace(const mmot_problem* prob, const mmot_options* opt, size_t* bytes);
 
 /* Admit one request: validates and sets up a solver in ws (>= the size from

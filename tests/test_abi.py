@@ -60,6 +60,15 @@ def test_host_only_entry_points():
     assert L.mmot_pool_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_EUNSUPPORTED
     o.keep_forward = 0
     assert L.mmot_pool_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_OK
+    # the pool's size is the solver's, 256 bytes of alignment and the program area of
+    # (check_every + 1) (2 T + 8) + 8 work items of 368 bytes
+    solo = ctypes.c_size_t(0)
+    for T, every in ((50, 10), (7, 1), (120, 25)):
+        p.T, o.check_every = T, every
+        assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(solo)) == _lib.MMOT_OK
+        assert L.mmot_pool_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_OK
+        assert nb.value - solo.value == 256 + ((every + 1) * (2 * T + 8) + 8) * 368
+    p.T, o.check_every = 50, 10
     o.keep_forward = 1
     p.eps = -1.0
     assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == _lib.MMOT_EINVAL
