@@ -79,3 +79,39 @@ def test_host_only_entry_points():
     assert L.mmot_occupancy(None, None, None) == _lib.MMOT_EINVAL
     assert L.mmot_occupancy_window(None, None, None, 0, 1) == _lib.MMOT_EINVAL
     assert L.mmot_edge_flows(None, None, None) == _lib.MMOT_EINVAL
+
+
+def _valid_csr_problem():
+    from paper_2106_14485_amd import _lib
+    p = _lib.Problem()
+    p.n, p.L, p.T, p.eps, p.kind, p.nnz = 500, 40, 12, 0.05, _lib.MMOT_CSR, 4000
+    return p
+
+
+@pytest.mark.parametrize("change,expected", [
+    (dict(n=0), "EINVAL"), (dict(L=0), "EINVAL"), (dict(T=0), "EINVAL"),
+    (dict(eps=0.0), "EINVAL"), (dict(eps=float("nan")), "EINVAL"), (dict(eps=float("inf")), "EINVAL"),
+    (dict(kind=7), "EINVAL"), (dict(cost_per_step=2), "EINVAL"), (dict(cap_comm_per_step=2), "EINVAL"),
+    (dict(nnz=0), "EINVAL"), (dict(n=1 << 24, L=1 << 10), "EINVAL"),
+    (dict(precision="BF16"), "EUNSUPPORTED"), (dict(domain=3), "EINVAL"), (dict(domain=-1), "EINVAL"),
+    (dict(kind="DENSE", precision="FP64"), "EUNSUPPORTED"), (dict(kind="DENSE", domain="LOG"), "EUNSUPPORTED"),
+    (dict(kind="DENSE", n=46341), "EINVAL"),
+    (dict(), "OK"), (dict(kind="DENSE"), "OK"), (dict(kind="DENSE", precision="BF16"), "OK"),
+    (dict(precision="FP64", domain="LOG"), "OK"),
+])
+def test_problem_and_option_validation(change, expected):
+    """Each field the library validates before touching the device, one at a
+    time, through mmot_query_workspace: out-of-range sizes, eps, kinds and flags
+    are EINVAL; combinations the dense or sparse path does not run (dense FP64 or
+    log domain, sparse BF16) EUNSUPPORTED; the rest succeed."""
+    from paper_2106_14485_amd import _lib, solver
+    L = _lib.lib()
+    p, o = _valid_csr_problem(), solver.default_options()
+    consts = {"DENSE": _lib.MMOT_DENSE, "BF16": _lib.MMOT_BF16, "FP64": _lib.MMOT_FP64, "LOG": _lib.MMOT_DOMAIN_LOG}
+    for k, v in change.items():
+        v = consts.get(v, v)
+        setattr(o if k in ("precision", "domain") else p, k, v)
+    nb = ctypes.c_size_t(0)
+    assert L.mmot_query_workspace(ctypes.byref(p), ctypes.byref(o), ctypes.byref(nb)) == getattr(_lib, "MMOT_" + expected)
+    if expected == "OK":
+        assert nb.value > 0
